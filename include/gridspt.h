@@ -1,0 +1,212 @@
+/*
+ * gridspt.h -- C ABI of libgridspt, a GPU (gfx950) implementation of the
+ * GridSPT hot path of Taruya, Nishimichi & Jeong (2018), "GridSPT: grid-based
+ * calculation for perturbation theory of large-scale structure",
+ * arXiv:1807.04215.
+ *
+ * What it computes.  From a Gaussian linear density field on an N^3 periodic
+ * grid (Sec. II C, step 1), the standard-perturbation-theory fields delta_n and
+ * theta_n for n = 1..nmax <= 5 by the real-space recursion of Eq. 10 with the
+ * linear order of Eq. 11, evaluated with FFTs as in steps 2-6 of Sec. II C,
+ * and the estimators built on them: shell-averaged cross spectra (Eq. 19-21)
+ * and closed-triangle bispectra (Eq. 22-23, FFT estimator).
+ *
+ * Conventions.
+ *   - Grid: N^3 cells, box side L [Mpc/h]; x_j = j L / N, j in [0, N).
+ *   - Modes: k = (2 pi / L) n with integer n; forward transform
+ *     F(k) = N^-3 sum_x f(x) e^{-i k.x}, inverse f(x) = sum_k F(k) e^{i k.x}
+ *     (Eq. 17, three-dimensional).
+ *   - Sharp-k masks are integer: a mode is kept when |n|^2 <= n2max.  Every
+ *     mask must satisfy n2max < (N/2)^2 (the cut lies below Nyquist).
+ *   - Real fields: float32 or float64 [x][y][z], z fastest, N^3 elements.
+ *   - Spectra ("cube layout"): the masked fields have no mode with
+ *     |n_i| > Kc, Kc = grid.kc; a spectrum is stored as interleaved complex
+ *     [kz][ky][kx] with kz in [0, Kc] and ky, kx in "fftfreq" order over
+ *     2Kc + 1 values (index i <= Kc is mode +i, index i > Kc is mode i - 2Kc - 1),
+ *     (Kc + 1)(2Kc + 1)^2 complex elements.  Only kz >= 0 is stored; the
+ *     rest follows from F(-k) = F(k)^*.
+ *   - Units: L in Mpc/h, k in h/Mpc, P in (Mpc/h)^3, B in (Mpc/h)^6;
+ *     fields are dimensionless, u in Mpc/h.
+ *   - D-form sources: the recursion uses div u = theta and u = grad phi to
+ *     write the sources of Eq. 10 as S_delta = div(sum_m delta_m u_{n-m}) and
+ *     S_theta = (1/2) lap(sum_m u_m . u_{n-m}); identical to the printed form
+ *     whenever products do not alias (the 2/3 rule of Sec. II C).
+ *
+ * Memory.  Every pointer is a caller-owned device pointer unless marked
+ * "host".  The library allocates no device memory: scratch comes in `work`
+ * (device, 256-byte aligned) of at least the size the matching
+ * *_workspace_bytes call returns.  Device pointers must be 256-byte aligned.
+ * Calls are asynchronous on the stream given to gridspt_create; results are
+ * ready when that stream has reached them (gridspt_sync waits).
+ *
+ * Errors.  Every entry point validates its arguments on the host before any
+ * work is enqueued and returns a negative gridspt_status on failure, in which
+ * case nothing has been written.  No exception crosses this interface.
+ * A context is not thread-safe; use one per host thread and stream.
+ */
+#ifndef GRIDSPT_H
+#define GRIDSPT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GRIDSPT_OK = 0,
+    GRIDSPT_EINVAL = -1,       /* an argument is out of range or inconsistent */
+    GRIDSPT_EUNSUPPORTED = -2, /* valid, but not built: N not a power of two in [16, 1024], ... */
+    GRIDSPT_EWORKSPACE = -3,   /* work is null or smaller than required */
+    GRIDSPT_EALIGN = -4,       /* a device pointer is null or not 256-byte aligned */
+    GRIDSPT_EHIP = -5          /* the HIP runtime reported an error */
+} gridspt_status;
+
+typedef enum { GRIDSPT_F32 = 0, GRIDSPT_F64 = 1 } gridspt_dtype;
+
+typedef struct {
+    int32_t n;     /* cells per side N: a power of two, 16 <= N <= 1024 */
+    int32_t dtype; /* gridspt_dtype of every real field and spectrum */
+    double box;    /* side L > 0 [Mpc/h] */
+    int32_t kc;    /* half-width of the spectral cube, 1 <= kc < N/2; every mask
+                      used with this grid needs floor(sqrt(n2max)) <= kc */
+    int32_t reserved;
+} gridspt_grid;
+
+/* Linear power spectrum P0(k) = amp k^ns T_BBKS(k / gamma)^2 (k in h/Mpc,
+ * Bardeen et al. 1986 transfer function), the growth factor multiplying the
+ * field, the mask W1 and the seed of the white noise (Sec. II C, step 1). */
+typedef struct {
+    double amp;      /* A [(Mpc/h)^(3 + ns)] */
+    double ns;       /* spectral index */
+    double gamma;    /* shape parameter Gamma [h/Mpc] */
+    double growth;   /* D, multiplies delta_1 */
+    int64_t n2max;   /* W1: keep 0 < |n|^2 <= n2max */
+    uint64_t seed;   /* Philox4x64-10 key word 0 */
+    uint64_t stream; /* Philox counter word 1: realisation index */
+} gridspt_linpk;
+
+typedef struct gridspt_ctx gridspt_ctx;
+
+/* Create a context bound to a HIP stream (hipStream_t passed as void*, NULL
+ * for the null stream).  Needs no GPU; the device is the one current at the
+ * first enqueue. */
+int gridspt_create(gridspt_ctx** out, void* hip_stream);
+void gridspt_destroy(gridspt_ctx* ctx);
+/* Waits for the context's stream; GRIDSPT_EHIP if an asynchronous error occurred. */
+int gridspt_sync(gridspt_ctx* ctx);
+const char* gridspt_status_string(int status);
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t gridspt_version(void);
+
+/* ---- host helpers (exact integer arithmetic where ties are possible) ---- */
+
+/* Mask threshold for a cut: kcut <= 0 selects the strict 2/3 rule of Sec. II C
+ * (keep |n| < N/3: n2max = ceil(N^2 / 9) - 1); otherwise the absolute cut
+ * |k| <= kcut: n2max = floor((kcut L / 2 pi)^2).  Returns < 0 on bad input. */
+int64_t gridspt_cut_n2max(int32_t n, double box, double kcut);
+/* floor(sqrt(n2max)), the cube half-width a mask needs; < 0 on bad input. */
+int32_t gridspt_cube_kc(int64_t n2max);
+/* Complex elements of one spectrum in the cube layout of `g`. */
+int64_t gridspt_cube_elems(const gridspt_grid* g);
+/* Linear bins on [0, k_max], k_max = (kmax_num / kmax_den) k_F, left-closed, the
+ * last bin closed at min(k_max, cut): edge_n2[0] = 1 (k = 0 excluded),
+ * edge_n2[b] = ceil((b k_max / nbins / k_F)^2), edge_n2[nbins] =
+ * min(floor((k_max / k_F)^2) + 1, n2max + 1).  Bin b holds
+ * edge_n2[b] <= |n|^2 < edge_n2[b+1].  edge_n2 is host memory of nbins + 1. */
+int gridspt_linear_edges(int32_t nbins, int64_t kmax_num, int64_t kmax_den, int64_t n2max, int64_t* edge_n2);
+/* Amplitude A giving sigma(R = 8 Mpc/h) = sigma8 for the uncut P0 (top-hat). */
+int gridspt_sigma8_amp(double sigma8, double ns, double gamma, double* amp);
+/* Linear growth D(z) / D(0) for matter and vacuum densities om, ol. */
+int gridspt_growth(double om, double ol, double z, double* d);
+
+/* ---- hot path ---- */
+
+/* Device scratch needed by gridspt_linear_field, gridspt_forward and
+ * gridspt_orders(nmax) on grid g. */
+int64_t gridspt_workspace_bytes(const gridspt_grid* g, int32_t nmax);
+
+/* Step (1) of Sec. II C.  delta1(x) = inverse transform of
+ * W1(k) sqrt(P0(k) N^3 / L^3) D w(k), where w(k) is the forward transform of
+ * unit white noise w(x) drawn per cell c = (x N + y) N + z from
+ * Philox4x64-10(counter = (c, stream, 0, 0), key = (seed, 0)) and Box-Muller
+ * (first two words as 53-bit uniforms in (0,1), cosine branch), so that
+ * L^3 <|delta1(k)|^2> = D^2 P0(k) on kept modes and delta1(k=0) = 0.
+ * delta1: N^3 real out.  delta1_k: cube-layout spectrum out, or NULL. */
+int gridspt_linear_field(gridspt_ctx* ctx, const gridspt_grid* g, const gridspt_linpk* lp, void* delta1,
+                         void* delta1_k, void* work, int64_t work_bytes);
+
+/* Masked forward transform of any real field into the cube layout:
+ * field_k(k) = [0 < |n|^2 <= n2max] N^-3 sum_x field(x) e^{-ik.x}. */
+int gridspt_forward(gridspt_ctx* ctx, const gridspt_grid* g, int64_t n2max, const void* field, void* field_k,
+                    void* work, int64_t work_bytes);
+
+/* The recursion of Eq. 10 (n >= 2) and Eq. 11 (n = 1) up to nmax in [1, 5].
+ * delta1: N^3 real input (any field; the mask W1 = n2max1 and the removal of
+ *   k = 0 are applied here).  It may alias delta[0].
+ * delta, theta: host arrays of nmax device pointers to N^3 real outputs;
+ *   delta[0] receives the masked delta_1, theta[0] (may be NULL or alias
+ *   delta[0]) the same field (theta_1 = delta_1).
+ * delta_k, theta_k: NULL, or host arrays of nmax device pointers (entries may
+ *   be NULL) receiving the cube-layout spectra of delta_n and theta_n.
+ * Orders n >= 2 are masked with W2 (n2max2); both masks need
+ * floor(sqrt(n2max)) <= g->kc. */
+int gridspt_orders(gridspt_ctx* ctx, const gridspt_grid* g, int32_t nmax, int64_t n2max1, int64_t n2max2,
+                   const void* delta1, void* const* delta, void* const* theta, void* const* delta_k,
+                   void* const* theta_k, void* work, int64_t work_bytes);
+
+/* Final sum of orders (the truncated series of Eq. 8):
+ * out(x) = sum_{n=1..nmax} coef[n-1] delta_n(x), accumulated in FP64.
+ * delta: host array of nmax device pointers; coef: host array of nmax;
+ * out: N^3 float64, device.  nmax <= 8. */
+int gridspt_sum_orders(gridspt_ctx* ctx, const gridspt_grid* g, int32_t nmax, const void* const* delta,
+                       const double* coef, double* out);
+
+/* Device scratch needed by gridspt_power. */
+int64_t gridspt_power_workspace_bytes(const gridspt_grid* g, int32_t npairs, int32_t nbins);
+
+/* Shell-averaged cross spectra, the estimators of Eq. 19-21 with the volume
+ * factor: P_ab(bin) = L^3 sum_k w Re[F_a(k) F_b(k)^*] / sum_k w over stored
+ * (kz >= 0) modes of the bin, w = 1 on kz = 0 and 2 elsewhere (so N_k counts
+ * k and -k).  fields_k: host array of nfields (<= 16) device cube spectra.
+ * pairs: host, 2 * npairs field indices (npairs <= 64).  edge_n2: host,
+ * nbins + 1 non-decreasing integers, edge_n2[0] >= 1, nbins <= 256.
+ * pk: device [npairs][nbins]; kmean, nmodes: device [nbins] or NULL.
+ * Empty bins report 0.  Sums are FP64 in a fixed order. */
+int gridspt_power(gridspt_ctx* ctx, const gridspt_grid* g, int32_t nfields, const void* const* fields_k,
+                  int32_t npairs, const int32_t* pairs, int32_t nbins, const int64_t* edge_n2, double* pk,
+                  double* kmean, double* nmodes, void* work, int64_t work_bytes);
+
+/* Device scratch needed by gridspt_bispectrum for these triangles and terms. */
+int64_t gridspt_bispectrum_workspace_bytes(const gridspt_grid* g, int32_t ntri, const int32_t* tri_bins,
+                                           int32_t nterms, const int32_t* terms);
+
+/* Closed-triangle bispectra of Eq. 22-23 by the FFT estimator:
+ * I_a^b(x) = inverse transform of F_a restricted to shell b, J^b the same for
+ * the indicator of shell b; for term (fa, fb, fc, tri) with shells (b1, b2, b3)
+ *   T = N^-3 sum_x I_fa^b1 I_fb^b2 I_fc^b3,  ntriangles = N^-3 sum_x J^b1 J^b2 J^b3,
+ *   bk = L^6 T / ntriangles.
+ * T counts triangles that close modulo N, which equals exact closure
+ * (k1 + k2 + k3 = 0) when every shell lies below N/3.
+ * tri_bins: host 3 * ntri bin indices; terms: host 4 * nterms (fa, fb, fc, tri);
+ * edge_n2 as for gridspt_power.  bk: device [nterms]; ntriangles: device
+ * [ntri].  Sums are FP64 in a fixed order. */
+int gridspt_bispectrum(gridspt_ctx* ctx, const gridspt_grid* g, int32_t nfields, const void* const* fields_k,
+                       int32_t ntri, const int32_t* tri_bins, int32_t nterms, const int32_t* terms, int32_t nbins,
+                       const int64_t* edge_n2, double* bk, double* ntriangles, void* work, int64_t work_bytes);
+
+/* ---- kernel timing ----
+ * With profiling on, every kernel the context enqueues is bracketed by HIP
+ * events on its stream.  gridspt_profile_read waits for the stream, then
+ * reports per kernel kind (up to max entries): name (host, 32 bytes each,
+ * NUL-terminated), launches, total milliseconds and the algorithmic bytes the
+ * launches move (inputs read once, outputs written once, in the layouts
+ * above).  Returns the number of kinds reported; reading resets the record. */
+int gridspt_set_profiling(gridspt_ctx* ctx, int32_t enable);
+int gridspt_profile_read(gridspt_ctx* ctx, int32_t max, char* names, int64_t* launches, double* ms, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRIDSPT_H */

@@ -1,0 +1,346 @@
+"""GridSPT on MI355X: Python binding of libgridspt (include/gridspt.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``csrc/``.  PyTorch provides device memory and the stream.  The
+binding raises if the library is missing; there is no CPU fallback.
+
+Layouts (see include/gridspt.h): real fields are ``[N, N, N]`` tensors
+indexed ``[x, y, z]``; spectra are cube-layout complex tensors of shape
+``[Kc + 1, 2Kc + 1, 2Kc + 1]`` indexed ``[kz, ky, kx]`` with the two last axes
+in fftfreq order, stored as real tensors with a trailing axis of 2.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgridspt.so")
+
+F32, F64 = 0, 1
+_STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported configuration", -3: "workspace too small",
+           -4: "null or misaligned device pointer", -5: "HIP runtime error"}
+
+
+class GridSPTError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__("%s: %s (status %d)" % (where, _STATUS.get(status, "unknown"), status))
+        self.status = status
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("dtype", ctypes.c_int32), ("box", ctypes.c_double),
+                ("kc", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _LinPk(ctypes.Structure):
+    _fields_ = [("amp", ctypes.c_double), ("ns", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("growth", ctypes.c_double), ("n2max", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("stream", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libgridspt.so is not built (run __graft_entry__.build() or "
+                              "python paper_1807_04215_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        gp = ctypes.POINTER(_Grid)
+        sig = {
+            "gridspt_create": ([ctypes.POINTER(vp), vp], ctypes.c_int),
+            "gridspt_destroy": ([vp], None),
+            "gridspt_sync": ([vp], ctypes.c_int),
+            "gridspt_status_string": ([ctypes.c_int], ctypes.c_char_p),
+            "gridspt_version": ([], i32),
+            "gridspt_cut_n2max": ([i32, dbl, dbl], i64),
+            "gridspt_cube_kc": ([i64], i32),
+            "gridspt_cube_elems": ([gp], i64),
+            "gridspt_linear_edges": ([i32, i64, i64, i64, vp], ctypes.c_int),
+            "gridspt_sigma8_amp": ([dbl, dbl, dbl, ctypes.POINTER(dbl)], ctypes.c_int),
+            "gridspt_growth": ([dbl, dbl, dbl, ctypes.POINTER(dbl)], ctypes.c_int),
+            "gridspt_workspace_bytes": ([gp, i32], i64),
+            "gridspt_linear_field": ([vp, gp, ctypes.POINTER(_LinPk), vp, vp, vp, i64], ctypes.c_int),
+            "gridspt_forward": ([vp, gp, i64, vp, vp, vp, i64], ctypes.c_int),
+            "gridspt_orders": ([vp, gp, i32, i64, i64, vp, vp, vp, vp, vp, vp, i64], ctypes.c_int),
+            "gridspt_sum_orders": ([vp, gp, i32, vp, vp, vp], ctypes.c_int),
+            "gridspt_power_workspace_bytes": ([gp, i32, i32], i64),
+            "gridspt_power": ([vp, gp, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp, i64], ctypes.c_int),
+            "gridspt_bispectrum_workspace_bytes": ([gp, i32, vp, i32, vp], i64),
+            "gridspt_bispectrum": ([vp, gp, i32, vp, i32, vp, i32, vp, i32, vp, vp, vp, vp, i64], ctypes.c_int),
+            "gridspt_set_profiling": ([vp, i32], ctypes.c_int),
+            "gridspt_profile_read": ([vp, i32, vp, vp, vp, vp], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str) -> int:
+    if rc < 0:
+        raise GridSPTError(rc, where)
+    return rc
+
+
+# --------------------------------------------------------------------------
+# host helpers
+# --------------------------------------------------------------------------
+
+def cut_n2max(n: int, box: float, kcut: float = 0.0) -> int:
+    """Mask threshold: kcut <= 0 is the strict 2/3 rule, else |k| <= kcut."""
+    return _check(lib().gridspt_cut_n2max(n, box, kcut), "cut_n2max")
+
+
+def cube_kc(n2max: int) -> int:
+    return _check(lib().gridspt_cube_kc(n2max), "cube_kc")
+
+
+def linear_edges(nbins: int, kmax_num: int, kmax_den: int, n2max: int):
+    import numpy as np
+    e = np.zeros(nbins + 1, dtype=np.int64)
+    _check(lib().gridspt_linear_edges(nbins, kmax_num, kmax_den, n2max, e.ctypes.data), "linear_edges")
+    return e
+
+
+def sigma8_amp(sigma8: float, ns: float, gamma: float) -> float:
+    out = ctypes.c_double()
+    _check(lib().gridspt_sigma8_amp(sigma8, ns, gamma, ctypes.byref(out)), "sigma8_amp")
+    return out.value
+
+
+def growth(om: float, ol: float, z: float) -> float:
+    out = ctypes.c_double()
+    _check(lib().gridspt_growth(om, ol, z, ctypes.byref(out)), "growth")
+    return out.value
+
+
+# --------------------------------------------------------------------------
+# grid, context, workspace
+# --------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class Grid:
+    n: int
+    box: float
+    kc: int
+    dtype: int = F32
+
+    @property
+    def cstruct(self) -> _Grid:
+        return _Grid(self.n, self.dtype, float(self.box), self.kc, 0)
+
+    @property
+    def real_dtype(self):
+        return torch.float64 if self.dtype == F64 else torch.float32
+
+    @property
+    def cube_shape(self):
+        return (self.kc + 1, 2 * self.kc + 1, 2 * self.kc + 1, 2)
+
+
+@dataclass
+class LinearSpectrum:
+    amp: float
+    ns: float = 0.96
+    gamma: float = 0.21
+    growth: float = 1.0
+    n2max: int = 0
+    seed: int = 1
+    stream: int = 0
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptr_array(ts: Sequence[Optional[torch.Tensor]]):
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = t.data_ptr() if t is not None else None
+    return arr
+
+
+class Context:
+    """A libgridspt context bound to a torch stream (default: current stream)."""
+
+    def __init__(self, stream: Optional[torch.cuda.Stream] = None):
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        h = ctypes.c_void_p()
+        _check(lib().gridspt_create(ctypes.byref(h), ctypes.c_void_p(s.cuda_stream)), "create")
+        self._h = h
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.gridspt_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def sync(self):
+        _check(lib().gridspt_sync(self._h), "sync")
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        """A device scratch buffer of at least nbytes, reused across calls."""
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    # ---- profiling ----
+    def set_profiling(self, enable: bool):
+        _check(lib().gridspt_set_profiling(self._h, 1 if enable else 0), "set_profiling")
+
+    def profile_read(self):
+        import numpy as np
+        m = 32
+        names = ctypes.create_string_buffer(32 * m)
+        launches = np.zeros(m, dtype=np.int64)
+        ms = np.zeros(m)
+        by = np.zeros(m)
+        k = _check(lib().gridspt_profile_read(self._h, m, names, launches.ctypes.data, ms.ctypes.data,
+                                              by.ctypes.data), "profile_read")
+        out = {}
+        for i in range(k):
+            nm = names.raw[32 * i: 32 * (i + 1)].split(b"\0", 1)[0].decode()
+            out[nm] = {"launches": int(launches[i]), "ms": float(ms[i]), "bytes": float(by[i])}
+        return out
+
+
+def workspace_bytes(grid: Grid, nmax: int) -> int:
+    g = grid.cstruct
+    return _check(lib().gridspt_workspace_bytes(ctypes.byref(g), nmax), "workspace_bytes")
+
+
+def _new_real(grid: Grid) -> torch.Tensor:
+    return torch.empty((grid.n,) * 3, dtype=grid.real_dtype, device="cuda")
+
+
+def _new_cube(grid: Grid) -> torch.Tensor:
+    return torch.empty(grid.cube_shape, dtype=grid.real_dtype, device="cuda")
+
+
+# --------------------------------------------------------------------------
+# hot path
+# --------------------------------------------------------------------------
+
+def linear_field(ctx: Context, grid: Grid, lp: LinearSpectrum, out: Optional[torch.Tensor] = None,
+                 out_k: Optional[torch.Tensor] = None, spectrum: bool = False):
+    """Seeded Gaussian delta_1 (step 1 of Sec. II C).  Returns delta1 or (delta1, delta1_k)."""
+    out = out if out is not None else _new_real(grid)
+    if spectrum and out_k is None:
+        out_k = _new_cube(grid)
+    g = grid.cstruct
+    c = _LinPk(lp.amp, lp.ns, lp.gamma, lp.growth, lp.n2max, lp.seed, lp.stream)
+    nb = workspace_bytes(grid, 1)
+    ws = ctx.workspace(nb)
+    _check(lib().gridspt_linear_field(ctx.handle, ctypes.byref(g), ctypes.byref(c), _ptr(out), _ptr(out_k),
+                                      _ptr(ws), ws.numel()), "linear_field")
+    return (out, out_k) if (spectrum or out_k is not None) else out
+
+
+def forward(ctx: Context, grid: Grid, n2max: int, field: torch.Tensor, out_k: Optional[torch.Tensor] = None):
+    """Masked forward transform of a real field into the cube layout."""
+    out_k = out_k if out_k is not None else _new_cube(grid)
+    g = grid.cstruct
+    ws = ctx.workspace(workspace_bytes(grid, 1))
+    _check(lib().gridspt_forward(ctx.handle, ctypes.byref(g), n2max, _ptr(field), _ptr(out_k), _ptr(ws),
+                                 ws.numel()), "forward")
+    return out_k
+
+
+class Orders:
+    """Outputs of gridspt_orders: lists delta, theta (real) and delta_k, theta_k (cube or None)."""
+
+    def __init__(self, delta, theta, delta_k, theta_k):
+        self.delta, self.theta, self.delta_k, self.theta_k = delta, theta, delta_k, theta_k
+
+
+def alloc_orders(grid: Grid, nmax: int, spectra: bool = True) -> Orders:
+    delta = [_new_real(grid) for _ in range(nmax)]
+    theta = [delta[0]] + [_new_real(grid) for _ in range(nmax - 1)]
+    dk = [_new_cube(grid) for _ in range(nmax)] if spectra else None
+    tk = ([dk[0]] + [_new_cube(grid) for _ in range(nmax - 1)]) if spectra else None
+    return Orders(delta, theta, dk, tk)
+
+
+def orders(ctx: Context, grid: Grid, nmax: int, n2max1: int, n2max2: int, delta1: torch.Tensor,
+           out: Optional[Orders] = None, spectra: bool = True) -> Orders:
+    """Recursion of Eq. 10/11 up to nmax (delta_1 input is masked with W1 here)."""
+    out = out if out is not None else alloc_orders(grid, nmax, spectra)
+    g = grid.cstruct
+    ws = ctx.workspace(workspace_bytes(grid, nmax))
+    d = _ptr_array(out.delta)
+    t = _ptr_array(out.theta)
+    dk = _ptr_array(out.delta_k) if out.delta_k is not None else None
+    tk = _ptr_array(out.theta_k) if out.theta_k is not None else None
+    _check(lib().gridspt_orders(ctx.handle, ctypes.byref(g), nmax, n2max1, n2max2, _ptr(delta1), d, t, dk, tk,
+                                _ptr(ws), ws.numel()), "orders")
+    return out
+
+
+def sum_orders(ctx: Context, grid: Grid, delta: Sequence[torch.Tensor], coef: Sequence[float],
+               out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """FP64 sum_n coef[n] delta_n(x) (the truncated series of Eq. 8)."""
+    import numpy as np
+    out = out if out is not None else torch.empty((grid.n,) * 3, dtype=torch.float64, device="cuda")
+    c = np.ascontiguousarray(np.asarray(coef, dtype=np.float64))
+    g = grid.cstruct
+    _check(lib().gridspt_sum_orders(ctx.handle, ctypes.byref(g), len(delta), _ptr_array(delta), c.ctypes.data,
+                                    _ptr(out)), "sum_orders")
+    return out
+
+
+def power(ctx: Context, grid: Grid, fields_k: Sequence[torch.Tensor], pairs, edges):
+    """Shell-averaged cross spectra; returns (pk [npairs, nbins], kmean, nmodes) as float64 tensors."""
+    import numpy as np
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1))
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64))
+    npairs, nb = pr.size // 2, e.size - 1
+    pk = torch.empty((npairs, nb), dtype=torch.float64, device="cuda")
+    km = torch.empty(nb, dtype=torch.float64, device="cuda")
+    nm = torch.empty(nb, dtype=torch.float64, device="cuda")
+    g = grid.cstruct
+    need = _check(lib().gridspt_power_workspace_bytes(ctypes.byref(g), npairs, nb), "power_workspace_bytes")
+    ws = ctx.workspace(need)
+    _check(lib().gridspt_power(ctx.handle, ctypes.byref(g), len(fields_k), _ptr_array(fields_k), npairs,
+                               pr.ctypes.data, nb, e.ctypes.data, _ptr(pk), _ptr(km), _ptr(nm), _ptr(ws),
+                               ws.numel()), "power")
+    return pk, km, nm
+
+
+def bispectrum(ctx: Context, grid: Grid, fields_k: Sequence[torch.Tensor], tris, terms, edges):
+    """FFT-estimator bispectra; returns (bk [nterms], ntriangles [ntri]) as float64 tensors."""
+    import numpy as np
+    tb = np.ascontiguousarray(np.asarray(tris, dtype=np.int32).reshape(-1))
+    tt = np.ascontiguousarray(np.asarray(terms, dtype=np.int32).reshape(-1))
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64))
+    ntri, nterms, nb = tb.size // 3, tt.size // 4, e.size - 1
+    bk = torch.empty(nterms, dtype=torch.float64, device="cuda")
+    nt = torch.empty(ntri, dtype=torch.float64, device="cuda")
+    g = grid.cstruct
+    need = _check(lib().gridspt_bispectrum_workspace_bytes(ctypes.byref(g), ntri, tb.ctypes.data, nterms,
+                                                           tt.ctypes.data), "bispectrum_workspace_bytes")
+    ws = ctx.workspace(need)
+    _check(lib().gridspt_bispectrum(ctx.handle, ctypes.byref(g), len(fields_k), _ptr_array(fields_k), ntri,
+                                    tb.ctypes.data, nterms, tt.ctypes.data, nb, e.ctypes.data, _ptr(bk), _ptr(nt),
+                                    _ptr(ws), ws.numel()), "bispectrum")
+    return bk, nt

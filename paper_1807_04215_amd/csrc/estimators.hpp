@@ -1,0 +1,228 @@
+// Estimator kernels: shell-binned cross spectra (Eq. 19-21), the FFT
+// bispectrum estimator's triple-product sums (Eq. 22-23), the weighted sum of
+// orders, and the twiddle table.  All sums accumulate in FP64 in a fixed order
+// (no floating-point atomics), so results are bitwise reproducible.
+#pragma once
+#include "fft_engine.hpp"
+
+namespace gridspt {
+
+constexpr int kMaxBins = 256;
+constexpr int kMaxFields = 16;
+constexpr int kMaxPairs = 64;
+
+// tw[m] = exp(-2 pi i m / N), evaluated in FP64 and rounded once.
+template <typename T>
+__global__ void k_twiddles(cpx<T>* tw, int n) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < n) {
+        double s, c;
+        sincospi(2.0 * (double)m / (double)n, &s, &c);
+        tw[m] = {(T)c, (T)(-s)};
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Cross spectra.  Each wavefront walks whole cube rows (kz, ky') and, for each
+// group of 64 consecutive kx', sums w Re[F_a F_b^*] per bin with a fixed-order
+// wavefront reduction for every distinct bin in the group, into its own LDS
+// accumulator.  Quantities per bin: npairs pair sums, then sum w, sum w |k|.
+// Block partials [block][bin][q] are summed over blocks in block order.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct PowerArgs {
+    const cpx<T>* f[kMaxFields];
+    int pa[kMaxPairs], pb[kMaxPairs];
+    int64_t edges[kMaxBins + 1];
+    int npairs, nbins;
+    double kF;
+    double* partial;  // [gridDim.x][nbins][npairs + 2]
+};
+
+constexpr int kPowerWaves = 4;
+
+template <typename T>
+__global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T> a, CubeDims cd) {
+    extern __shared__ double acc[];  // [kPowerWaves][nbins][Q]
+    __shared__ int64_t edges[kMaxBins + 1];
+    const int Q = a.npairs + 2;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int i = threadIdx.x; i <= a.nbins; i += blockDim.x) edges[i] = a.edges[i];
+    for (int i = threadIdx.x; i < kPowerWaves * a.nbins * Q; i += blockDim.x) acc[i] = 0.0;
+    __syncthreads();
+    double* my = acc + (size_t)wave * a.nbins * Q;
+    const int Kx = cd.Ky;
+    const long nrows = (long)cd.Kz * cd.Ky;
+    const long gw = (long)blockIdx.x * kPowerWaves + wave, nw = (long)gridDim.x * kPowerWaves;
+    for (long rowi = gw; rowi < nrows; rowi += nw) {
+        const int kz = (int)(rowi / cd.Ky), kyc = (int)(rowi % cd.Ky);
+        const int ky = kyc <= cd.Kc ? kyc : kyc - cd.Ky;
+        const double w = kz == 0 ? 1.0 : 2.0;
+        const size_t base = (size_t)rowi * Kx;
+        for (int c0 = 0; c0 < Kx; c0 += 64) {
+            const int kxc = c0 + lane;
+            int bin = -1;
+            int64_t n2 = 0;
+            if (kxc < Kx) {
+                const int kx = kxc <= cd.Kc ? kxc : kxc - Kx;
+                n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
+                if (n2 >= edges[0] && n2 < edges[a.nbins]) {
+                    int lo = 0, hi = a.nbins;  // edges[lo] <= n2 < edges[hi]
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (n2 >= edges[mid]) lo = mid;
+                        else hi = mid;
+                    }
+                    bin = lo;
+                }
+            }
+            uint64_t pending = __ballot(bin >= 0);
+            while (pending) {
+                const int leader = __ffsll((unsigned long long)pending) - 1;
+                const int b = __shfl(bin, leader, 64);
+                const bool mine = bin == b;
+                for (int q = 0; q < Q; ++q) {
+                    double v = 0.0;
+                    if (mine) {
+                        if (q < a.npairs) {
+                            const cpx<T> x = a.f[a.pa[q]][base + kxc], y = a.f[a.pb[q]][base + kxc];
+                            v = w * ((double)x.x * (double)y.x + (double)x.y * (double)y.y);
+                        } else if (q == a.npairs) {
+                            v = w;
+                        } else {
+                            v = w * a.kF * sqrt((double)n2);
+                        }
+                    }
+                    v = wave_sum(v);
+                    if (lane == 0) my[b * Q + q] += v;
+                }
+                pending &= ~__ballot(mine);
+            }
+        }
+    }
+    __syncthreads();
+    double* out = a.partial + (size_t)blockIdx.x * a.nbins * Q;
+    for (int i = threadIdx.x; i < a.nbins * Q; i += blockDim.x) {
+        double s = 0.0;
+        for (int wv = 0; wv < kPowerWaves; ++wv) s += acc[(size_t)wv * a.nbins * Q + i];
+        out[i] = s;
+    }
+}
+
+// Sum block partials in block order; then P = L^3 S / sum w, kmean, nmodes.
+__global__ void k_power_final(const double* partial, int nblocks, int nbins, int npairs, double vol, double* pk,
+                              double* kmean, double* nmodes) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbins) return;
+    const int Q = npairs + 2;
+    double cnt = 0.0, ks = 0.0;
+    for (int i = 0; i < nblocks; ++i) {
+        cnt += partial[((size_t)i * nbins + b) * Q + npairs];
+        ks += partial[((size_t)i * nbins + b) * Q + npairs + 1];
+    }
+    if (nmodes) nmodes[b] = cnt;
+    if (kmean) kmean[b] = cnt > 0.0 ? ks / cnt : 0.0;
+    for (int p = 0; p < npairs; ++p) {
+        double s = 0.0;
+        for (int i = 0; i < nblocks; ++i) s += partial[((size_t)i * nbins + b) * Q + p];
+        pk[(size_t)p * nbins + b] = cnt > 0.0 ? vol * s / cnt : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Triple products sum_x I_a(x) I_b(x) I_c(x) for up to 8 terms per launch,
+// FP64 per thread, fixed-order block tree, partials [block][term].
+// ---------------------------------------------------------------------------
+template <typename T>
+struct TripleArgs {
+    const T* a[8];
+    const T* b[8];
+    const T* c[8];
+    int nterms;
+    size_t ncell;
+    double* partial;  // [gridDim.x][8]
+};
+
+constexpr int kTripleThreads = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kTripleThreads) void k_triple_partial(TripleArgs<T> t) {
+    __shared__ double red[kTripleThreads];
+    double s[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] = 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < t.ncell; i += stride) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (u < t.nterms) s[u] += (double)t.a[u][i] * (double)t.b[u][i] * (double)t.c[u][i];
+    }
+    for (int u = 0; u < t.nterms; ++u) {
+        red[threadIdx.x] = s[u];
+        __syncthreads();
+        for (int h = kTripleThreads / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) t.partial[(size_t)blockIdx.x * 8 + u] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ void k_triple_final(const double* partial, int nblocks, int nterms, double* out) {
+    const int u = threadIdx.x;
+    if (u >= nterms) return;
+    double s = 0.0;
+    for (int i = 0; i < nblocks; ++i) s += partial[(size_t)i * 8 + u];
+    out[u] = s;
+}
+
+// bk = L^6 T / J for terms u0 .. u0+nu-1 (both sums over x of the same grid, so
+// the N^-3 cancels); ntriangles = N^-3 J for triangles u0 .. u0+nt-1.
+struct TriMap {
+    int tri[64];
+};
+__global__ void k_bisp_final(const double* tsum, const double* jsum, TriMap m, int u0, int nu, int nt,
+                             double vol2, double invN3, double* bk, double* ntriangles) {
+    const int i = threadIdx.x;
+    if (i < nu) {
+        const double j = jsum[m.tri[i]];
+        bk[u0 + i] = j != 0.0 ? vol2 * tsum[u0 + i] / j : 0.0;
+    }
+    if (i < nt) ntriangles[u0 + i] = jsum[u0 + i] * invN3;
+}
+
+// out(x) = sum_n coef_n delta_n(x) in FP64
+template <typename T>
+struct SumArgs {
+    const T* d[8];
+    double coef[8];
+    int nmax;
+    size_t ncell;
+    double* out;
+};
+
+template <typename T>
+__global__ void k_sum_orders(SumArgs<T> s) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < s.ncell; i += stride) {
+        double v = 0.0;
+        for (int n = 0; n < s.nmax; ++n) v += s.coef[n] * (double)s.d[n][i];
+        s.out[i] = v;
+    }
+}
+
+// copy a real field (theta_1 = delta_1)
+template <typename T>
+__global__ void k_copy(const T* __restrict__ src, T* __restrict__ dst, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+}  // namespace gridspt

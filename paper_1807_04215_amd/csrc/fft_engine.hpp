@@ -1,0 +1,214 @@
+// Row FFT engine for gfx950: one row of N complex points is held by a team of
+// P = N/16 lanes of one 64-wide wavefront, 16 points per lane, and transformed
+// by Stockham autosort passes (first radix 16 in registers, later passes
+// exchanging through a per-row LDS buffer).  Rows of N <= 1024 fit in one
+// wavefront, so the exchanges only need wavefront-scope synchronisation.
+//
+// Register layout ("canonical"): lane l of the team, register e holds point
+// l + P*e of the row, both before and after a transform.  This is also the
+// order in which a team reads a contiguous row from HBM (consecutive lanes,
+// consecutive addresses), so loads feed the first radix-16 pass directly.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <utility>
+
+namespace gridspt {
+
+// Spectral cube extents: Kc half-width, Kz = Kc + 1, Ky = Kx = 2Kc + 1.
+struct CubeDims {
+    int Kc, Kz, Ky;
+};
+
+template <typename T>
+struct cpx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cscale(cpx<T> a, T s) { return {a.x * s, a.y * s}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cconj(cpx<T> a) { return {a.x, -a.y}; }
+// multiply by +i
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul_i(cpx<T> a) { return {-a.y, a.x}; }
+
+// Compile-time loop.
+template <typename F, int... Ks>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Ks...>) {
+    (f(std::integral_constant<int, Ks>{}), ...);
+}
+template <int Count, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, Count>{});
+}
+
+// cos and sin of 2 pi m / 16, m = 0..15 (exact values of the eighth-circle
+// constants cos(pi/8), cos(pi/4), cos(3pi/8)).
+__device__ constexpr double kCos16[16] = {
+    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+
+// a * exp(DIR * 2 pi i K / R) for a compile-time root of unity of order R | 16,
+// with the trivial multiples of pi/2 done by swaps and sign flips.
+template <int R, int K, int DIR, typename T>
+__device__ __forceinline__ cpx<T> twiddle_const(cpx<T> a) {
+    constexpr int k = ((K % R) + R) % R;
+    constexpr int m = k * (16 / R);  // position on the 16-point circle
+    if constexpr (m == 0) {
+        return a;
+    } else if constexpr (m == 8) {
+        return {-a.x, -a.y};
+    } else if constexpr (m == 4) {  // exp(DIR i pi/2) = DIR i
+        if constexpr (DIR > 0) return {-a.y, a.x};
+        else return {a.y, -a.x};
+    } else if constexpr (m == 12) {  // exp(DIR i 3pi/2) = -DIR i
+        if constexpr (DIR > 0) return {a.y, -a.x};
+        else return {-a.y, a.x};
+    } else {
+        constexpr double c = kCos16[m];
+        constexpr double s = (DIR > 0 ? 1.0 : -1.0) * kCos16[(m + 12) % 16];  // sin = cos(. - pi/2)
+        const T cc = (T)c, ss = (T)s;
+        return {a.x * cc - a.y * ss, a.x * ss + a.y * cc};
+    }
+}
+
+// In-place DFT of R points in natural order: X[k] = sum_j x[j] exp(DIR 2 pi i jk/R).
+// Radix-2 decimation in time, all twiddles compile-time constants.
+template <int R, int DIR, typename T>
+struct Dft {
+    static __device__ __forceinline__ void run(cpx<T>* x) {
+        cpx<T> ev[R / 2], od[R / 2];
+#pragma unroll
+        for (int i = 0; i < R / 2; ++i) {
+            ev[i] = x[2 * i];
+            od[i] = x[2 * i + 1];
+        }
+        Dft<R / 2, DIR, T>::run(ev);
+        Dft<R / 2, DIR, T>::run(od);
+        static_for<R / 2>([&](auto kk) {
+            constexpr int k = decltype(kk)::value;
+            const cpx<T> t = twiddle_const<R, k, DIR>(od[k]);
+            x[k] = cadd(ev[k], t);
+            x[k + R / 2] = csub(ev[k], t);
+        });
+    }
+};
+template <int DIR, typename T>
+struct Dft<1, DIR, T> {
+    static __device__ __forceinline__ void run(cpx<T>*) {}
+};
+
+// Wavefront-scope barrier: orders LDS traffic of all lanes of this wave.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// LDS row buffer: element `pos` of a row lives at pad(pos); one extra slot
+// every 16 breaks the power-of-two strides of the Stockham exchanges.
+__host__ __device__ constexpr int lds_pad(int pos) { return pos + (pos >> 4); }
+__host__ __device__ constexpr int lds_row_elems(int n) { return n + (n >> 4) + 1; }
+
+// Radix plan: the first pass is radix 16; the remaining factor of N is split
+// into at most two more passes of radix <= 16.
+template <int N>
+struct Plan {
+    static constexpr int P = N / 16;  // lanes per row
+    static constexpr int R2 = (N <= 16) ? 1 : (N / 16 >= 16 ? 16 : N / 16);
+    static constexpr int R3 = (N <= 256) ? 1 : N / 256;
+    static_assert(N >= 16 && N <= 1024 && (N & (N - 1)) == 0, "N must be a power of two in [16, 1024]");
+};
+
+// Stockham pass of radix R over a row held in LDS (not the first pass).
+// Lane l handles butterflies b = l + P t, t < 16/R; butterfly b reads points
+// b + j N/R, twiddles input j by w_{pR}^{j (b mod p)}, and writes its outputs
+// to (b - k) R + k + j p, or, on the last pass, keeps them in registers in
+// canonical order (register t + j 16/R holds point l + P (t + j 16/R)).
+template <int N, int R, int PSTRIDE, bool LAST, int DIR, typename T>
+__device__ __forceinline__ void stockham_pass(cpx<T> (&x)[16], cpx<T>* row, const cpx<T>* __restrict__ tw,
+                                              int l) {
+    constexpr int P = N / 16;
+    constexpr int NB = 16 / R;
+    cpx<T> y[16];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+        const int b = l + P * t;
+#pragma unroll
+        for (int j = 0; j < R; ++j) y[t * R + j] = row[lds_pad(b + j * (N / R))];
+    }
+    wave_sync();  // every lane has read before anyone overwrites
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+        const int b = l + P * t;
+        const int k = b & (PSTRIDE - 1);
+        // w_{pR}^{jk} = w_N^{jk N/(pR)} from the forward table; conjugate for DIR > 0
+#pragma unroll
+        for (int j = 1; j < R; ++j) {
+            cpx<T> w = tw[j * k * (N / (PSTRIDE * R))];
+            if (DIR > 0) w.y = -w.y;
+            y[t * R + j] = cmul(y[t * R + j], w);
+        }
+        Dft<R, DIR, T>::run(&y[t * R]);
+    }
+    if constexpr (LAST) {
+#pragma unroll
+        for (int t = 0; t < NB; ++t)
+#pragma unroll
+            for (int j = 0; j < R; ++j) x[t + j * NB] = y[t * R + j];
+    } else {
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+            const int b = l + P * t;
+            const int k = b & (PSTRIDE - 1);
+#pragma unroll
+            for (int j = 0; j < R; ++j) row[lds_pad((b - k) * R + k + j * PSTRIDE)] = y[t * R + j];
+        }
+        wave_sync();
+    }
+}
+
+// Transform one row held in canonical registers, in place (unnormalised).
+// `row` is this row's LDS buffer (lds_row_elems(N) elements), `tw` the
+// forward table w_N^m = exp(-2 pi i m / N), m < N, and l the lane in the team.
+template <int N, int DIR, typename T>
+__device__ __forceinline__ void fft_row(cpx<T> (&x)[16], cpx<T>* row, const cpx<T>* __restrict__ tw, int l) {
+    using PL = Plan<N>;
+    Dft<16, DIR, T>::run(x);  // pass 1: butterfly b = l over points l + P j, no twiddles
+    if constexpr (N == 16) {
+        return;
+    } else {
+        // pass-1 outputs go to points 16 l + j
+#pragma unroll
+        for (int j = 0; j < 16; ++j) row[lds_pad(16 * l + j)] = x[j];
+        wave_sync();
+        if constexpr (PL::R3 == 1) {
+            stockham_pass<N, PL::R2, 16, true, DIR, T>(x, row, tw, l);
+        } else {
+            stockham_pass<N, PL::R2, 16, false, DIR, T>(x, row, tw, l);
+            stockham_pass<N, PL::R3, 16 * PL::R2, true, DIR, T>(x, row, tw, l);
+        }
+    }
+}
+
+// Block-index remap so that consecutive logical blocks (which write adjacent
+// pieces of the same cache lines) run on the same XCD: the hardware deals
+// blocks round-robin over 8 XCDs.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t phys, uint32_t total) {
+    if (total % 8u != 0u) return phys;
+    return (phys % 8u) * (total / 8u) + phys / 8u;
+}
+
+}  // namespace gridspt
