@@ -128,9 +128,11 @@ int64_t gridspt_workspace_bytes(const gridspt_grid* g, int32_t nmax);
 
 /* Step (1) of Sec. II C.  delta1(x) = inverse transform of
  * W1(k) sqrt(P0(k) N^3 / L^3) D w(k), where w(k) is the forward transform of
- * unit white noise w(x) drawn per cell c = (x N + y) N + z from
- * Philox4x64-10(counter = (c, stream, 0, 0), key = (seed, 0)) and Box-Muller
- * (first two words as 53-bit uniforms in (0,1), cosine branch), so that
+ * unit white noise w(x).  Cells c = (x N + y) N + z come in groups of four:
+ * group q = c / 4 draws Philox4x64-10(counter = (q, stream, 0, 0),
+ * key = (seed, 0)); its word pairs (w0, w1), (w2, w3) become 53-bit uniforms
+ * in (0, 1) and Box-Muller gives two Gaussians per pair (cosine first); cell
+ * 4q + r takes pair r / 2, branch r % 2.  So that
  * L^3 <|delta1(k)|^2> = D^2 P0(k) on kept modes and delta1(k=0) = 0.
  * delta1: N^3 real out.  delta1_k: cube-layout spectrum out, or NULL. */
 int gridspt_linear_field(gridspt_ctx* ctx, const gridspt_grid* g, const gridspt_linpk* lp, void* delta1,

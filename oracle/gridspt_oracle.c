@@ -227,18 +227,22 @@ void or_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* Unit Gaussian for cell `cell` of realisation `stream`: the first two words
- * of Philox(counter = (cell, stream, 0, 0), key = (seed, 0)) become uniforms
- * in (0, 1) with 53 random bits, then Box-Muller (cosine branch). */
+/* Unit Gaussian for cell `cell` of realisation `stream`.  Cells come in
+ * groups of four: group q = cell / 4 draws Philox(counter = (q, stream, 0, 0),
+ * key = (seed, 0)); word pairs (w0, w1) and (w2, w3) become uniforms in
+ * (0, 1) with 53 random bits, and Box-Muller turns each pair into two
+ * Gaussians, cosine branch first.  Cell 4q + r takes pair r / 2, branch r % 2. */
 double or_unit_gaussian(uint64_t seed, uint64_t stream, uint64_t cell)
 {
-    const uint64_t ctr[4] = {cell, stream, 0, 0};
+    const uint64_t ctr[4] = {cell >> 2, stream, 0, 0};
     const uint64_t key[2] = {seed, 0};
     uint64_t w[4];
     or_philox4x64_10(ctr, key, w);
-    const double u1 = ((double)(w[0] >> 11) + 0.5) * 0x1p-53;
-    const double u2 = ((double)(w[1] >> 11) + 0.5) * 0x1p-53;
-    return sqrt(-2.0 * log(u1)) * cos(TWO_PI * u2);
+    const int pair = (int)((cell >> 1) & 1), branch = (int)(cell & 1);
+    const double u1 = ((double)(w[2 * pair] >> 11) + 0.5) * 0x1p-53;
+    const double u2 = ((double)(w[2 * pair + 1] >> 11) + 0.5) * 0x1p-53;
+    const double r = sqrt(-2.0 * log(u1));
+    return branch ? r * sin(TWO_PI * u2) : r * cos(TWO_PI * u2);
 }
 
 /* ------------------------------------------------------------------------ */

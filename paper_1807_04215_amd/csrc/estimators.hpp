@@ -29,18 +29,23 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// Cross spectra.  Each wavefront walks whole cube rows (kz, ky') and, for each
-// group of 64 consecutive kx', sums w Re[F_a F_b^*] per bin with a fixed-order
-// wavefront reduction for every distinct bin in the group, into its own LDS
-// accumulator.  Quantities per bin: npairs pair sums, then sum w, sum w |k|.
-// Block partials [block][bin][q] are summed over blocks in block order.
+// Cross spectra.  A wavefront walks half-rows of the cube: the kx >= 0 part
+// (|kx| ascending) and the kx < 0 part (|kx| descending), so the bins of 64
+// consecutive modes are monotone and every bin present forms one contiguous
+// run of lanes.  A segmented inclusive scan over the 64 lanes (fixed order)
+// leaves each run's total in its last lane, which adds it to the wavefront's
+// own LDS accumulator.  Quantities per bin: npairs pair sums w Re[F_a F_b^*],
+// then sum w and sum w |k|.  Block partials [block][bin][q] are reduced in a
+// fixed order by k_power_reduce, so the result is bitwise reproducible.
 // ---------------------------------------------------------------------------
+constexpr int kPowerPairsPerLaunch = 16;
+
 template <typename T>
 struct PowerArgs {
-    const cpx<T>* f[kMaxFields];
-    int pa[kMaxPairs], pb[kMaxPairs];
+    const cpx<T>* f[kMaxFields];  // distinct fields used by this launch
+    int pa[kPowerPairsPerLaunch], pb[kPowerPairsPerLaunch];  // indices into f
     int64_t edges[kMaxBins + 1];
-    int npairs, nbins;
+    int nf, npairs, nbins;
     double kF;
     double* partial;  // [gridDim.x][nbins][npairs + 2]
 };
@@ -49,6 +54,7 @@ constexpr int kPowerWaves = 4;
 
 template <typename T>
 __global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T> a, CubeDims cd) {
+    constexpr int QP = kPowerPairsPerLaunch;
     extern __shared__ double acc[];  // [kPowerWaves][nbins][Q]
     __shared__ int64_t edges[kMaxBins + 1];
     const int Q = a.npairs + 2;
@@ -58,18 +64,21 @@ __global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T>
     __syncthreads();
     double* my = acc + (size_t)wave * a.nbins * Q;
     const int Kx = cd.Ky;
-    const long nrows = (long)cd.Kz * cd.Ky;
+    const long nhalf = 2L * cd.Kz * cd.Ky;  // half-rows
     const long gw = (long)blockIdx.x * kPowerWaves + wave, nw = (long)gridDim.x * kPowerWaves;
-    for (long rowi = gw; rowi < nrows; rowi += nw) {
+    for (long hr = gw; hr < nhalf; hr += nw) {
+        const long rowi = hr >> 1;
+        const int half = (int)(hr & 1);
         const int kz = (int)(rowi / cd.Ky), kyc = (int)(rowi % cd.Ky);
         const int ky = kyc <= cd.Kc ? kyc : kyc - cd.Ky;
         const double w = kz == 0 ? 1.0 : 2.0;
         const size_t base = (size_t)rowi * Kx;
-        for (int c0 = 0; c0 < Kx; c0 += 64) {
+        const int c_begin = half ? cd.Kc + 1 : 0, c_end = half ? Kx : cd.Kc + 1;
+        for (int c0 = c_begin; c0 < c_end; c0 += 64) {
             const int kxc = c0 + lane;
             int bin = -1;
             int64_t n2 = 0;
-            if (kxc < Kx) {
+            if (kxc < c_end) {
                 const int kx = kxc <= cd.Kc ? kxc : kxc - Kx;
                 n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
                 if (n2 >= edges[0] && n2 < edges[a.nbins]) {
@@ -82,27 +91,41 @@ __global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T>
                     bin = lo;
                 }
             }
-            uint64_t pending = __ballot(bin >= 0);
-            while (pending) {
-                const int leader = __ffsll((unsigned long long)pending) - 1;
-                const int b = __shfl(bin, leader, 64);
-                const bool mine = bin == b;
-                for (int q = 0; q < Q; ++q) {
-                    double v = 0.0;
-                    if (mine) {
-                        if (q < a.npairs) {
-                            const cpx<T> x = a.f[a.pa[q]][base + kxc], y = a.f[a.pb[q]][base + kxc];
-                            v = w * ((double)x.x * (double)y.x + (double)x.y * (double)y.y);
-                        } else if (q == a.npairs) {
-                            v = w;
-                        } else {
-                            v = w * a.kF * sqrt((double)n2);
-                        }
-                    }
-                    v = wave_sum(v);
-                    if (lane == 0) my[b * Q + q] += v;
+            if (!__any(bin >= 0)) continue;
+            // per-mode quantities (repeated fields of different pairs hit the cache)
+            double v[QP + 2];
+#pragma unroll
+            for (int q = 0; q < QP; ++q) {
+                v[q] = 0.0;
+                if (q < a.npairs && bin >= 0) {
+                    const cpx<T> x = a.f[a.pa[q]][base + kxc], y = a.f[a.pb[q]][base + kxc];
+                    v[q] = w * ((double)x.x * (double)y.x + (double)x.y * (double)y.y);
                 }
-                pending &= ~__ballot(mine);
+            }
+            v[QP] = bin >= 0 ? w : 0.0;
+            v[QP + 1] = bin >= 0 ? w * a.kF * sqrt((double)n2) : 0.0;
+            // segmented inclusive scan over runs of equal bin
+#pragma unroll
+            for (int s = 1; s < 64; s <<= 1) {
+                const int ob = __shfl_up(bin, s, 64);
+                const bool same = lane >= s && ob == bin;
+#pragma unroll
+                for (int q = 0; q < QP + 2; ++q) {
+                    if (q < a.npairs || q >= QP) {
+                        const double o = __shfl_up(v[q], s, 64);
+                        if (same) v[q] += o;
+                    }
+                }
+            }
+            const int nb = __shfl_down(bin, 1, 64);
+            const bool last = lane == 63 || nb != bin;
+            if (last && bin >= 0) {
+                double* dst = my + (size_t)bin * Q;
+#pragma unroll
+                for (int q = 0; q < QP; ++q)
+                    if (q < a.npairs) dst[q] += v[q];
+                dst[a.npairs] += v[QP];
+                dst[a.npairs + 1] += v[QP + 1];
             }
         }
     }
@@ -115,24 +138,34 @@ __global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T>
     }
 }
 
-// Sum block partials in block order; then P = L^3 S / sum w, kmean, nmodes.
-__global__ void k_power_final(const double* partial, int nblocks, int nbins, int npairs, double vol, double* pk,
+// One block per (bin, q): sum the block partials in a fixed order (strided
+// per thread, then an LDS tree) into sums[bin][q].
+constexpr int kReduceThreads = 256;
+__global__ __launch_bounds__(kReduceThreads) void k_power_reduce(const double* partial, int nblocks, int nq,
+                                                                 double* sums) {
+    __shared__ double red[kReduceThreads];
+    const int item = blockIdx.x;  // bin * nq + q
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += kReduceThreads) s += partial[(size_t)i * gridDim.x + item];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[item] = red[0];
+}
+
+// P = L^3 S / sum w, kmean = sum w |k| / sum w, nmodes = sum w.
+__global__ void k_power_final(const double* sums, int nbins, int npairs, double vol, double* pk, int pk_stride,
                               double* kmean, double* nmodes) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nbins) return;
     const int Q = npairs + 2;
-    double cnt = 0.0, ks = 0.0;
-    for (int i = 0; i < nblocks; ++i) {
-        cnt += partial[((size_t)i * nbins + b) * Q + npairs];
-        ks += partial[((size_t)i * nbins + b) * Q + npairs + 1];
-    }
+    const double cnt = sums[(size_t)b * Q + npairs], ks = sums[(size_t)b * Q + npairs + 1];
     if (nmodes) nmodes[b] = cnt;
     if (kmean) kmean[b] = cnt > 0.0 ? ks / cnt : 0.0;
-    for (int p = 0; p < npairs; ++p) {
-        double s = 0.0;
-        for (int i = 0; i < nblocks; ++i) s += partial[((size_t)i * nbins + b) * Q + p];
-        pk[(size_t)p * nbins + b] = cnt > 0.0 ? vol * s / cnt : 0.0;
-    }
+    for (int p = 0; p < npairs; ++p) pk[(size_t)p * pk_stride + b] = cnt > 0.0 ? vol * sums[(size_t)b * Q + p] / cnt : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -210,11 +243,22 @@ struct SumArgs {
 
 template <typename T>
 __global__ void k_sum_orders(SumArgs<T> s) {
+    // four consecutive cells per thread and iteration (ncell is a multiple of 4)
+    using V4 = HIP_vector_type<T, 4>;
+    const size_t n4 = s.ncell / 4;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < s.ncell; i += stride) {
-        double v = 0.0;
-        for (int n = 0; n < s.nmax; ++n) v += s.coef[n] * (double)s.d[n][i];
-        s.out[i] = v;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int n = 0; n < s.nmax; ++n) {
+            const V4 v = reinterpret_cast<const V4*>(s.d[n])[i];
+            acc[0] += s.coef[n] * (double)v.x;
+            acc[1] += s.coef[n] * (double)v.y;
+            acc[2] += s.coef[n] * (double)v.z;
+            acc[3] += s.coef[n] * (double)v.w;
+        }
+        double2* o = reinterpret_cast<double2*>(s.out + 4 * i);
+        o[0] = make_double2(acc[0], acc[1]);
+        o[1] = make_double2(acc[2], acc[3]);
     }
 }
 

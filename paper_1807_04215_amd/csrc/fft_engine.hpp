@@ -42,6 +42,14 @@ __device__ __forceinline__ cpx<T> cconj(cpx<T> a) { return {a.x, -a.y}; }
 template <typename T>
 __device__ __forceinline__ cpx<T> cmul_i(cpx<T> a) { return {-a.y, a.x}; }
 
+// Force a value to be materialised in registers at this point: an empty asm
+// with a read-write register operand (emits no instruction), which stops the
+// compiler from sinking the computation of v past later code.
+template <typename T>
+__device__ __forceinline__ void keep_here(cpx<T>& v) {
+    asm volatile("" : "+v"(v.x), "+v"(v.y));
+}
+
 // Compile-time loop.
 template <typename F, int... Ks>
 __device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Ks...>) {

@@ -254,7 +254,7 @@ struct Pipe {
     int zfwd_single(const T* f, bool noise, uint64_t seed, uint64_t stream) {
         ProductInputs<T> pin{};
         const double bytes = (noise ? 0.0 : (double)d.ncell() * d.real_bytes) + (double)d.s1() * d.cpx_bytes;
-        const dim3 grid(N * (N / RW::RPB)), block(RW::THREADS);
+        const dim3 grid(N * (N / (2 * RW::RPB))), block(RW::THREADS);  // two rows per transform
         if (noise)
             return launch(c, KD_ZFWD_NOISE, bytes, grid, block, 0, k_zfwd<T, N, 1, 0>, f, pin, seed, stream, A(),
                           (size_t)L.a_field_s1, (const cpx<T>*)tw(), (int)d.Kz);
@@ -329,27 +329,28 @@ struct Pipe {
                       (size_t)L.b_field_s4, (const cpx<T>*)tw(), cd);
     }
 
-    // P5: S4 (B) -> real outputs, fields paired two per transform
-    int zinv(const ZPairs<T>& zp, int npairs) {
+    // P5: S4 (B) -> real outputs, two real rows per complex transform
+    int zinv(const ZJobs<T>& zj, int njobs) {
         int nout = 0;
-        for (int i = 0; i < npairs; ++i) nout += 1 + (zp.fb[i] >= 0 ? 1 : 0);
+        for (int i = 0; i < njobs; ++i) nout += zj.fb[i] >= 0 ? 2 : 1;
         const double bytes = (double)nout * ((double)d.s4() * d.cpx_bytes + (double)d.ncell() * d.real_bytes);
-        return launch(c, KD_ZINV, bytes, dim3((unsigned)(N * N / RW::RPB), npairs), dim3(RW::THREADS), 0,
-                      k_zinv<T, N>, (const cpx<T>*)B(), (size_t)L.b_field_s4, zp, (const cpx<T>*)tw(), cd);
+        return launch(c, KD_ZINV, bytes, dim3((unsigned)(N * N / RW::RPB), njobs), dim3(RW::THREADS), 0,
+                      k_zinv<T, N>, (const cpx<T>*)B(), (size_t)L.b_field_s4, zj, (const cpx<T>*)tw(), cd);
     }
 
-    // P4 + P5 for nf fields of S3 into real outputs out[0..nf-1] (paired)
+    // P4 + P5 for nf fields of S3 into real outputs out[0..nf-1]: fields two
+    // by two, an odd last field two rows at a time
     int to_real(int nf, T* const* out) {
         CHECK(yinv(nf));
-        ZPairs<T> zp{};
-        int np = 0;
-        for (int i = 0; i < nf; i += 2, ++np) {
-            zp.fa[np] = i;
-            zp.outa[np] = out[i];
-            zp.fb[np] = (i + 1 < nf) ? i + 1 : -1;
-            zp.outb[np] = (i + 1 < nf) ? out[i + 1] : nullptr;
+        ZJobs<T> zj{};
+        int nj = 0;
+        for (int i = 0; i < nf; i += 2, ++nj) {
+            zj.fa[nj] = i;
+            zj.outa[nj] = out[i];
+            zj.fb[nj] = (i + 1 < nf) ? i + 1 : -1;
+            zj.outb[nj] = (i + 1 < nf) ? out[i + 1] : nullptr;
         }
-        return zinv(zp, np);
+        return zinv(zj, nj);
     }
 
     int copy(const T* src, T* dst) {
@@ -700,10 +701,12 @@ int gridspt_sum_orders(gridspt_ctx* c, const gridspt_grid* g, int32_t nmax, cons
 }
 
 // per-wave LDS accumulators: nbins * (pairs + 2) doubles, at most 1792 (56 KB per block)
-static int power_chunk(int nbins) { return std::max(1, std::min(kMaxPairs, 1792 / nbins - 2)); }
+static int power_chunk(int nbins) {
+    return std::max(1, std::min(kPowerPairsPerLaunch, 1792 / nbins - 2));
+}
 static int power_blocks(const Dims& d) {
-    const int64_t rows = d.Kz * d.Ky;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (rows + kPowerWaves - 1) / kPowerWaves));
+    const int64_t halves = 2 * d.Kz * d.Ky;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (halves + kPowerWaves - 1) / kPowerWaves));
 }
 
 int64_t gridspt_power_workspace_bytes(const gridspt_grid* g, int32_t npairs, int32_t nbins) {
@@ -712,7 +715,8 @@ int64_t gridspt_power_workspace_bytes(const gridspt_grid* g, int32_t npairs, int
     if (npairs < 1 || npairs > kMaxPairs || nbins < 1 || nbins > kMaxBins) return GRIDSPT_EINVAL;
     const Dims d = dims_of(g);
     const int q = std::min(npairs, power_chunk(nbins)) + 2;
-    return align_up((int64_t)power_blocks(d) * nbins * q * 8);
+    // block partials, then the reduced sums
+    return align_up((int64_t)power_blocks(d) * nbins * q * 8) + align_up((int64_t)nbins * q * 8);
 }
 
 int gridspt_power(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, const void* const* fields_k,
@@ -739,30 +743,43 @@ int gridspt_power(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, const 
     const int chunk = power_chunk(nbins);
     auto go = [&](auto tag) -> int {
         using T = typename decltype(tag)::type;
+        double* partial = static_cast<double*>(work);
+        double* sums = reinterpret_cast<double*>(static_cast<char*>(work) +
+                                                 align_up((int64_t)nblk * nbins * (std::min(npairs, chunk) + 2) * 8));
         for (int p0 = 0; p0 < npairs; p0 += chunk) {
             const int np = std::min(chunk, npairs - p0);
             PowerArgs<T> a{};
-            std::vector<int> used(nfields, 0);
-            for (int i = 0; i < nfields; ++i) a.f[i] = static_cast<const cpx<T>*>(fields_k[i]);
+            // distinct fields of this chunk
+            int slot_of[kMaxFields];
+            for (int i = 0; i < kMaxFields; ++i) slot_of[i] = -1;
+            int nf = 0;
+            for (int q = 0; q < np; ++q)
+                for (int k = 0; k < 2; ++k) {
+                    const int f = pairs[2 * (p0 + q) + k];
+                    if (slot_of[f] < 0) {
+                        slot_of[f] = nf;
+                        a.f[nf++] = static_cast<const cpx<T>*>(fields_k[f]);
+                    }
+                }
             for (int q = 0; q < np; ++q) {
-                a.pa[q] = pairs[2 * (p0 + q)];
-                a.pb[q] = pairs[2 * (p0 + q) + 1];
-                used[a.pa[q]] = used[a.pb[q]] = 1;
+                a.pa[q] = slot_of[pairs[2 * (p0 + q)]];
+                a.pb[q] = slot_of[pairs[2 * (p0 + q) + 1]];
             }
             for (int b = 0; b <= nbins; ++b) a.edges[b] = edge_n2[b];
+            a.nf = nf;
             a.npairs = np;
             a.nbins = nbins;
             a.kF = 2.0 * M_PI / g->box;
-            a.partial = static_cast<double*>(work);
-            int nused = 0;
-            for (int i = 0; i < nfields; ++i) nused += used[i];
-            const size_t shm = (size_t)kPowerWaves * nbins * (np + 2) * sizeof(double);
-            CHECK(launch(c, KD_POWER, (double)nused * d.cube() * d.cpx_bytes, dim3(nblk), dim3(64 * kPowerWaves), shm,
+            a.partial = partial;
+            const int nq = np + 2;
+            const size_t shm = (size_t)kPowerWaves * nbins * nq * sizeof(double);
+            CHECK(launch(c, KD_POWER, (double)nf * d.cube() * d.cpx_bytes, dim3(nblk), dim3(64 * kPowerWaves), shm,
                          k_power_partial<T>, a, CubeDims{(int)d.Kc, (int)d.Kz, (int)d.Ky}));
-            CHECK(launch(c, KD_POWER_FINAL, (double)nblk * nbins * (np + 2) * 8.0, dim3((nbins + 63) / 64), dim3(64),
-                         0, k_power_final, (const double*)a.partial, nblk, nbins, np,
-                         g->box * g->box * g->box, pk + (size_t)p0 * nbins, p0 == 0 ? kmean : nullptr,
-                         p0 == 0 ? nmodes : nullptr));
+            CHECK(launch(c, KD_POWER_FINAL, (double)nblk * nbins * nq * 8.0, dim3(nbins * nq), dim3(kReduceThreads),
+                         0, k_power_reduce, (const double*)partial, nblk, nq, sums));
+            CHECK(launch(c, KD_POWER_FINAL, 0.0, dim3((nbins + 63) / 64), dim3(64), 0, k_power_final,
+                         (const double*)sums, nbins, np, g->box * g->box * g->box, pk + (size_t)p0 * nbins, nbins,
+                         p0 == 0 ? kmean : nullptr, p0 == 0 ? nmodes : nullptr));
         }
         return GRIDSPT_OK;
     };

@@ -17,6 +17,14 @@
 //   S4 [x][y][kz]    N  x N  x Kz     after the inverse y pass
 //   cube [kz][ky][kx] Kz x Ky x Kx    the spectra handed to the caller
 // Real fields are [x][y][z], z contiguous.
+//
+// Real data along z is transformed two rows (or two fields) per complex FFT:
+// c = a + i b gives A(k) = (C(k) + C(-k)^*) / 2 and B(k) = (C(k) - C(-k)^*) / 2i,
+// and in reverse C(k) = A(k) + i B(k), C(-k) = A(k)^* + i B(k)^*.
+//
+// Addressing: the rows a block touches start at a block-uniform base pointer;
+// the bulk loads add a 32-bit per-lane offset to it, so loads use the scalar
+// base + vector offset form and need no 64-bit address registers.
 #pragma once
 #include "fft_engine.hpp"
 
@@ -24,14 +32,24 @@ namespace gridspt {
 
 template <typename T, int N>
 struct Rows {
-    // rows per block: about 64 KB of LDS, at most 32 rows, at most N rows
+    // rows per block: about 64 KB of LDS, at most 32 rows, at most N/2 rows
     static constexpr int bytes = 65536 / (N * (int)sizeof(cpx<T>));
     static constexpr int RPB0 = bytes < 1 ? 1 : (bytes > 32 ? 32 : bytes);
-    static constexpr int RPB = RPB0 > N ? N : RPB0;
+    static constexpr int RPB = RPB0 > N / 2 ? N / 2 : RPB0;
     static constexpr int P = N / 16;
     static constexpr int THREADS = RPB * P;
     static constexpr int ROWE = lds_row_elems(N);
 };
+
+// element at a 32-bit element offset from a block-uniform base
+template <typename T>
+__device__ __forceinline__ T ldo(const T* base, uint32_t idx) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void sto(T* base, uint32_t idx, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(T)) = v;
+}
 
 // signed mode index of FFT position p on an N grid
 __device__ __forceinline__ int signed_pos(int p, int n) { return p < n / 2 ? p : p - n; }
@@ -45,11 +63,13 @@ __device__ __forceinline__ int pos_to_compact(int p, int Kc, int n) {
 }
 
 // --------------------------------------------------------------------------
-// Philox4x64-10 (Salmon et al., SC'11) and Box-Muller: unit Gaussian of a cell.
-// counter = (cell, stream, 0, 0), key = (seed, 0); two 53-bit uniforms in (0,1).
+// Philox4x64-10 (Salmon et al., SC'11) and Box-Muller: unit Gaussians of the
+// four cells 4q .. 4q+3.  counter = (q, stream, 0, 0), key = (seed, 0); word
+// pairs (w0, w1), (w2, w3) give 53-bit uniforms in (0, 1); cell 4q + r takes
+// pair r / 2 and the cosine (r even) or sine (r odd) branch.
 // --------------------------------------------------------------------------
-__device__ __forceinline__ double cell_gaussian(uint64_t seed, uint64_t stream, uint64_t cell) {
-    uint64_t c0 = cell, c1 = stream, c2 = 0, c3 = 0;
+__device__ __forceinline__ void group_gaussians(uint64_t seed, uint64_t stream, uint64_t q, double (&g)[4]) {
+    uint64_t c0 = q, c1 = stream, c2 = 0, c3 = 0;
     uint64_t k0 = seed, k1 = 0;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
@@ -65,9 +85,16 @@ __device__ __forceinline__ double cell_gaussian(uint64_t seed, uint64_t stream, 
         c2 = n2;
         c3 = lo0;
     }
-    const double u1 = ((double)(c0 >> 11) + 0.5) * 0x1p-53;
-    const double u2 = ((double)(c1 >> 11) + 0.5) * 0x1p-53;
-    return sqrt(-2.0 * log(u1)) * cos(6.28318530717958647692528676655900577 * u2);
+    const uint64_t w[4] = {c0, c1, c2, c3};
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const double u1 = ((double)(w[2 * p] >> 11) + 0.5) * 0x1p-53;
+        const double u2 = ((double)(w[2 * p + 1] >> 11) + 0.5) * 0x1p-53;
+        const double rad = sqrt(-2.0 * log(u1));
+        const double ang = 6.28318530717958647692528676655900577 * u2;
+        g[2 * p] = rad * cos(ang);
+        g[2 * p + 1] = rad * sin(ang);
+    }
 }
 
 // Linear amplitude sqrt(P0(k) N^3 / L^3) D, P0 = A k^ns T(k / Gamma)^2 with the
@@ -86,10 +113,6 @@ __device__ __forceinline__ double lin_amplitude(double k, const LinParams& p) {
     return sqrt(p0 * p.vol) * p.growth;
 }
 
-// --------------------------------------------------------------------------
-// shared pieces
-// --------------------------------------------------------------------------
-
 // canonical registers of one row -> this row's LDS buffer in natural order
 template <int N, typename T>
 __device__ __forceinline__ void stage_row(const cpx<T> (&v)[16], cpx<T>* row, int l) {
@@ -98,11 +121,22 @@ __device__ __forceinline__ void stage_row(const cpx<T> (&v)[16], cpx<T>* row, in
     for (int e = 0; e < 16; ++e) row[lds_pad(l + P * e)] = v[e];
 }
 
+// unpack the transform C of c = a + i b at mode k (m = C(-k)):
+// which = 0 gives A(k), which = 1 gives B(k)
+template <typename T>
+__device__ __forceinline__ cpx<T> unpack_real_pair(cpx<T> c, cpx<T> m, int which) {
+    if (which == 0) return {(T)0.5 * (c.x + m.x), (T)0.5 * (c.y - m.y)};
+    return {(T)0.5 * (c.y + m.y), (T)0.5 * (m.x - c.x)};
+}
+
 // --------------------------------------------------------------------------
-// P1: z pass, forward.  Block = RPB consecutive y at one x.
-// SRC 0: one real field; SRC 1: Gaussian noise generated in place;
-// SRC 2: the products of order n (V = sum delta_m u_{n-m}, W = sum u_m.u_{n-m}).
-// Output S1 fields.
+// P1: z pass, forward, into S1.
+// SRC 0: one real field, SRC 1: Gaussian noise generated in place.  A block
+//   covers 2 RPB consecutive y at one x; team r transforms rows y0 + r (real
+//   part) and y0 + RPB + r (imaginary part) together.
+// SRC 2: the products of order NORD, V = sum_m delta_m u_{n-m} and
+//   W = sum_m u_m . u_{n-m} (the divergence form of the sources of Eq. 10),
+//   packed as V_x + i V_y and V_z + i W; a block covers RPB consecutive y.
 // --------------------------------------------------------------------------
 template <typename T>
 struct ProductInputs {
@@ -110,16 +144,15 @@ struct ProductInputs {
     const T* u[4][3];  // u_1 .. u_{n-1}
 };
 
-// SRC 2, order NORD: every input field is read once per cell; V and W are
-// formed in registers and packed as a = V_x + i V_y, b = V_z + i W.
 template <typename T, int NORD>
-__device__ __forceinline__ void load_products(const ProductInputs<T>& pin, size_t c, cpx<T>& a, cpx<T>& b) {
+__device__ __forceinline__ void load_products(const ProductInputs<T>& pin, size_t blockbase, uint32_t off,
+                                              cpx<T>& a, cpx<T>& b) {
     T d[NORD], u[NORD][3];
 #pragma unroll
     for (int m = 1; m < NORD; ++m) {
-        d[m] = pin.d[m - 1][c];
+        d[m] = ldo(pin.d[m - 1] + blockbase, off);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) u[m][j] = pin.u[m - 1][j][c];
+        for (int j = 0; j < 3; ++j) u[m][j] = ldo(pin.u[m - 1][j] + blockbase, off);
     }
     T vx = 0, vy = 0, vz = 0, w = 0;
 #pragma unroll
@@ -135,28 +168,55 @@ __device__ __forceinline__ void load_products(const ProductInputs<T>& pin, size_
 
 template <typename T, int N, int SRC, int NORD>
 __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zfwd(const T* __restrict__ f, ProductInputs<T> pin,
-                                                               uint64_t seed, uint64_t stream, cpx<T>* __restrict__ s1,
-                                                               size_t s1_field, const cpx<T>* __restrict__ tw, int Kz) {
+                                                                 uint64_t seed, uint64_t stream,
+                                                                 cpx<T>* __restrict__ s1, size_t s1_field,
+                                                                 const cpx<T>* __restrict__ tw, int Kz) {
     using RW = Rows<T, N>;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
+    constexpr int YB = (SRC == 2) ? RPB : 2 * RPB;  // rows of y per block
     __shared__ cpx<T> lds[RPB * ROWE];
-    const uint32_t groups = N / RPB;
+    constexpr uint32_t groups = N / YB;
     const uint32_t blk = xcd_block(blockIdx.x, N * groups);
-    const int x = blk / groups, y0 = (blk % groups) * RPB;
+    const int x = blk / groups, y0 = (blk % groups) * YB;
     const int r = threadIdx.x / P, l = threadIdx.x % P;
-    const size_t rowbase = ((size_t)x * N + (y0 + r)) * N;
+    const size_t blockbase = ((size_t)x * N + y0) * N;  // first cell of the block
     cpx<T>* row = lds + r * ROWE;
 
     cpx<T> a[16], b[16];
+    if constexpr (SRC == 1) {
+        // 2 RPB N consecutive cells: each thread draws 8 groups of 4 cells
+        // straight into the LDS rows (row y0 + rr goes to team rr % RPB, real
+        // part for rr < RPB, imaginary part otherwise)
+        T* words = reinterpret_cast<T*>(lds);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const size_t c = rowbase + l + P * e;
-        if constexpr (SRC == 0) {
-            a[e] = {f[c], (T)0};
-        } else if constexpr (SRC == 1) {
-            a[e] = {(T)cell_gaussian(seed, stream, c), (T)0};
-        } else {
-            load_products<T, NORD>(pin, c, a[e], b[e]);
+        for (int i = 0; i < 8; ++i) {
+            const int grp = threadIdx.x + RW::THREADS * i;  // < 2 RPB N / 4
+            double gs[4];
+            group_gaussians(seed, stream, (blockbase >> 2) + grp, gs);
+            const int rr = (4 * grp) / N, pos = (4 * grp) % N;
+            const int team = rr % RPB, part = rr / RPB;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) words[2 * (team * ROWE + lds_pad(pos + k)) + part] = (T)gs[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 16; ++e) a[e] = row[lds_pad(l + P * e)];
+        wave_sync();
+    } else if constexpr (SRC == 0) {
+        const T* f0 = f + blockbase;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const uint32_t o = (uint32_t)(r * N + l + P * e);
+            a[e] = {ldo(f0, o), ldo(f0, o + (uint32_t)(RPB * N))};
+        }
+    } else {
+        // the packed products are formed here, not after the first transform,
+        // so the raw inputs are dead before the FFTs start
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            load_products<T, NORD>(pin, blockbase, (uint32_t)(r * N + l + P * e), a[e], b[e]);
+            keep_here(a[e]);
+            keep_here(b[e]);
         }
     }
 
@@ -170,21 +230,19 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zfwd(const T* __restr
         fft_row<N, -1, T>(v, row, tw, l);
         stage_row<N, T>(v, row, l);
         __syncthreads();
-        // read-out: element (kz, y0 + rr) of every row
-        for (int idx = threadIdx.x; idx < Kz * RPB; idx += RW::THREADS) {
-            const int kz = idx / RPB, rr = idx % RPB;
-            const cpx<T> c = lds[rr * ROWE + lds_pad(kz)];
-            const size_t o = ((size_t)kz * N + x) * N + y0 + rr;
+        // read-out: S1[kz][x][y0 + rr] for every kept kz
+        cpx<T>* out = s1 + ((size_t)x * N + y0);
+        for (int idx = threadIdx.x; idx < Kz * YB; idx += RW::THREADS) {
+            const int kz = idx / YB, rr = idx % YB;
+            const int team = (SRC == 2) ? rr : rr % RPB;
+            const cpx<T> c = lds[team * ROWE + lds_pad(kz)];
+            const cpx<T> m = lds[team * ROWE + lds_pad((N - kz) & (N - 1))];
+            const size_t o = (size_t)kz * N * N + rr;
             if constexpr (SRC == 2) {
-                // two real fields packed as c = A + iB:
-                // A(k) = (C(k) + C(-k)^*) / 2,  B(k) = (C(k) - C(-k)^*) / 2i
-                const cpx<T> m = lds[rr * ROWE + lds_pad((N - kz) & (N - 1))];
-                const cpx<T> A = {(T)0.5 * (c.x + m.x), (T)0.5 * (c.y - m.y)};
-                const cpx<T> B = {(T)0.5 * (c.y + m.y), (T)0.5 * (m.x - c.x)};
-                s1[(size_t)(2 * pk) * s1_field + o] = A;
-                s1[(size_t)(2 * pk + 1) * s1_field + o] = B;
+                out[(size_t)(2 * pk) * s1_field + o] = unpack_real_pair(c, m, 0);
+                out[(size_t)(2 * pk + 1) * s1_field + o] = unpack_real_pair(c, m, 1);
             } else {
-                s1[o] = c;
+                out[o] = unpack_real_pair(c, m, rr / RPB);
             }
         }
     });
@@ -196,27 +254,27 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zfwd(const T* __restr
 // --------------------------------------------------------------------------
 template <typename T, int N>
 __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_yfwd(const cpx<T>* __restrict__ s1, size_t s1_field,
-                                                               cpx<T>* __restrict__ s2, size_t s2_field,
-                                                               const cpx<T>* __restrict__ tw, CubeDims cd) {
+                                                                 cpx<T>* __restrict__ s2, size_t s2_field,
+                                                                 const cpx<T>* __restrict__ tw, CubeDims cd) {
     using RW = Rows<T, N>;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
     __shared__ cpx<T> lds[RPB * ROWE];
-    const uint32_t groups = N / RPB;
+    constexpr uint32_t groups = N / RPB;
     const uint32_t blk = xcd_block(blockIdx.x, cd.Kz * groups);
     const int kz = blk / groups, x0 = (blk % groups) * RPB;
     const int r = threadIdx.x / P, l = threadIdx.x % P;
-    const cpx<T>* in = s1 + (size_t)blockIdx.y * s1_field + ((size_t)kz * N + x0 + r) * N;
-    cpx<T>* out = s2 + (size_t)blockIdx.y * s2_field;
+    const cpx<T>* in = s1 + (size_t)blockIdx.y * s1_field + ((size_t)kz * N + x0) * N;
     cpx<T>* row = lds + r * ROWE;
     cpx<T> v[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) v[e] = in[l + P * e];
+    for (int e = 0; e < 16; ++e) v[e] = ldo(in, (uint32_t)(r * N + l + P * e));
     fft_row<N, -1, T>(v, row, tw, l);
     stage_row<N, T>(v, row, l);
     __syncthreads();
+    cpx<T>* out = s2 + (size_t)blockIdx.y * s2_field + (size_t)kz * cd.Ky * N + x0;
     for (int idx = threadIdx.x; idx < cd.Ky * RPB; idx += RW::THREADS) {
         const int ky = idx / RPB, rr = idx % RPB;
-        out[((size_t)kz * cd.Ky + ky) * N + x0 + rr] = lds[rr * ROWE + lds_pad(compact_to_pos(ky, cd.Kc, N))];
+        sto(out, (uint32_t)(ky * N + rr), lds[rr * ROWE + lds_pad(compact_to_pos(ky, cd.Kc, N))]);
     }
 }
 
@@ -241,9 +299,26 @@ struct XArgs {
     LinParams lin;
 };
 
+// inverse x transform of one output row and its transposed store into S3
+template <typename T, int N>
+__device__ __forceinline__ void x_inverse_store(cpx<T> (&v)[16], cpx<T>* lds, cpx<T>* row,
+                                                const cpx<T>* __restrict__ tw, int l, cpx<T>* out, int Ky,
+                                                int nrows) {
+    using RW = Rows<T, N>;
+    constexpr int RPB = RW::RPB, ROWE = RW::ROWE;
+    __syncthreads();  // the previous read-out is done with LDS
+    fft_row<N, +1, T>(v, row, tw, l);
+    stage_row<N, T>(v, row, l);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < N * RPB; idx += RW::THREADS) {
+        const int x = idx / RPB, rr = idx % RPB;
+        if (rr < nrows) sto(out, (uint32_t)(x * Ky + rr), lds[rr * ROWE + lds_pad(x)]);
+    }
+}
+
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xfused(XArgs<T> a, const cpx<T>* __restrict__ tw,
-                                                                 CubeDims cd) {
+                                                                   CubeDims cd) {
     using RW = Rows<T, N>;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
     __shared__ cpx<T> lds[RPB * ROWE];
@@ -254,22 +329,24 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xfused(XArgs<T> a, co
     const int kyc = ky0 + r;
     const bool active = kyc < cd.Ky;
     const int ky = active ? (kyc <= cd.Kc ? kyc : kyc - cd.Ky) : 0;
+    const int nrows = min(RPB, cd.Ky - ky0);
     cpx<T>* row = lds + r * ROWE;
-    const size_t rowoff = ((size_t)kz * cd.Ky + (active ? kyc : 0)) * N;
+    const size_t inbase = ((size_t)kz * cd.Ky + ky0) * N;
 
     // k-space step: sd holds delta_n(k), st holds theta_n(k) afterwards
     cpx<T> sd[16], st[16];
-    const int nin = (MODE == XM_ORDER) ? 4 : 1;
+    constexpr int NIN = (MODE == XM_ORDER) ? 4 : 1;
 #pragma unroll
     for (int e = 0; e < 16; ++e) sd[e] = st[e] = {(T)0, (T)0};
-    for (int f = 0; f < nin; ++f) {
+    static_for<NIN>([&](auto fc) {
+        constexpr int f = decltype(fc)::value;
         cpx<T> v[16];
-        const cpx<T>* in = a.s2 + (size_t)f * a.s2_field + rowoff;
+        const cpx<T>* in = a.s2 + (size_t)f * a.s2_field + inbase;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = active ? in[l + P * e] : cpx<T>{(T)0, (T)0};
+        for (int e = 0; e < 16; ++e) v[e] = active ? ldo(in, (uint32_t)(r * N + l + P * e)) : cpx<T>{(T)0, (T)0};
         fft_row<N, -1, T>(v, row, tw, l);
         if constexpr (MODE == XM_ORDER) {
-            if (f < 3) {
+            if constexpr (f < 3) {
                 // S_delta += i k_f V_f(k)  (kF and N^-3 applied below)
 #pragma unroll
                 for (int e = 0; e < 16; ++e) {
@@ -281,11 +358,16 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xfused(XArgs<T> a, co
 #pragma unroll
                 for (int e = 0; e < 16; ++e) st[e] = v[e];
             }
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                keep_here(sd[e]);
+                keep_here(st[e]);
+            }
         } else {
 #pragma unroll
             for (int e = 0; e < 16; ++e) sd[e] = v[e];
         }
-    }
+    });
 
     const T kF = (T)a.kF, invN3 = (T)a.invN3;
 #pragma unroll
@@ -307,11 +389,14 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xfused(XArgs<T> a, co
             T s = (T)0;
             if (keep) s = (T)(lin_amplitude(a.kF * sqrt((double)n2), a.lin) * a.invN3);
             sd[e] = cscale(sd[e], s);
-            st[e] = sd[e];
         } else {
             sd[e] = keep ? cscale(sd[e], invN3) : cpx<T>{(T)0, (T)0};
-            st[e] = sd[e];
         }
+    }
+    // theta_1 = delta_1 below order 2
+    if constexpr (MODE != XM_ORDER) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) st[e] = sd[e];
     }
 
     // cube stores (masked spectra), kept kx only
@@ -326,37 +411,33 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xfused(XArgs<T> a, co
             }
         }
     }
-    if constexpr (MODE == XM_FORWARD) return;
-
-    // outputs: 0 delta, 1 theta (or u_x for order 1), then u components
-    for (int o = 0; o < a.nout; ++o) {
-        cpx<T> v[16];
-        // field o: ORDER: {delta, theta, ux, uy, uz}; ORDER1: {delta, ux, uy, uz}; LINEAR: {delta}
-        const int comp = (MODE == XM_ORDER) ? o - 2 : o - 1;  // velocity component, < 0 for delta/theta
+    if constexpr (MODE != XM_FORWARD) {
+        // outputs.  ORDER: delta, theta, u_x, u_y, u_z;  ORDER1: delta, u_x, u_y, u_z;  LINEAR: delta
+        constexpr int NOUT_MAX = (MODE == XM_ORDER) ? 5 : (MODE == XM_ORDER1 ? 4 : 1);
+        constexpr int FIRST_U = (MODE == XM_ORDER) ? 2 : 1;
+        const size_t outbase = (size_t)kz * N * cd.Ky + ky0;
+        static_for<NOUT_MAX>([&](auto oc) {
+            constexpr int o = decltype(oc)::value;
+            if (o < a.nout) {
+                cpx<T> v[16];
+                if constexpr (o < FIRST_U) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            if (comp < 0) {
-                v[e] = (MODE == XM_ORDER && o == 1) ? st[e] : sd[e];
-            } else {
-                // u_j(k) = (-i k_j / k^2) theta(k)
-                const int kx = signed_pos(l + P * e, N);
-                const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
-                const int kj = comp == 0 ? kx : (comp == 1 ? ky : kz);
-                const T s = n2 > 0 ? (T)((double)kj / (a.kF * (double)n2)) : (T)0;
-                const cpx<T> t = st[e];
-                v[e] = {t.y * s, -t.x * s};
+                    for (int e = 0; e < 16; ++e) v[e] = (o == 0) ? sd[e] : st[e];
+                } else {
+                    // u_j(k) = (-i k_j / k^2) theta(k)
+                    constexpr int comp = o - FIRST_U;
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const int kx = signed_pos(l + P * e, N);
+                        const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
+                        const int kj = comp == 0 ? kx : (comp == 1 ? ky : kz);
+                        const T s = n2 > 0 ? (T)((double)kj / (a.kF * (double)n2)) : (T)0;
+                        v[e] = {st[e].y * s, -st[e].x * s};
+                    }
+                }
+                x_inverse_store<T, N>(v, lds, row, tw, l, a.s3 + (size_t)o * a.s3_field + outbase, cd.Ky, nrows);
             }
-        }
-        __syncthreads();  // previous field's read-out is done with LDS
-        fft_row<N, +1, T>(v, row, tw, l);
-        stage_row<N, T>(v, row, l);
-        __syncthreads();
-        cpx<T>* out = a.s3 + (size_t)o * a.s3_field;
-        const int nrows = min(RPB, cd.Ky - ky0);
-        for (int idx = threadIdx.x; idx < N * RPB; idx += RW::THREADS) {
-            const int x = idx / RPB, rr = idx % RPB;
-            if (rr < nrows) out[((size_t)kz * N + x) * cd.Ky + ky0 + rr] = lds[rr * ROWE + lds_pad(x)];
-        }
+        });
     }
 }
 
@@ -375,7 +456,7 @@ struct ShellSlots {
 
 template <typename T, int N>
 __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xshell(ShellSlots<T> a, const cpx<T>* __restrict__ tw,
-                                                                 CubeDims cd) {
+                                                                   CubeDims cd) {
     using RW = Rows<T, N>;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
     __shared__ cpx<T> lds[RPB * ROWE];
@@ -388,7 +469,7 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xshell(ShellSlots<T> 
     const int ky = active ? (kyc <= cd.Kc ? kyc : kyc - cd.Ky) : 0;
     const int slot = blockIdx.y;
     const cpx<T>* cube = a.cube[slot];
-    const size_t cbase = ((size_t)kz * cd.Ky + (active ? kyc : 0)) * cd.Ky;
+    const size_t cbase = ((size_t)kz * cd.Ky + ky0) * cd.Ky;
     cpx<T>* row = lds + r * ROWE;
     cpx<T> v[16];
 #pragma unroll
@@ -399,18 +480,11 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xshell(ShellSlots<T> 
         const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
         const bool in = active && ic >= 0 && n2 >= a.lo[slot] && n2 < a.hi[slot];
         cpx<T> c = {(T)0, (T)0};
-        if (in) c = cube ? cube[cbase + ic] : cpx<T>{(T)1, (T)0};
+        if (in) c = cube ? cube[cbase + (size_t)r * cd.Ky + ic] : cpx<T>{(T)1, (T)0};
         v[e] = c;
     }
-    fft_row<N, +1, T>(v, row, tw, l);
-    stage_row<N, T>(v, row, l);
-    __syncthreads();
-    cpx<T>* out = a.s3 + (size_t)slot * a.s3_field;
-    const int nrows = min(RPB, cd.Ky - ky0);
-    for (int idx = threadIdx.x; idx < N * RPB; idx += RW::THREADS) {
-        const int x = idx / RPB, rr = idx % RPB;
-        if (rr < nrows) out[((size_t)kz * N + x) * cd.Ky + ky0 + rr] = lds[rr * ROWE + lds_pad(x)];
-    }
+    x_inverse_store<T, N>(v, lds, row, tw, l, a.s3 + (size_t)slot * a.s3_field + (size_t)kz * N * cd.Ky + ky0, cd.Ky,
+                          min(RPB, cd.Ky - ky0));
 }
 
 // --------------------------------------------------------------------------
@@ -419,8 +493,8 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xshell(ShellSlots<T> 
 // --------------------------------------------------------------------------
 template <typename T, int N>
 __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_yinv(const cpx<T>* __restrict__ s3, size_t s3_field,
-                                                               cpx<T>* __restrict__ s4, size_t s4_field,
-                                                               const cpx<T>* __restrict__ tw, CubeDims cd) {
+                                                                 cpx<T>* __restrict__ s4, size_t s4_field,
+                                                                 const cpx<T>* __restrict__ tw, CubeDims cd) {
     using RW = Rows<T, N>;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
     __shared__ cpx<T> lds[RPB * ROWE];
@@ -429,53 +503,56 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_yinv(const cpx<T>* __
     const int x = blk / groups, kz0 = (blk % groups) * RPB;
     const int r = threadIdx.x / P, l = threadIdx.x % P;
     const bool active = kz0 + r < cd.Kz;
-    const cpx<T>* in = s3 + (size_t)blockIdx.y * s3_field + ((size_t)(active ? kz0 + r : 0) * N + x) * cd.Ky;
+    const cpx<T>* in = s3 + (size_t)blockIdx.y * s3_field + ((size_t)kz0 * N + x) * cd.Ky;
+    const uint32_t rowoff = (uint32_t)(r * N * cd.Ky);
     cpx<T>* row = lds + r * ROWE;
     cpx<T> v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const int ic = pos_to_compact(l + P * e, cd.Kc, N);
-        v[e] = (active && ic >= 0) ? in[ic] : cpx<T>{(T)0, (T)0};
+        v[e] = (active && ic >= 0) ? ldo(in, rowoff + (uint32_t)ic) : cpx<T>{(T)0, (T)0};
     }
     fft_row<N, +1, T>(v, row, tw, l);
     stage_row<N, T>(v, row, l);
     __syncthreads();
-    cpx<T>* out = s4 + (size_t)blockIdx.y * s4_field;
+    cpx<T>* out = s4 + (size_t)blockIdx.y * s4_field + (size_t)x * N * cd.Kz + kz0;
     const int nrows = min(RPB, cd.Kz - kz0);
     for (int idx = threadIdx.x; idx < N * RPB; idx += RW::THREADS) {
         const int y = idx / RPB, rr = idx % RPB;
-        if (rr < nrows) out[((size_t)x * N + y) * cd.Kz + kz0 + rr] = lds[rr * ROWE + lds_pad(y)];
+        if (rr < nrows) sto(out, (uint32_t)(y * cd.Kz + rr), lds[rr * ROWE + lds_pad(y)]);
     }
 }
 
 // --------------------------------------------------------------------------
-// P5: z pass, inverse to real.  Rows (x, y) of S4 (Kz values).  Two real
-// outputs per complex transform: C(k) = A(k) + i B(k) for k in [0, Kz),
-// C(-k) = A(k)^* + i B(k)^*; then a(z) = Re c(z), b(z) = Im c(z).
-// grid.y = pair; block = RPB consecutive rows.
+// P5: z pass, inverse to real.  Rows (x, y) of S4 (Kz values).  Job j pairs
+// either two fields of the same row (fb[j] >= 0; block = RPB rows) or one
+// field of two rows q and q + RPB (fb[j] < 0; block = 2 RPB rows, and the
+// second half of the grid idles).  grid.y = job.
 // --------------------------------------------------------------------------
 template <typename T>
-struct ZPairs {
-    int fa[3], fb[3];  // S4 field indices (fb < 0: none)
+struct ZJobs {
+    int fa[3], fb[3];  // S4 field indices (fb < 0: one field over two rows)
     T* outa[3];
     T* outb[3];
 };
 
 template <typename T, int N>
 __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zinv(const cpx<T>* __restrict__ s4, size_t s4_field,
-                                                               ZPairs<T> zp, const cpx<T>* __restrict__ tw,
-                                                               CubeDims cd) {
+                                                                 ZJobs<T> zj, const cpx<T>* __restrict__ tw,
+                                                                 CubeDims cd) {
     using RW = Rows<T, N>;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
     __shared__ cpx<T> lds[RPB * ROWE];
-    const int pair = blockIdx.y;
+    const int job = blockIdx.y;
+    const bool tworows = zj.fb[job] < 0;
     const uint32_t nblk = (uint32_t)((size_t)N * N / RPB);
     const uint32_t blk = xcd_block(blockIdx.x, nblk);
+    if (tworows && blk >= nblk / 2) return;  // whole block leaves; the kernel has no block barrier
     const int r = threadIdx.x / P, l = threadIdx.x % P;
-    const size_t q = (size_t)blk * RPB + r;  // row index x N + y
-    const cpx<T>* A = s4 + (size_t)zp.fa[pair] * s4_field + q * cd.Kz;
-    const bool hasb = zp.fb[pair] >= 0;
-    const cpx<T>* B = s4 + (size_t)(hasb ? zp.fb[pair] : 0) * s4_field + q * cd.Kz;
+    const size_t q0 = (size_t)blk * (tworows ? 2 * RPB : RPB);  // first row of the block
+    const cpx<T>* A = s4 + (size_t)zj.fa[job] * s4_field + q0 * cd.Kz;
+    const cpx<T>* B = tworows ? A : s4 + (size_t)zj.fb[job] * s4_field + q0 * cd.Kz;
+    const uint32_t ra = (uint32_t)(r * cd.Kz), rb = (uint32_t)((tworows ? r + RPB : r) * cd.Kz);
     cpx<T>* row = lds + r * ROWE;
     cpx<T> v[16];
 #pragma unroll
@@ -483,25 +560,22 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zinv(const cpx<T>* __
         const int p = l + P * e;
         cpx<T> c = {(T)0, (T)0};
         if (p < cd.Kz) {
-            const cpx<T> av = A[p];
-            const cpx<T> bv = hasb ? B[p] : cpx<T>{(T)0, (T)0};
+            const cpx<T> av = ldo(A, ra + (uint32_t)p), bv = ldo(B, rb + (uint32_t)p);
             c = {av.x - bv.y, av.y + bv.x};
         } else if (p > N - cd.Kz) {
-            const cpx<T> av = A[N - p];
-            const cpx<T> bv = hasb ? B[N - p] : cpx<T>{(T)0, (T)0};
+            const cpx<T> av = ldo(A, ra + (uint32_t)(N - p)), bv = ldo(B, rb + (uint32_t)(N - p));
             c = {av.x + bv.y, bv.x - av.y};
         }
         v[e] = c;
     }
     fft_row<N, +1, T>(v, row, tw, l);
-    T* oa = zp.outa[pair] + q * N;
+    T* oa = zj.outa[job] + q0 * N;
+    T* ob = (tworows ? zj.outa[job] : zj.outb[job]) + q0 * N;
+    const uint32_t wa = (uint32_t)(r * N), wb = (uint32_t)((tworows ? r + RPB : r) * N);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) oa[l + P * e] = v[e].x;
-    if (hasb) {
-        T* ob = zp.outb[pair] + q * N;
+    for (int e = 0; e < 16; ++e) sto(oa, wa + (uint32_t)(l + P * e), v[e].x);
 #pragma unroll
-        for (int e = 0; e < 16; ++e) ob[l + P * e] = v[e].y;
-    }
+    for (int e = 0; e < 16; ++e) sto(ob, wb + (uint32_t)(l + P * e), v[e].y);
 }
 
 }  // namespace gridspt

@@ -45,14 +45,17 @@ def test_power_matches_full_grid_route():
 
 
 def _numpy_gaussian(seed, stream, cell):
-    """Box-Muller on words from numpy's Philox at counter (cell, stream, 0, 0)."""
-    v = cell + (stream << 64) - 1          # numpy steps the counter once before drawing
+    """Box-Muller on words from numpy's Philox at counter (cell // 4, stream, 0, 0):
+    word pair cell % 4 // 2, cosine branch for even cells, sine for odd."""
+    v = (cell >> 2) + (stream << 64) - 1   # numpy steps the counter once before drawing
     v %= 1 << 256
     ctr = np.array([(v >> (64 * i)) & (2 ** 64 - 1) for i in range(4)], dtype=np.uint64)
-    w = np.random.Philox(counter=ctr, key=np.array([seed, 0], dtype=np.uint64)).random_raw(2)
-    u1 = ((int(w[0]) >> 11) + 0.5) * 2.0 ** -53
-    u2 = ((int(w[1]) >> 11) + 0.5) * 2.0 ** -53
-    return math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2)
+    w = np.random.Philox(counter=ctr, key=np.array([seed, 0], dtype=np.uint64)).random_raw(4)
+    pair, branch = (cell >> 1) & 1, cell & 1
+    u1 = ((int(w[2 * pair]) >> 11) + 0.5) * 2.0 ** -53
+    u2 = ((int(w[2 * pair + 1]) >> 11) + 0.5) * 2.0 ** -53
+    r = math.sqrt(-2.0 * math.log(u1))
+    return r * (math.sin(2.0 * math.pi * u2) if branch else math.cos(2.0 * math.pi * u2))
 
 
 def test_linear_field_noise_and_amplitude():
