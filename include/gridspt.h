@@ -190,7 +190,8 @@ int64_t gridspt_bispectrum_workspace_bytes(const gridspt_grid* g, int32_t ntri, 
  *   bk = L^6 T / ntriangles.
  * T counts triangles that close modulo N, which equals exact closure
  * (k1 + k2 + k3 = 0) when every shell lies below N/3.
- * tri_bins: host 3 * ntri bin indices; terms: host 4 * nterms (fa, fb, fc, tri);
+ * tri_bins: host 3 * ntri bin indices (ntri <= 4096); terms: host 4 * nterms
+ * (fa, fb, fc, tri), nterms <= 16384;
  * edge_n2 as for gridspt_power.  bk: device [nterms]; ntriangles: device
  * [ntri].  Sums are FP64 in a fixed order. */
 int gridspt_bispectrum(gridspt_ctx* ctx, const gridspt_grid* g, int32_t nfields, const void* const* fields_k,

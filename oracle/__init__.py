@@ -74,6 +74,11 @@ def _load():
                                       c_i64p, c_dp, c_dp]
         lib.or_bispectrum.restype = ctypes.c_int
         lib.or_sum_orders.argtypes = [ctypes.c_long, ctypes.c_int, c_dp, c_dp, c_dp]
+        lib.or_group_gaussians.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, c_dp]
+        lib.or_linear_modes.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64,
+                                        ctypes.c_uint64, ctypes.c_int, c_dp, c_dp]
+        lib.or_linear_modes.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -137,9 +142,26 @@ def growth(om: float, ol: float, z: float) -> float:
     return _load().or_growth(float(om), float(ol), float(z))
 
 
+def group_gaussians(seed: int, stream: int, q: int) -> np.ndarray:
+    out = np.zeros(4)
+    _load().or_group_gaussians(seed, stream, q, _ptr(out))
+    return out
+
+
 # --------------------------------------------------------------------------
 # hot path
 # --------------------------------------------------------------------------
+
+def linear_modes(n: int, box: float, amp: float, ns: float, gamma: float, growth_d: float, n2max1: int,
+                 seed: int, modes, stream: int = 0) -> np.ndarray:
+    """The linear field's spectrum at single signed modes by the direct DFT
+    sum over all n^3 noise cells (no FFT); for sampling large grids."""
+    m = np.ascontiguousarray(np.asarray(modes, dtype=np.int32).reshape(-1))
+    out = np.zeros(m.size // 3, dtype=np.complex128)
+    _load().or_linear_modes(n, box, amp, ns, gamma, growth_d, int(n2max1), int(seed), int(stream),
+                            m.size // 3, _ptr(m), _ptr(out))
+    return out
+
 
 def linear_field(n: int, box: float, amp: float, ns: float, gamma: float, growth_d: float,
                  n2max1: int, seed: int, stream: int = 0) -> np.ndarray:
@@ -258,3 +280,6 @@ def linear_edges(nbins: int, kmax_num: int, kmax_den: int, n2max: int):
         e.append(-(-num // den))
     e.append(min(kmax_num * kmax_num // (kmax_den * kmax_den) + 1, n2max + 1))
     return np.asarray(e, dtype=np.int64)
+
+
+from .sparse import sparse_orders  # noqa: E402  (pure-Python Fourier-space recursion)

@@ -227,22 +227,31 @@ void or_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* Unit Gaussian for cell `cell` of realisation `stream`.  Cells come in
- * groups of four: group q = cell / 4 draws Philox(counter = (q, stream, 0, 0),
- * key = (seed, 0)); word pairs (w0, w1) and (w2, w3) become uniforms in
- * (0, 1) with 53 random bits, and Box-Muller turns each pair into two
- * Gaussians, cosine branch first.  Cell 4q + r takes pair r / 2, branch r % 2. */
-double or_unit_gaussian(uint64_t seed, uint64_t stream, uint64_t cell)
+/* Unit Gaussians of the four cells 4q .. 4q+3 of realisation `stream`:
+ * Philox(counter = (q, stream, 0, 0), key = (seed, 0)); word pairs (w0, w1)
+ * and (w2, w3) become uniforms in (0, 1) with 53 random bits, and Box-Muller
+ * turns each pair into two Gaussians, cosine branch first.  Cell 4q + r
+ * takes pair r / 2, branch r % 2. */
+void or_group_gaussians(uint64_t seed, uint64_t stream, uint64_t q, double g[4])
 {
-    const uint64_t ctr[4] = {cell >> 2, stream, 0, 0};
+    const uint64_t ctr[4] = {q, stream, 0, 0};
     const uint64_t key[2] = {seed, 0};
     uint64_t w[4];
     or_philox4x64_10(ctr, key, w);
-    const int pair = (int)((cell >> 1) & 1), branch = (int)(cell & 1);
-    const double u1 = ((double)(w[2 * pair] >> 11) + 0.5) * 0x1p-53;
-    const double u2 = ((double)(w[2 * pair + 1] >> 11) + 0.5) * 0x1p-53;
-    const double r = sqrt(-2.0 * log(u1));
-    return branch ? r * sin(TWO_PI * u2) : r * cos(TWO_PI * u2);
+    for (int pair = 0; pair < 2; ++pair) {
+        const double u1 = ((double)(w[2 * pair] >> 11) + 0.5) * 0x1p-53;
+        const double u2 = ((double)(w[2 * pair + 1] >> 11) + 0.5) * 0x1p-53;
+        const double r = sqrt(-2.0 * log(u1));
+        g[2 * pair] = r * cos(TWO_PI * u2);
+        g[2 * pair + 1] = r * sin(TWO_PI * u2);
+    }
+}
+
+double or_unit_gaussian(uint64_t seed, uint64_t stream, uint64_t cell)
+{
+    double g[4];
+    or_group_gaussians(seed, stream, cell >> 2, g);
+    return g[cell & 3];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -351,6 +360,64 @@ int or_linear_field(int N, double L, double A, double ns, double gamma,
     }
     inverse_real(F, delta1, tmp, N);
     free(F); free(tmp); free(w);
+    return 0;
+}
+
+/* The same field evaluated at single modes, straight from the definition:
+ * out[j] = W1(k_j) sqrt(P0(k_j) N^3 / L^3) D N^-3 sum_x w(x) e^{-i k_j.x}
+ * for signed integer modes k_j = modes[3j..3j+2], one pass over all N^3 cells
+ * (compensated summation), without any FFT.  For sampling very large grids. */
+int or_linear_modes(int N, double L, double A, double ns, double gamma, double growth, int64_t n2max1,
+                    uint64_t seed, uint64_t stream, int nm, const int *modes, cplx *out)
+{
+    const long M = (long)N * N * N;
+    cplx *tab = malloc(sizeof(cplx) * (size_t)nm * 3 * N);      /* e^{-2 pi i m x / N} per axis */
+    for (int j = 0; j < nm; ++j)
+        for (int a = 0; a < 3; ++a)
+            for (int x = 0; x < N; ++x) {
+                const long e = ((long)modes[3 * j + a] * x) % N;
+                const double ang = -TWO_PI * (double)(e < 0 ? e + N : e) / (double)N;
+                tab[((long)j * 3 + a) * N + x] = cos(ang) + I * sin(ang);
+            }
+    cplx *sum = calloc((size_t)nm, sizeof(cplx)), *cmp = calloc((size_t)nm, sizeof(cplx));
+#pragma omp parallel
+    {
+        cplx *ls = calloc((size_t)nm, sizeof(cplx)), *lc = calloc((size_t)nm, sizeof(cplx));
+#pragma omp for schedule(static)
+        for (long q = 0; q < M / 4; ++q) {
+            double g[4];
+            or_group_gaussians(seed, stream, (uint64_t)q, g);
+            for (int r = 0; r < 4; ++r) {
+                const long c = 4 * q + r;
+                const int ix = (int)(c / ((long)N * N)), iy = (int)((c / N) % N), iz = (int)(c % N);
+                for (int j = 0; j < nm; ++j) {
+                    const cplx t = g[r] * tab[((long)j * 3 + 0) * N + ix] * tab[((long)j * 3 + 1) * N + iy] *
+                                   tab[((long)j * 3 + 2) * N + iz];
+                    const cplx y = t - lc[j];          /* Kahan */
+                    const cplx s2 = ls[j] + y;
+                    lc[j] = (s2 - ls[j]) - y;
+                    ls[j] = s2;
+                }
+            }
+        }
+#pragma omp critical
+        for (int j = 0; j < nm; ++j) {
+            const cplx y = ls[j] - cmp[j];
+            const cplx s2 = sum[j] + y;
+            cmp[j] = (s2 - sum[j]) - y;
+            sum[j] = s2;
+        }
+        free(ls); free(lc);
+    }
+    const double kF = TWO_PI / L, vol = (double)M / (L * L * L);
+    for (int j = 0; j < nm; ++j) {
+        const long long a = modes[3 * j], b = modes[3 * j + 1], c = modes[3 * j + 2];
+        const long long n2 = a * a + b * b + c * c;
+        if (n2 == 0 || n2 > n2max1) { out[j] = 0; continue; }
+        const double k = kF * sqrt((double)n2);
+        out[j] = sum[j] / (double)M * sqrt(or_p0(k, A, ns, gamma) * vol) * growth;
+    }
+    free(tab); free(sum); free(cmp);
     return 0;
 }
 

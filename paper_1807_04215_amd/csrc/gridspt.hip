@@ -848,7 +848,7 @@ int gridspt_bispectrum(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, c
     CHECK(check_grid(g));
     if (nfields < 1 || nfields > kMaxFields || ntri < 1 || nterms < 1 || nbins < 1 || nbins > kMaxBins)
         return GRIDSPT_EINVAL;
-    if (ntri > 512 || nterms > 512) return GRIDSPT_EINVAL;
+    if (ntri > 4096 || nterms > 16384) return GRIDSPT_EINVAL;
     for (int t = 0; t < 3 * ntri; ++t)
         if (tri_bins[t] < 0 || tri_bins[t] >= nbins) return GRIDSPT_EINVAL;
     for (int u = 0; u < nterms; ++u) {

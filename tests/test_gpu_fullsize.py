@@ -1,0 +1,232 @@
+"""GPU checks at the full sizes of the benchmark workloads.
+
+1024^3 (the benchmark configuration: L = 2000 Mpc/h, strict 2/3 cut, FP32):
+  - a plane-wave input through all five orders against the sparse Fourier-
+    space oracle, at every excited mode, plus the energy anywhere else and
+    sampled real-space values;
+  - the seeded linear field against the direct-DFT oracle at sampled modes;
+  - bitwise determinism and exact homogeneity of the whole recursion.
+256^3 (L = 1000 Mpc/h, z = 1): every field against the full oracle in FP64 and
+FP32, the 15 delta-delta cross spectra in 64 bins, and the bispectrum of the
+lowest shells against direct triangle enumeration.
+"""
+import gc
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1807_04215_amd as g
+from tests.layouts import cube_from_tensor, half_to_cube, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+NS, GAMMA, SIGMA8 = 0.96, 0.21, 0.8
+
+
+def _free():
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def _plane_field(n, waves, dtype):
+    """sum of A cos(2 pi m.x / N + phi) on the GPU (torch, FP64, slab by slab)"""
+    out = torch.empty((n, n, n), dtype=dtype, device="cuda")
+    j = torch.arange(n, device="cuda", dtype=torch.int64)
+    slab = 32
+    for x0 in range(0, n, slab):
+        xs = j[x0:x0 + slab].view(-1, 1, 1)
+        acc = torch.zeros((xs.shape[0], n, n), dtype=torch.float64, device="cuda")
+        for amp, phase, m in waves:
+            e = (m[0] * xs + m[1] * j.view(1, -1, 1) + m[2] * j.view(1, 1, -1)) % n
+            acc += amp * torch.cos(e.to(torch.float64) * (2 * math.pi / n) + phase)
+        out[x0:x0 + slab] = acc.to(dtype)
+        del acc, e
+    return out
+
+
+def _spectrum_of(waves):
+    spec = {}
+    for amp, phase, m in waves:
+        v = 0.5 * amp * complex(math.cos(phase), math.sin(phase))
+        spec[tuple(m)] = spec.get(tuple(m), 0) + v
+        spec[tuple(-x for x in m)] = spec.get(tuple(-x for x in m), 0) + v.conjugate()
+    return spec
+
+
+def _cube_index(kc, m):
+    """(kz, ky', kx') of signed mode m in the cube, and whether m is stored or its mirror"""
+    a, b, c = m
+    conj = c < 0
+    if conj:
+        a, b, c = -a, -b, -c
+    K = 2 * kc + 1
+    return (c, b % K if b >= 0 else b + K, a if a >= 0 else a + K), conj
+
+
+def _compare_sparse(cube, kc, sparse):
+    """relative L2 error of a GPU cube spectrum against a sparse expectation,
+    counting energy at every mode the expectation leaves empty"""
+    keys = [k for k in sparse if k[2] > 0 or (k[2] == 0)]
+    idx = [_cube_index(kc, k)[0] for k in keys]
+    t = torch.tensor(idx, device="cuda", dtype=torch.int64)
+    vals = cube[t[:, 0], t[:, 1], t[:, 2]].double().cpu().numpy()
+    got = vals[:, 0] + 1j * vals[:, 1]
+    want = np.array([sparse[k] for k in keys])
+    w = np.array([1.0 if k[2] == 0 else 2.0 for k in keys])
+    c = cube.double()
+    e2 = (c[..., 0] ** 2 + c[..., 1] ** 2)
+    total = float(e2[0].sum() + 2.0 * e2[1:].sum())
+    on = float((w * np.abs(got) ** 2).sum())
+    err2 = float((w * np.abs(got - want) ** 2).sum()) + max(total - on, 0.0)
+    ref2 = float((w * np.abs(want) ** 2).sum())
+    return math.sqrt(err2 / ref2)
+
+
+def test_c3_plane_waves_all_orders_fp32():
+    n, box, nmax = 1024, 2000.0, 5
+    cut = g.cut_n2max(n, box)
+    grid = g.Grid(n, box, g.cube_kc(cut), g.F32)
+    waves = [(0.08, 0.3, (13, -7, 2)), (0.06, -1.2, (-5, 21, 9)), (0.07, 2.1, (30, 4, -17)),
+             (0.05, 0.9, (2, -3, 44)), (0.04, -2.5, (-95, 60, 31))]       # the last one makes high orders hit the cut
+    d1 = _plane_field(n, waves, torch.float32)
+    ctx = g.Context()
+    out = g.orders(ctx, grid, nmax, cut, cut, d1)
+    ctx.sync()
+    sd, st = oracle.sparse_orders(_spectrum_of(waves), n, nmax, cut, cut)
+    rng = np.random.default_rng(0)
+    pts = rng.integers(0, n, size=(24, 3))
+    for o in range(nmax):
+        ed = _compare_sparse(out.delta_k[o], grid.kc, sd[o])
+        et = _compare_sparse(out.theta_k[o], grid.kc, st[o])
+        assert ed < 1e-5 and et < 1e-5, (o + 1, ed, et)
+        # sampled real-space values: delta_n(x) = sum_k delta_n(k) e^{ik.x}
+        modes = np.array(list(sd[o].keys()), dtype=np.float64)
+        amps = np.array(list(sd[o].values()))
+        rms = math.sqrt(float((np.abs(amps) ** 2).sum()))
+        want = np.real(np.exp(2j * np.pi * (pts @ modes.T) / n) @ amps)
+        t = torch.tensor(pts, device="cuda")
+        got = out.delta[o][t[:, 0], t[:, 1], t[:, 2]].double().cpu().numpy()
+        assert np.abs(got - want).max() < 2e-5 * rms, o + 1
+    del out, d1, ctx
+    _free()
+
+
+def test_c3_linear_field_sampled_modes():
+    """The benchmark's linear field (seed 3, z = 0) at sampled modes against
+    the oracle's direct DFT over all 1024^3 noise cells."""
+    n, box = 1024, 2000.0
+    cut = g.cut_n2max(n, box)
+    grid = g.Grid(n, box, g.cube_kc(cut), g.F32)
+    amp = g.sigma8_amp(SIGMA8, NS, GAMMA)
+    dz = g.growth(0.279, 0.721, 0.0)
+    ctx = g.Context()
+    d1, d1k = g.linear_field(ctx, grid, g.LinearSpectrum(amp=amp, ns=NS, gamma=GAMMA, growth=dz, n2max=cut,
+                                                         seed=3), spectrum=True)
+    ctx.sync()
+    modes = [(1, 0, 0), (0, 7, -3), (-40, 12, 5), (150, -200, 33), (0, 0, 341), (-197, 197, 196)]
+    want = oracle.linear_modes(n, box, amp, NS, GAMMA, dz, cut, 3, modes)
+    for m, wv in zip(modes, want):
+        (kz, ky, kx), conj = _cube_index(grid.kc, m)
+        v = d1k[kz, ky, kx].double().cpu().numpy()
+        got = complex(v[0], -v[1] if conj else v[1])
+        assert abs(got - wv) <= 1e-4 * abs(wv), (m, got, wv)
+    del d1, d1k, ctx
+    _free()
+
+
+def test_c3_determinism_and_homogeneity_bitwise():
+    n, box, nmax = 1024, 2000.0, 5
+    cut = g.cut_n2max(n, box)
+    grid = g.Grid(n, box, g.cube_kc(cut), g.F32)
+    amp = g.sigma8_amp(SIGMA8, NS, GAMMA)
+    ctx = g.Context()
+    d1 = g.linear_field(ctx, grid, g.LinearSpectrum(amp=amp, n2max=cut, seed=5))
+    a = g.orders(ctx, grid, nmax, cut, cut, d1, spectra=False)
+    b = g.orders(ctx, grid, nmax, cut, cut, d1, spectra=False)
+    ctx.sync()
+    for i in range(nmax):
+        assert torch.equal(a.delta[i], b.delta[i]) and torch.equal(a.theta[i], b.theta[i]), i + 1
+    d1.mul_(2.0)
+    g.orders(ctx, grid, nmax, cut, cut, d1, out=b, spectra=False)
+    ctx.sync()
+    for i in range(nmax):
+        s = 2.0 ** (i + 1)
+        assert torch.equal(b.delta[i], a.delta[i] * s) and torch.equal(b.theta[i], a.theta[i] * s), i + 1
+    del a, b, d1, ctx
+    _free()
+
+
+@pytest.fixture(scope="module")
+def c2_reference():
+    n, box, z, nmax = 256, 1000.0, 1.0, 5
+    cut = oracle.cut_n2max_strict(n)
+    amp = oracle.sigma8_amp(SIGMA8, NS, GAMMA)
+    dz = oracle.growth(0.279, 0.721, z)
+    d1 = oracle.linear_field(n, box, amp, NS, GAMMA, dz, cut, 2)
+    rd, rt, rdk, rtk = oracle.orders(d1, box, nmax, cut, cut, form="D")
+    return dict(n=n, box=box, nmax=nmax, cut=cut, amp=amp, dz=dz, d1=d1, rd=rd, rt=rt, rdk=rdk, rtk=rtk)
+
+
+@pytest.mark.parametrize("dtype", [g.F64, g.F32])
+def test_c2_full_oracle_parity(c2_reference, dtype):
+    R = c2_reference
+    n, box, nmax, cut = R["n"], R["box"], R["nmax"], R["cut"]
+    grid = g.Grid(n, box, g.cube_kc(cut), dtype)
+    tol = 1e-12 if dtype == g.F64 else 1e-5
+    ctx = g.Context()
+    # the seeded linear field itself
+    d1 = g.linear_field(ctx, grid, g.LinearSpectrum(amp=R["amp"], ns=NS, gamma=GAMMA, growth=R["dz"],
+                                                    n2max=cut, seed=2))
+    ctx.sync()
+    assert rel_l2(d1.cpu().numpy(), R["d1"]) < tol
+    # the recursion from the oracle's delta_1 (FP32 runs take it rounded to FP32; the
+    # reference stays the unrounded one: rounding moves delta_n by < n * 6e-8, far
+    # below the FP32 tolerance)
+    rd, rt, rdk, rtk = R["rd"], R["rt"], R["rdk"], R["rtk"]
+    out = g.orders(ctx, grid, nmax, cut, cut, torch.from_numpy(R["d1"]).to("cuda", grid.real_dtype))
+    ctx.sync()
+    errs = []
+    for i in range(nmax):
+        ed = rel_l2(out.delta[i].cpu().numpy(), rd[i])
+        et = rel_l2(out.theta[i].cpu().numpy(), rt[i])
+        errs.append((ed, et))
+        assert ed < tol and et < tol, (i + 1, ed, et)
+    print("C2 %s per-order rel L2 (delta, theta): %s" % ("f64" if dtype == g.F64 else "f32",
+                                                        ["%.2e/%.2e" % e for e in errs]))
+    # 15 delta-delta cross spectra in 64 bins
+    edges = g.linear_edges(64, n, 3, cut)
+    pairs = [(a, b) for a in range(nmax) for b in range(a, nmax)]
+    pk, km, nm = g.power(ctx, grid, out.delta_k, pairs, edges)
+    rpk, rkm, rnm = oracle.power(list(rdk), box, pairs, edges)
+    assert np.array_equal(nm.cpu().numpy(), rnm)
+    diag = {f: oracle.power([rdk[f]], box, [(0, 0)], edges)[0][0] for f in range(nmax)}
+    got = pk.cpu().numpy()
+    for p, (a, b) in enumerate(pairs):
+        e = np.abs(got[p] - rpk[p]) / (np.sqrt(diag[a] * diag[b]) + 1e-300)
+        assert np.all(e[rnm > 0] < 10 * tol), (a, b, e.max())
+    # bispectrum: equilateral (b, b, b) and squeezed (b, b, 0) in 20 bins, tree
+    # and one-loop terms; the two lowest shells against direct enumeration
+    e20 = g.linear_edges(20, n, 3, cut)
+    tris = [(b, b, b) for b in range(20)] + [(b, b, 0) for b in range(1, 20)]
+    combos = [(0, 0, 1), (0, 1, 0), (1, 0, 0), (0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0),
+              (1, 1, 1), (0, 0, 3), (0, 3, 0), (3, 0, 0)]
+    terms = [c + (t,) for t in range(len(tris)) for c in combos]
+    bk, nt = g.bispectrum(ctx, grid, out.delta_k[:4], tris, terms, e20)
+    ctx.sync()
+    low = [t for t, tr in enumerate(tris) if max(tr) <= 1]
+    lt = [tris[t] for t in low]
+    lterms = [c + (i,) for i in range(len(low)) for c in combos]
+    rbk, rnt = oracle.bispectrum(list(rdk[:4]), box, lt, lterms, e20)
+    gnt = nt.cpu().numpy()
+    gbk = bk.cpu().numpy()
+    for i, t in enumerate(low):
+        assert abs(gnt[t] - rnt[i]) <= (1e-9 if dtype == g.F64 else 1e-5) * max(rnt[i], 1.0)
+        got_t = gbk[t * len(combos):(t + 1) * len(combos)]
+        want_t = rbk[i * len(combos):(i + 1) * len(combos)]
+        assert np.all(np.abs(got_t - want_t) <= (1e-10 if dtype == g.F64 else 1e-4) * np.abs(want_t).max())
+    del out, d1, ctx
+    _free()
