@@ -52,6 +52,92 @@ def cpu_baseline(n_sample: int = 256, box: float = 1000.0, nmax: int = 5):
             "sample": "%d^3 grid, L=%g, linear field + D-form orders 1..%d, FP64, %.1f s" % (n_sample, box, nmax, dt)}
 
 
+def kernel_source_digest() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1807_04215_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kind: str, args):
+    """HBM bytes per launch (GB) of `kind` from the committed rocprofv3 counter
+    summary, if it was taken on this workload and on the current kernel
+    sources; otherwise None."""
+    if args.workload != "c3" or args.dtype != "f32":
+        return None
+    path = os.path.join(ROOT, "profiles", "c3_fp32_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    digest = kernel_source_digest()
+    with open(path) as f:
+        for line in f:
+            if line.startswith("machine-readable: traffic "):
+                _, _, k, nbytes, dg = line.split()
+                if k == kind and dg == digest:
+                    return round(float(nbytes) / 1e9, 3)
+    return None
+
+
+def precision_report(args) -> int:
+    """FP32 path vs FP64 path (linear field + orders 1..nmax from the same
+    seed) on the chosen workload: relative L2 of every delta_n and theta_n,
+    and the FP64 throughput.  FP32 fields wait in host memory while the FP64
+    path runs."""
+    import torch
+
+    import paper_1807_04215_amd as g
+
+    n, box, z, nmax, _, desc = WORKLOADS[args.workload]
+    cut = g.cut_n2max(n, box)
+    dz = g.growth(0.279, 0.721, z)
+    amp = g.sigma8_amp(0.8, 0.96, 0.21)
+    lp = g.LinearSpectrum(amp=amp, ns=0.96, gamma=0.21, growth=dz, n2max=cut, seed=3)
+    host = {}
+    rates = {}
+    for dtype in (g.F32, g.F64):
+        grid = g.Grid(n, box, g.cube_kc(cut), dtype)
+        ctx = g.Context()
+        out = g.alloc_orders(grid, nmax, spectra=False)
+        ctx.workspace(g.workspace_bytes(grid, nmax))
+        for rep in range(2):                       # the second run is timed
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.linear_field(ctx, grid, lp, out=out.delta[0])
+            g.orders(ctx, grid, nmax, cut, cut, out.delta[0], out=out, spectra=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        rates["f32" if dtype == g.F32 else "f64"] = n ** 3 / dt / 1e6
+        if dtype == g.F32:
+            for i in range(nmax):
+                host[("delta", i)] = out.delta[i].cpu()
+                if i > 0:
+                    host[("theta", i)] = out.theta[i].cpu()
+        else:
+            errs = []
+            for i in range(nmax):
+                row = []
+                for kind, t64 in (("delta", out.delta[i]), ("theta", out.theta[i])):
+                    t32 = host[(kind, i)] if (kind, i) in host else host[("delta", 0)]  # theta_1 = delta_1
+                    d = t32.to("cuda", torch.float64)
+                    num = torch.linalg.vector_norm((d - t64).reshape(-1)).item()
+                    den = torch.linalg.vector_norm(t64.reshape(-1)).item()
+                    row.append(num / den)
+                    del d
+                errs.append(row)
+        del out, ctx
+        import gc
+        gc.collect()
+        torch.cuda.empty_cache()
+    res = {"workload": "%s: %s" % (args.workload, desc), "mcells_per_s": {k: round(v, 1) for k, v in rates.items()},
+           "fp32_vs_fp64_rel_l2": {"delta": ["%.3e" % e[0] for e in errs], "theta": ["%.3e" % e[1] for e in errs]},
+           "tolerance": 1e-5}
+    print(json.dumps(res), flush=True)
+    return 0 if all(max(e) <= 1e-5 for e in errs) else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,6 +148,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-spectra", action="store_true", help="skip the spectrum stores and P(k)")
     ap.add_argument("--kernels", action="store_true", help="also print the per-kernel table to stderr")
+    ap.add_argument("--precision", action="store_true",
+                    help="FP32 path against the FP64 path from the same seed: per-order errors and FP64 rate")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="one 4 GiB device-to-device copy (calibrates HBM byte counters), then exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -74,6 +164,17 @@ def main() -> int:
     import paper_1807_04215_amd as g
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        a = torch.empty(1 << 30, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 << 30, "copy_probe_bytes_written": 4 << 30}))
+        return 0
+    if args.precision:
+        return precision_report(args)
     n, box, z, nmax, nbins, desc = WORKLOADS[args.workload]
     dtype = g.F64 if args.dtype == "f64" else g.F32
     cut = g.cut_n2max(n, box)
@@ -141,7 +242,9 @@ def main() -> int:
                                                                  ", 15 P_mn pairs in %d bins" % nbins if spectra else ""),
                    "n": n, "box": box, "z": z, "nmax": nmax, "kc": grid.kc},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom, args), "launch_ms": round(d["ms"] / d["launches"], 3),
+                     "algorithmic_gb_per_launch": round(d["bytes"] / d["launches"] / 1e9, 3)},
         "fft_hbm_gbs": round(fft_b / (fft_ms / 1000.0) / 1e9, 1) if fft_ms > 0 else None,
         "kernel_ms_per_step": round(kern_ms / args.steps, 3),
         "path_gbs": round(sum(v["bytes"] for v in prof.values()) / (kern_ms / 1000.0) / 1e9, 1),
