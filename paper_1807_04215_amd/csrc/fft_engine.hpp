@@ -140,14 +140,66 @@ struct Plan {
     static_assert(N >= 16 && N <= 1024 && (N & (N - 1)) == 0, "N must be a power of two in [16, 1024]");
 };
 
+// Twiddles of the Stockham passes after the first: pass (R, p) multiplies
+// input j of butterfly b by w_{pR}^{j k}, k = b mod p, with w_M = exp(-2 pi i / M).
+//   LDS form (FP32): one table per pass laid out [j - 1][k], so the lanes of a
+//     wavefront (consecutive k) read consecutive words; about N entries.
+//   global form (FP64): the full table w_N^m, m < N, read through the cache.
+template <int N>
+struct TwLayout {
+    static constexpr int R2 = Plan<N>::R2, R3 = Plan<N>::R3;
+    static constexpr int PASS3 = R2 > 1 ? (R2 - 1) * 16 : 0;  // start of the third pass's table
+    static constexpr int SIZE = PASS3 + (R3 > 1 ? (R3 - 1) * 16 * R2 : 0);
+    static constexpr int ALLOC = SIZE > 0 ? SIZE : 1;
+};
+
+template <typename T, int N, bool LDS>
+struct Twiddles {
+    const cpx<T>* t;
+    template <int R, int PSTRIDE>
+    __device__ __forceinline__ cpx<T> get(int j, int k) const {
+        if constexpr (LDS) {
+            constexpr int base = PSTRIDE == 16 ? 0 : TwLayout<N>::PASS3;
+            return t[base + (j - 1) * PSTRIDE + k];
+        } else {
+            return t[j * k * (N / (PSTRIDE * R))];
+        }
+    }
+};
+
+// Only FP32 may keep the per-pass tables in LDS: FP64 tables would cost a
+// block per CU of LDS, so FP64 always reads the global table.  Each pass
+// kernel further decides whether its own LDS traffic leaves room for them.
+template <typename T>
+constexpr bool kLdsTwiddles = sizeof(T) == 4;
+
+// Fill the LDS tables from the global full table w_N^m; the caller
+// synchronises the block before the first transform.
+template <int N, typename T>
+__device__ __forceinline__ void load_twiddles(cpx<T>* lds_tw, const cpx<T>* __restrict__ tw) {
+    using TL = TwLayout<N>;
+    {
+        for (int i = threadIdx.x; i < TL::SIZE; i += blockDim.x) {
+            int m;
+            if (i < TL::PASS3) {
+                const int j = i / 16 + 1, k = i % 16;             // pass 2: p = 16, R = R2
+                m = j * k * (N / (16 * TL::R2));
+            } else {
+                const int q = i - TL::PASS3, j = q / (16 * TL::R2) + 1, k = q % (16 * TL::R2);
+                m = j * k * (N / (16 * TL::R2 * TL::R3));      // pass 3: p = 16 R2, R = R3
+            }
+            lds_tw[i] = tw[m];
+        }
+    }
+}
+
 // Stockham pass of radix R over a row held in LDS (not the first pass).
 // Lane l handles butterflies b = l + P t, t < 16/R; butterfly b reads points
 // b + j N/R, twiddles input j by w_{pR}^{j (b mod p)}, and writes its outputs
 // to (b - k) R + k + j p, or, on the last pass, keeps them in registers in
 // canonical order (register t + j 16/R holds point l + P (t + j 16/R)).
-template <int N, int R, int PSTRIDE, bool LAST, int DIR, typename T>
-__device__ __forceinline__ void stockham_pass(cpx<T> (&x)[16], cpx<T>* row, const cpx<T>* __restrict__ tw,
-                                              int l) {
+template <int N, int R, int PSTRIDE, bool LAST, int DIR, typename T, bool LT>
+__device__ __forceinline__ void stockham_pass(cpx<T> (&x)[16], cpx<T>* row, Twiddles<T, N, LT> tw, int l) {
     constexpr int P = N / 16;
     constexpr int NB = 16 / R;
     cpx<T> y[16];
@@ -165,7 +217,7 @@ __device__ __forceinline__ void stockham_pass(cpx<T> (&x)[16], cpx<T>* row, cons
         // w_{pR}^{jk} = w_N^{jk N/(pR)} from the forward table; conjugate for DIR > 0
 #pragma unroll
         for (int j = 1; j < R; ++j) {
-            cpx<T> w = tw[j * k * (N / (PSTRIDE * R))];
+            cpx<T> w = tw.template get<R, PSTRIDE>(j, k);
             if (DIR > 0) w.y = -w.y;
             y[t * R + j] = cmul(y[t * R + j], w);
         }
@@ -190,9 +242,9 @@ __device__ __forceinline__ void stockham_pass(cpx<T> (&x)[16], cpx<T>* row, cons
 
 // Transform one row held in canonical registers, in place (unnormalised).
 // `row` is this row's LDS buffer (lds_row_elems(N) elements), `tw` the
-// forward table w_N^m = exp(-2 pi i m / N), m < N, and l the lane in the team.
-template <int N, int DIR, typename T>
-__device__ __forceinline__ void fft_row(cpx<T> (&x)[16], cpx<T>* row, const cpx<T>* __restrict__ tw, int l) {
+// twiddle source (see Twiddles), and l the lane in the team.
+template <int N, int DIR, typename T, bool LT>
+__device__ __forceinline__ void fft_row(cpx<T> (&x)[16], cpx<T>* row, Twiddles<T, N, LT> tw, int l) {
     using PL = Plan<N>;
     Dft<16, DIR, T>::run(x);  // pass 1: butterfly b = l over points l + P j, no twiddles
     if constexpr (N == 16) {
@@ -203,10 +255,10 @@ __device__ __forceinline__ void fft_row(cpx<T> (&x)[16], cpx<T>* row, const cpx<
         for (int j = 0; j < 16; ++j) row[lds_pad(16 * l + j)] = x[j];
         wave_sync();
         if constexpr (PL::R3 == 1) {
-            stockham_pass<N, PL::R2, 16, true, DIR, T>(x, row, tw, l);
+            stockham_pass<N, PL::R2, 16, true, DIR, T, LT>(x, row, tw, l);
         } else {
-            stockham_pass<N, PL::R2, 16, false, DIR, T>(x, row, tw, l);
-            stockham_pass<N, PL::R3, 16 * PL::R2, true, DIR, T>(x, row, tw, l);
+            stockham_pass<N, PL::R2, 16, false, DIR, T, LT>(x, row, tw, l);
+            stockham_pass<N, PL::R3, 16 * PL::R2, true, DIR, T, LT>(x, row, tw, l);
         }
     }
 }

@@ -175,6 +175,12 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zfwd(const T* __restr
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
     constexpr int YB = (SRC == 2) ? RPB : 2 * RPB;  // rows of y per block
     __shared__ cpx<T> lds[RPB * ROWE];
+    // twiddles in LDS for FP32 (this pass's LDS traffic is light), else from the cache
+    constexpr bool LT = kLdsTwiddles<T> && true;
+    __shared__ cpx<T> twl[LT ? TwLayout<N>::ALLOC : 1];
+    if constexpr (LT) load_twiddles<N, T>(twl, tw);
+    __syncthreads();
+    const Twiddles<T, N, LT> tws{LT ? twl : tw};
     constexpr uint32_t groups = N / YB;
     const uint32_t blk = xcd_block(blockIdx.x, N * groups);
     const int x = blk / groups, y0 = (blk % groups) * YB;
@@ -227,7 +233,7 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zfwd(const T* __restr
 #pragma unroll
         for (int e = 0; e < 16; ++e) v[e] = pk == 0 ? a[e] : b[e];
         if constexpr (pk > 0) __syncthreads();  // previous read-out has finished with LDS
-        fft_row<N, -1, T>(v, row, tw, l);
+        fft_row<N, -1, T>(v, row, tws, l);
         stage_row<N, T>(v, row, l);
         __syncthreads();
         // read-out: S1[kz][x][y0 + rr] for every kept kz
@@ -259,6 +265,12 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_yfwd(const cpx<T>* __
     using RW = Rows<T, N>;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
     __shared__ cpx<T> lds[RPB * ROWE];
+    // twiddles in LDS for FP32 (this pass's LDS traffic is light), else from the cache
+    constexpr bool LT = kLdsTwiddles<T> && true;
+    __shared__ cpx<T> twl[LT ? TwLayout<N>::ALLOC : 1];
+    if constexpr (LT) load_twiddles<N, T>(twl, tw);
+    __syncthreads();
+    const Twiddles<T, N, LT> tws{LT ? twl : tw};
     constexpr uint32_t groups = N / RPB;
     const uint32_t blk = xcd_block(blockIdx.x, cd.Kz * groups);
     const int kz = blk / groups, x0 = (blk % groups) * RPB;
@@ -268,7 +280,7 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_yfwd(const cpx<T>* __
     cpx<T> v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = ldo(in, (uint32_t)(r * N + l + P * e));
-    fft_row<N, -1, T>(v, row, tw, l);
+    fft_row<N, -1, T>(v, row, tws, l);
     stage_row<N, T>(v, row, l);
     __syncthreads();
     cpx<T>* out = s2 + (size_t)blockIdx.y * s2_field + (size_t)kz * cd.Ky * N + x0;
@@ -300,10 +312,9 @@ struct XArgs {
 };
 
 // inverse x transform of one output row and its transposed store into S3
-template <typename T, int N>
-__device__ __forceinline__ void x_inverse_store(cpx<T> (&v)[16], cpx<T>* lds, cpx<T>* row,
-                                                const cpx<T>* __restrict__ tw, int l, cpx<T>* out, int Ky,
-                                                int nrows) {
+template <typename T, int N, bool LT>
+__device__ __forceinline__ void x_inverse_store(cpx<T> (&v)[16], cpx<T>* lds, cpx<T>* row, Twiddles<T, N, LT> tw,
+                                                int l, cpx<T>* out, int Ky, int nrows) {
     using RW = Rows<T, N>;
     constexpr int RPB = RW::RPB, ROWE = RW::ROWE;
     __syncthreads();  // the previous read-out is done with LDS
@@ -322,6 +333,12 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xfused(XArgs<T> a, co
     using RW = Rows<T, N>;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
     __shared__ cpx<T> lds[RPB * ROWE];
+    // twiddles from the cache: this pass's LDS is busy with exchanges and staging
+    constexpr bool LT = kLdsTwiddles<T> && false;
+    __shared__ cpx<T> twl[LT ? TwLayout<N>::ALLOC : 1];
+    if constexpr (LT) load_twiddles<N, T>(twl, tw);
+    __syncthreads();
+    const Twiddles<T, N, LT> tws{LT ? twl : tw};
     const uint32_t groups = (cd.Ky + RPB - 1) / RPB;
     const uint32_t blk = xcd_block(blockIdx.x, cd.Kz * groups);
     const int kz = blk / groups, ky0 = (blk % groups) * RPB;
@@ -344,7 +361,7 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xfused(XArgs<T> a, co
         const cpx<T>* in = a.s2 + (size_t)f * a.s2_field + inbase;
 #pragma unroll
         for (int e = 0; e < 16; ++e) v[e] = active ? ldo(in, (uint32_t)(r * N + l + P * e)) : cpx<T>{(T)0, (T)0};
-        fft_row<N, -1, T>(v, row, tw, l);
+        fft_row<N, -1, T>(v, row, tws, l);
         if constexpr (MODE == XM_ORDER) {
             if constexpr (f < 3) {
                 // S_delta += i k_f V_f(k)  (kF and N^-3 applied below)
@@ -435,7 +452,7 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xfused(XArgs<T> a, co
                         v[e] = {st[e].y * s, -st[e].x * s};
                     }
                 }
-                x_inverse_store<T, N>(v, lds, row, tw, l, a.s3 + (size_t)o * a.s3_field + outbase, cd.Ky, nrows);
+                x_inverse_store<T, N, LT>(v, lds, row, tws, l, a.s3 + (size_t)o * a.s3_field + outbase, cd.Ky, nrows);
             }
         });
     }
@@ -460,6 +477,12 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xshell(ShellSlots<T> 
     using RW = Rows<T, N>;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
     __shared__ cpx<T> lds[RPB * ROWE];
+    // twiddles from the cache: this pass's LDS is busy with exchanges and staging
+    constexpr bool LT = kLdsTwiddles<T> && false;
+    __shared__ cpx<T> twl[LT ? TwLayout<N>::ALLOC : 1];
+    if constexpr (LT) load_twiddles<N, T>(twl, tw);
+    __syncthreads();
+    const Twiddles<T, N, LT> tws{LT ? twl : tw};
     const uint32_t groups = (cd.Ky + RPB - 1) / RPB;
     const uint32_t blk = xcd_block(blockIdx.x, cd.Kz * groups);
     const int kz = blk / groups, ky0 = (blk % groups) * RPB;
@@ -483,7 +506,7 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xshell(ShellSlots<T> 
         if (in) c = cube ? cube[cbase + (size_t)r * cd.Ky + ic] : cpx<T>{(T)1, (T)0};
         v[e] = c;
     }
-    x_inverse_store<T, N>(v, lds, row, tw, l, a.s3 + (size_t)slot * a.s3_field + (size_t)kz * N * cd.Ky + ky0, cd.Ky,
+    x_inverse_store<T, N, LT>(v, lds, row, tws, l, a.s3 + (size_t)slot * a.s3_field + (size_t)kz * N * cd.Ky + ky0, cd.Ky,
                           min(RPB, cd.Ky - ky0));
 }
 
@@ -498,6 +521,12 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_yinv(const cpx<T>* __
     using RW = Rows<T, N>;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
     __shared__ cpx<T> lds[RPB * ROWE];
+    // twiddles from the cache: this pass's LDS is busy with exchanges and staging
+    constexpr bool LT = kLdsTwiddles<T> && false;
+    __shared__ cpx<T> twl[LT ? TwLayout<N>::ALLOC : 1];
+    if constexpr (LT) load_twiddles<N, T>(twl, tw);
+    __syncthreads();
+    const Twiddles<T, N, LT> tws{LT ? twl : tw};
     const uint32_t groups = (cd.Kz + RPB - 1) / RPB;
     const uint32_t blk = xcd_block(blockIdx.x, N * groups);
     const int x = blk / groups, kz0 = (blk % groups) * RPB;
@@ -512,7 +541,7 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_yinv(const cpx<T>* __
         const int ic = pos_to_compact(l + P * e, cd.Kc, N);
         v[e] = (active && ic >= 0) ? ldo(in, rowoff + (uint32_t)ic) : cpx<T>{(T)0, (T)0};
     }
-    fft_row<N, +1, T>(v, row, tw, l);
+    fft_row<N, +1, T>(v, row, tws, l);
     stage_row<N, T>(v, row, l);
     __syncthreads();
     cpx<T>* out = s4 + (size_t)blockIdx.y * s4_field + (size_t)x * N * cd.Kz + kz0;
@@ -543,11 +572,17 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zinv(const cpx<T>* __
     using RW = Rows<T, N>;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
     __shared__ cpx<T> lds[RPB * ROWE];
+    // twiddles in LDS for FP32 (this pass's LDS traffic is light), else from the cache
+    constexpr bool LT = kLdsTwiddles<T> && true;
+    __shared__ cpx<T> twl[LT ? TwLayout<N>::ALLOC : 1];
+    if constexpr (LT) load_twiddles<N, T>(twl, tw);
+    __syncthreads();
+    const Twiddles<T, N, LT> tws{LT ? twl : tw};
     const int job = blockIdx.y;
     const bool tworows = zj.fb[job] < 0;
     const uint32_t nblk = (uint32_t)((size_t)N * N / RPB);
     const uint32_t blk = xcd_block(blockIdx.x, nblk);
-    if (tworows && blk >= nblk / 2) return;  // whole block leaves; the kernel has no block barrier
+    if (tworows && blk >= nblk / 2) return;  // whole block leaves; no block barrier follows
     const int r = threadIdx.x / P, l = threadIdx.x % P;
     const size_t q0 = (size_t)blk * (tworows ? 2 * RPB : RPB);  // first row of the block
     const cpx<T>* A = s4 + (size_t)zj.fa[job] * s4_field + q0 * cd.Kz;
@@ -568,7 +603,7 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zinv(const cpx<T>* __
         }
         v[e] = c;
     }
-    fft_row<N, +1, T>(v, row, tw, l);
+    fft_row<N, +1, T>(v, row, tws, l);
     T* oa = zj.outa[job] + q0 * N;
     T* ob = (tworows ? zj.outa[job] : zj.outb[job]) + q0 * N;
     const uint32_t wa = (uint32_t)(r * N), wb = (uint32_t)((tworows ? r + RPB : r) * N);
