@@ -263,6 +263,84 @@ __device__ __forceinline__ void fft_row(cpx<T> (&x)[16], cpx<T>* row, Twiddles<T
     }
 }
 
+// ---------------------------------------------------------------------------
+// Split-exchange variant: the same Stockham passes, but every exchange moves
+// the real parts and then the imaginary parts through a real-valued row
+// buffer (lds_row_elems(N) elements of T), halving the LDS a row needs.
+// ---------------------------------------------------------------------------
+
+// Move values from register array `a` (a[i] at row position pa(i)) to
+// register array `b` (b[i] from row position pb(i)), two rounds through `row`.
+template <int NA, int NB, typename T, typename FA, typename FB>
+__device__ __forceinline__ void exchange_split(const cpx<T> (&a)[NA], cpx<T> (&b)[NB], T* row, FA pa, FB pb) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) row[lds_pad(pa(i))] = a[i].x;
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) b[i].x = row[lds_pad(pb(i))];
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < NA; ++i) row[lds_pad(pa(i))] = a[i].y;
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < NB; ++i) b[i].y = row[lds_pad(pb(i))];
+    wave_sync();
+}
+
+// Stockham pass of radix R on values already gathered into y (butterfly
+// t of this lane holds inputs y[t R + j] = points b + j N/R, b = l + P t).
+template <int N, int R, int PSTRIDE, int DIR, typename T, bool LT>
+__device__ __forceinline__ void stockham_compute(cpx<T> (&y)[16], Twiddles<T, N, LT> tw, int l) {
+    constexpr int P = N / 16;
+    constexpr int NB = 16 / R;
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+        const int k = (l + P * t) & (PSTRIDE - 1);
+#pragma unroll
+        for (int j = 1; j < R; ++j) {
+            cpx<T> w = tw.template get<R, PSTRIDE>(j, k);
+            if (DIR > 0) w.y = -w.y;
+            y[t * R + j] = cmul(y[t * R + j], w);
+        }
+        Dft<R, DIR, T>::run(&y[t * R]);
+    }
+}
+
+template <int N, int DIR, typename T, bool LT>
+__device__ __forceinline__ void fft_row_split(cpx<T> (&x)[16], T* row, Twiddles<T, N, LT> tw, int l) {
+    using PL = Plan<N>;
+    constexpr int P = N / 16;
+    Dft<16, DIR, T>::run(x);  // pass 1: outputs at points 16 l + j
+    if constexpr (N > 16) {
+        constexpr int R2 = PL::R2, NB2 = 16 / R2;
+        cpx<T> y[16];
+        exchange_split<16, 16, T>(x, y, row, [&](int j) { return 16 * l + j; },
+                                  [&](int i) { return (l + P * (i / R2)) + (i % R2) * (N / R2); });
+        stockham_compute<N, R2, 16, DIR, T, LT>(y, tw, l);
+        if constexpr (PL::R3 == 1) {
+#pragma unroll
+            for (int t = 0; t < NB2; ++t)
+#pragma unroll
+                for (int j = 0; j < R2; ++j) x[t + j * NB2] = y[t * R2 + j];
+        } else {
+            constexpr int R3 = PL::R3, NB3 = 16 / R3, PS3 = 16 * R2;
+            cpx<T> z[16];
+            exchange_split<16, 16, T>(
+                y, z, row,
+                [&](int i) {
+                    const int b = l + P * (i / R2), k = b & 15;
+                    return (b - k) * R2 + k + (i % R2) * 16;
+                },
+                [&](int i) { return (l + P * (i / R3)) + (i % R3) * (N / R3); });
+            stockham_compute<N, R3, PS3, DIR, T, LT>(z, tw, l);
+#pragma unroll
+            for (int t = 0; t < NB3; ++t)
+#pragma unroll
+                for (int j = 0; j < R3; ++j) x[t + j * NB3] = z[t * R3 + j];
+        }
+    }
+}
+
 // Block-index remap so that consecutive logical blocks (which write adjacent
 // pieces of the same cache lines) run on the same XCD: the hardware deals
 // blocks round-robin over 8 XCDs.

@@ -121,6 +121,35 @@ __device__ __forceinline__ void stage_row(const cpx<T> (&v)[16], cpx<T>* row, in
     for (int e = 0; e < 16; ++e) row[lds_pad(l + P * e)] = v[e];
 }
 
+// Transposed store of the block's rows through real-valued LDS rows (split
+// exchange): output item idx < count is (o, rr) = (idx / RPB, idx % RPB) and
+// takes position pos(o) of row rr; store(o, rr, value) writes it.  Real parts
+// travel first and wait in registers (at most N / P = 16 items per thread).
+template <int N, typename T, typename PosF, typename StoreF>
+__device__ __forceinline__ void transpose_out_split(const cpx<T> (&v)[16], const T* lds, T* row, int l, int count,
+                                                    PosF pos, StoreF store) {
+    using RW = Rows<T, N>;
+    constexpr int RPB = RW::RPB, ROWE = RW::ROWE, P = RW::P;
+    T re[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) row[lds_pad(l + P * e)] = v[e].x;
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int idx = threadIdx.x + RW::THREADS * it;
+        if (idx < count) re[it] = lds[(idx % RPB) * ROWE + lds_pad(pos(idx / RPB))];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) row[lds_pad(l + P * e)] = v[e].y;
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int idx = threadIdx.x + RW::THREADS * it;
+        if (idx < count) store(idx / RPB, idx % RPB, cpx<T>{re[it], lds[(idx % RPB) * ROWE + lds_pad(pos(idx / RPB))]});
+    }
+}
+
 // unpack the transform C of c = a + i b at mode k (m = C(-k)):
 // which = 0 gives A(k), which = 1 gives B(k)
 template <typename T>
@@ -264,7 +293,7 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_yfwd(const cpx<T>* __
                                                                  const cpx<T>* __restrict__ tw, CubeDims cd) {
     using RW = Rows<T, N>;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
-    __shared__ cpx<T> lds[RPB * ROWE];
+    __shared__ T lds[RPB * ROWE];  // real-valued rows (split exchange)
     // twiddles in LDS for FP32 (this pass's LDS traffic is light), else from the cache
     constexpr bool LT = kLdsTwiddles<T> && true;
     __shared__ cpx<T> twl[LT ? TwLayout<N>::ALLOC : 1];
@@ -276,18 +305,15 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_yfwd(const cpx<T>* __
     const int kz = blk / groups, x0 = (blk % groups) * RPB;
     const int r = threadIdx.x / P, l = threadIdx.x % P;
     const cpx<T>* in = s1 + (size_t)blockIdx.y * s1_field + ((size_t)kz * N + x0) * N;
-    cpx<T>* row = lds + r * ROWE;
+    T* row = lds + r * ROWE;
     cpx<T> v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) v[e] = ldo(in, (uint32_t)(r * N + l + P * e));
-    fft_row<N, -1, T>(v, row, tws, l);
-    stage_row<N, T>(v, row, l);
-    __syncthreads();
+    fft_row_split<N, -1, T>(v, row, tws, l);
     cpx<T>* out = s2 + (size_t)blockIdx.y * s2_field + (size_t)kz * cd.Ky * N + x0;
-    for (int idx = threadIdx.x; idx < cd.Ky * RPB; idx += RW::THREADS) {
-        const int ky = idx / RPB, rr = idx % RPB;
-        sto(out, (uint32_t)(ky * N + rr), lds[rr * ROWE + lds_pad(compact_to_pos(ky, cd.Kc, N))]);
-    }
+    transpose_out_split<N, T>(
+        v, lds, row, l, cd.Ky * RPB, [&](int ky) { return compact_to_pos(ky, cd.Kc, N); },
+        [&](int ky, int rr, cpx<T> val) { sto(out, (uint32_t)(ky * N + rr), val); });
 }
 
 // --------------------------------------------------------------------------
@@ -520,7 +546,7 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_yinv(const cpx<T>* __
                                                                  const cpx<T>* __restrict__ tw, CubeDims cd) {
     using RW = Rows<T, N>;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
-    __shared__ cpx<T> lds[RPB * ROWE];
+    __shared__ T lds[RPB * ROWE];  // real-valued rows (split exchange)
     // twiddles from the cache: this pass's LDS is busy with exchanges and staging
     constexpr bool LT = kLdsTwiddles<T> && false;
     __shared__ cpx<T> twl[LT ? TwLayout<N>::ALLOC : 1];
@@ -534,22 +560,19 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_yinv(const cpx<T>* __
     const bool active = kz0 + r < cd.Kz;
     const cpx<T>* in = s3 + (size_t)blockIdx.y * s3_field + ((size_t)kz0 * N + x) * cd.Ky;
     const uint32_t rowoff = (uint32_t)(r * N * cd.Ky);
-    cpx<T>* row = lds + r * ROWE;
+    T* row = lds + r * ROWE;
     cpx<T> v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const int ic = pos_to_compact(l + P * e, cd.Kc, N);
         v[e] = (active && ic >= 0) ? ldo(in, rowoff + (uint32_t)ic) : cpx<T>{(T)0, (T)0};
     }
-    fft_row<N, +1, T>(v, row, tws, l);
-    stage_row<N, T>(v, row, l);
-    __syncthreads();
+    fft_row_split<N, +1, T>(v, row, tws, l);
     cpx<T>* out = s4 + (size_t)blockIdx.y * s4_field + (size_t)x * N * cd.Kz + kz0;
     const int nrows = min(RPB, cd.Kz - kz0);
-    for (int idx = threadIdx.x; idx < N * RPB; idx += RW::THREADS) {
-        const int y = idx / RPB, rr = idx % RPB;
-        if (rr < nrows) sto(out, (uint32_t)(y * cd.Kz + rr), lds[rr * ROWE + lds_pad(y)]);
-    }
+    transpose_out_split<N, T>(v, lds, row, l, N * RPB, [](int y) { return y; }, [&](int y, int rr, cpx<T> val) {
+        if (rr < nrows) sto(out, (uint32_t)(y * cd.Kz + rr), val);
+    });
 }
 
 // --------------------------------------------------------------------------
@@ -571,7 +594,7 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zinv(const cpx<T>* __
                                                                  CubeDims cd) {
     using RW = Rows<T, N>;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
-    __shared__ cpx<T> lds[RPB * ROWE];
+    __shared__ T lds[RPB * ROWE];  // real-valued exchange rows (split exchange)
     // twiddles in LDS for FP32 (this pass's LDS traffic is light), else from the cache
     constexpr bool LT = kLdsTwiddles<T> && true;
     __shared__ cpx<T> twl[LT ? TwLayout<N>::ALLOC : 1];
@@ -588,7 +611,7 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zinv(const cpx<T>* __
     const cpx<T>* A = s4 + (size_t)zj.fa[job] * s4_field + q0 * cd.Kz;
     const cpx<T>* B = tworows ? A : s4 + (size_t)zj.fb[job] * s4_field + q0 * cd.Kz;
     const uint32_t ra = (uint32_t)(r * cd.Kz), rb = (uint32_t)((tworows ? r + RPB : r) * cd.Kz);
-    cpx<T>* row = lds + r * ROWE;
+    T* row = lds + r * ROWE;
     cpx<T> v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
@@ -603,7 +626,7 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zinv(const cpx<T>* __
         }
         v[e] = c;
     }
-    fft_row<N, +1, T>(v, row, tws, l);
+    fft_row_split<N, +1, T>(v, row, tws, l);
     T* oa = zj.outa[job] + q0 * N;
     T* ob = (tworows ? zj.outa[job] : zj.outb[job]) + q0 * N;
     const uint32_t wa = (uint32_t)(r * N), wb = (uint32_t)((tworows ? r + RPB : r) * N);
