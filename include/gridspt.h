@@ -56,7 +56,7 @@ extern "C" {
 typedef enum {
     GRIDSPT_OK = 0,
     GRIDSPT_EINVAL = -1,       /* an argument is out of range or inconsistent */
-    GRIDSPT_EUNSUPPORTED = -2, /* valid, but not built: N not a power of two in [16, 1024], ... */
+    GRIDSPT_EUNSUPPORTED = -2, /* valid, but not built: N not 2^a in [16, 1024] or 3 2^a in [48, 768], ... */
     GRIDSPT_EWORKSPACE = -3,   /* work is null or smaller than required */
     GRIDSPT_EALIGN = -4,       /* a device pointer is null or not 256-byte aligned */
     GRIDSPT_EHIP = -5          /* the HIP runtime reported an error */
@@ -65,7 +65,7 @@ typedef enum {
 typedef enum { GRIDSPT_F32 = 0, GRIDSPT_F64 = 1 } gridspt_dtype;
 
 typedef struct {
-    int32_t n;     /* cells per side N: a power of two, 16 <= N <= 1024 */
+    int32_t n;     /* cells per side N: 2^a with 16 <= N <= 1024, or 3 2^a with 48 <= N <= 768 */
     int32_t dtype; /* gridspt_dtype of every real field and spectrum */
     double box;    /* side L > 0 [Mpc/h] */
     int32_t kc;    /* half-width of the spectral cube, 1 <= kc < N/2; every mask
@@ -197,6 +197,79 @@ int64_t gridspt_bispectrum_workspace_bytes(const gridspt_grid* g, int32_t ntri, 
 int gridspt_bispectrum(gridspt_ctx* ctx, const gridspt_grid* g, int32_t nfields, const void* const* fields_k,
                        int32_t ntri, const int32_t* tri_bins, int32_t nterms, const int32_t* terms, int32_t nbins,
                        const int64_t* edge_n2, double* bk, double* ntriangles, void* work, int64_t work_bytes);
+
+/* ---- batched realisations in one captured graph ----
+ * Many independent realisations, of several grid sizes, computed by one HIP
+ * graph: every pass of a size class is one launch over all its realisations
+ * (realisation r of a class uses the buffers of realisation 0 shifted by a
+ * fixed byte stride), and the size classes are independent branches of the
+ * graph.  Each realisation runs the linear field (step 1 of Sec. II C, Philox
+ * stream lin.stream + r), orders 1..nmax, the cross spectra of its delta_n and,
+ * optionally, bispectra; the graph ends with the realisation mean and sample
+ * standard deviation of every spectrum bin and bispectrum term (the
+ * realisation averages of Sec. IV). */
+typedef struct {
+    gridspt_grid grid;       /* size class; grid.kc must hold both masks */
+    int32_t nreal;           /* realisations >= 1 */
+    int32_t nmax;            /* orders 1..nmax, nmax in [1, 5] */
+    int64_t n2max2;          /* W2 of orders n >= 2 (W1 is lin.n2max) */
+    gridspt_linpk lin;       /* spectrum, growth, W1, seed; realisation r uses stream lin.stream + r */
+    int32_t npairs;          /* cross spectra P_ab of delta_(a+1), delta_(b+1); 1..64 */
+    const int32_t* pairs;    /* host, 2 * npairs indices in [0, nmax) */
+    int32_t nbins;           /* spectrum bins, 1..256 */
+    const int64_t* edge_n2;  /* host, nbins + 1, as for gridspt_power */
+    int32_t ntri;            /* bispectrum triangles, 0 for none */
+    const int32_t* tri_bins; /* host, 3 * ntri bins of edge_n2 */
+    int32_t nterms;          /* bispectrum terms */
+    const int32_t* terms;    /* host, 4 * nterms (fa, fb, fc, tri), fields in [0, nmax) */
+} gridspt_batch_group;
+
+/* Device outputs of one group (NULL entries are skipped). */
+typedef struct {
+    double* pk_mean;    /* [npairs][nbins] realisation mean of P_ab */
+    double* pk_std;     /* [npairs][nbins] sample standard deviation */
+    double* kmean;      /* [nbins] */
+    double* nmodes;     /* [nbins] */
+    double* bk_mean;    /* [nterms] */
+    double* bk_std;     /* [nterms] */
+    double* ntriangles; /* [ntri] */
+} gridspt_batch_out;
+
+typedef struct gridspt_batch gridspt_batch;
+
+enum {
+    GRIDSPT_BATCH_TUNE = 1, /* autotune the launch variant of every pass kind per group */
+    GRIDSPT_BATCH_EAGER = 2 /* no graph: gridspt_batch_run enqueues the launches directly */
+};
+
+/* Device scratch of a batch (all realisations' fields, spectra and scratch). */
+int64_t gridspt_batch_workspace_bytes(int32_t ngroups, const gridspt_batch_group* groups);
+/* Validate the groups, lay out `work`, run the autotuner if asked (it
+ * enqueues and waits for complete trial runs, overwriting `work`), and
+ * capture the graph.  Host arrays of the groups are copied; `outs` (host
+ * array of ngroups) and `work` must stay valid for the batch's life. */
+int gridspt_batch_create(gridspt_ctx* ctx, int32_t ngroups, const gridspt_batch_group* groups,
+                         const gridspt_batch_out* outs, void* work, int64_t work_bytes, uint32_t flags,
+                         gridspt_batch** out);
+/* Launch the whole batch (one graph launch) on the context's stream. */
+int gridspt_batch_run(gridspt_batch* b);
+void gridspt_batch_destroy(gridspt_batch* b);
+
+enum {
+    GRIDSPT_BATCH_DELTA = 0,   /* delta_n(x) of a realisation, N^3 real; index = n - 1 */
+    GRIDSPT_BATCH_THETA = 1,   /* theta_n(x), index = n - 1 (n = 1 gives delta_1) */
+    GRIDSPT_BATCH_DELTA_K = 2, /* cube-layout spectrum of delta_n, index = n - 1 */
+    GRIDSPT_BATCH_PK = 3,      /* the realisation's P_ab, [npairs][nbins] doubles; index 0 */
+    GRIDSPT_BATCH_BK = 4       /* the realisation's bispectrum terms, [nterms] doubles; index 0 */
+};
+/* Device address, inside `work`, of one realisation's buffer `what`. */
+int gridspt_batch_buffer(const gridspt_batch* b, int32_t group, int32_t real, int32_t what, int32_t index,
+                         void** ptr);
+/* The launch variant chosen per pass kind for a group (0 without tuning),
+ * with the tuner's time for it: up to max kinds; names as for
+ * gridspt_profile_read; ms may be NULL.  Returns the number of kinds. */
+int gridspt_batch_tuning(const gridspt_batch* b, int32_t group, int32_t max, char* names, int32_t* variant,
+                         double* ms);
 
 /* ---- kernel timing ----
  * With profiling on, every kernel the context enqueues is bracketed by HIP

@@ -43,6 +43,21 @@ class _LinPk(ctypes.Structure):
                 ("stream", ctypes.c_uint64)]
 
 
+class _BatchGroup(ctypes.Structure):
+    _fields_ = [("grid", _Grid), ("nreal", ctypes.c_int32), ("nmax", ctypes.c_int32), ("n2max2", ctypes.c_int64),
+                ("lin", _LinPk), ("npairs", ctypes.c_int32), ("pairs", ctypes.c_void_p), ("nbins", ctypes.c_int32),
+                ("edge_n2", ctypes.c_void_p), ("ntri", ctypes.c_int32), ("tri_bins", ctypes.c_void_p),
+                ("nterms", ctypes.c_int32), ("terms", ctypes.c_void_p)]
+
+
+class _BatchOut(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("pk_mean", "pk_std", "kmean", "nmodes", "bk_mean", "bk_std",
+                                               "ntriangles")]
+
+
+BATCH_TUNE, BATCH_EAGER = 1, 2
+BATCH_DELTA, BATCH_THETA, BATCH_DELTA_K, BATCH_PK, BATCH_BK = 0, 1, 2, 3, 4
+
 _lib = None
 
 
@@ -77,6 +92,13 @@ def lib():
             "gridspt_power": ([vp, gp, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp, i64], ctypes.c_int),
             "gridspt_bispectrum_workspace_bytes": ([gp, i32, vp, i32, vp], i64),
             "gridspt_bispectrum": ([vp, gp, i32, vp, i32, vp, i32, vp, i32, vp, vp, vp, vp, i64], ctypes.c_int),
+            "gridspt_batch_workspace_bytes": ([i32, ctypes.POINTER(_BatchGroup)], i64),
+            "gridspt_batch_create": ([vp, i32, ctypes.POINTER(_BatchGroup), ctypes.POINTER(_BatchOut), vp, i64,
+                                      ctypes.c_uint32, ctypes.POINTER(vp)], ctypes.c_int),
+            "gridspt_batch_run": ([vp], ctypes.c_int),
+            "gridspt_batch_destroy": ([vp], None),
+            "gridspt_batch_buffer": ([vp, i32, i32, i32, i32, ctypes.POINTER(vp)], ctypes.c_int),
+            "gridspt_batch_tuning": ([vp, i32, i32, vp, vp, vp], ctypes.c_int),
             "gridspt_set_profiling": ([vp, i32], ctypes.c_int),
             "gridspt_profile_read": ([vp, i32, vp, vp, vp, vp], ctypes.c_int),
         }
@@ -344,3 +366,111 @@ def bispectrum(ctx: Context, grid: Grid, fields_k: Sequence[torch.Tensor], tris,
                                     tb.ctypes.data, nterms, tt.ctypes.data, nb, e.ctypes.data, _ptr(bk), _ptr(nt),
                                     _ptr(ws), ws.numel()), "bispectrum")
     return bk, nt
+
+
+# --------------------------------------------------------------------------
+# batches of realisations (one captured graph)
+# --------------------------------------------------------------------------
+
+@dataclass
+class BatchGroup:
+    """nreal realisations of one grid: linear field (Philox stream lin.stream + r),
+    orders 1..nmax, spectra of the delta_n pairs and optional bispectrum terms."""
+    grid: Grid
+    nreal: int
+    nmax: int
+    n2max2: int
+    lin: LinearSpectrum
+    pairs: Sequence
+    edges: Sequence
+    tris: Optional[Sequence] = None
+    terms: Optional[Sequence] = None
+
+
+class Batch:
+    """gridspt_batch_*: every group's passes launched once over all its
+    realisations, the groups as parallel branches of one HIP graph, ending in
+    realisation means and standard deviations of P and B."""
+
+    def __init__(self, ctx: Context, groups: Sequence[BatchGroup], tune: bool = False, eager: bool = False):
+        import numpy as np
+        self.ctx = ctx
+        self.groups = list(groups)
+        ng = len(self.groups)
+        self._keep = []
+        cg = (_BatchGroup * ng)()
+        self.out = []
+        co = (_BatchOut * ng)()
+        for i, bg in enumerate(self.groups):
+            pr = np.ascontiguousarray(np.asarray(bg.pairs, dtype=np.int32).reshape(-1))
+            e = np.ascontiguousarray(np.asarray(bg.edges, dtype=np.int64))
+            tb = np.ascontiguousarray(np.asarray(bg.tris if bg.tris is not None else [], dtype=np.int32).reshape(-1))
+            tt = np.ascontiguousarray(np.asarray(bg.terms if bg.terms is not None else [], dtype=np.int32).reshape(-1))
+            self._keep += [pr, e, tb, tt]
+            lp = bg.lin
+            cg[i] = _BatchGroup(bg.grid.cstruct, bg.nreal, bg.nmax, bg.n2max2,
+                                _LinPk(lp.amp, lp.ns, lp.gamma, lp.growth, lp.n2max, lp.seed, lp.stream),
+                                pr.size // 2, pr.ctypes.data, e.size - 1, e.ctypes.data, tb.size // 3,
+                                tb.ctypes.data if tb.size else None, tt.size // 4, tt.ctypes.data if tt.size else None)
+            npairs, nb, ntri, nterms = pr.size // 2, e.size - 1, tb.size // 3, tt.size // 4
+            dev = dict(device="cuda", dtype=torch.float64)
+            o = {"pk_mean": torch.zeros((npairs, nb), **dev), "pk_std": torch.zeros((npairs, nb), **dev),
+                 "kmean": torch.zeros(nb, **dev), "nmodes": torch.zeros(nb, **dev)}
+            if ntri:
+                o.update(bk_mean=torch.zeros(nterms, **dev), bk_std=torch.zeros(nterms, **dev),
+                         ntriangles=torch.zeros(ntri, **dev))
+            self.out.append(o)
+            co[i] = _BatchOut(*[o[k].data_ptr() if k in o else None for k, _ in _BatchOut._fields_])
+        self._cg, self._co = cg, co
+        need = _check(lib().gridspt_batch_workspace_bytes(ng, cg), "batch_workspace_bytes")
+        self.work = torch.empty(max(int(need), 256), dtype=torch.uint8, device="cuda")
+        flags = (BATCH_TUNE if tune else 0) | (BATCH_EAGER if eager else 0)
+        h = ctypes.c_void_p()
+        _check(lib().gridspt_batch_create(ctx.handle, ng, cg, co, _ptr(self.work), self.work.numel(), flags,
+                                          ctypes.byref(h)), "batch_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.gridspt_batch_destroy(h)
+            self._h = None
+
+    def run(self):
+        _check(lib().gridspt_batch_run(self._h), "batch_run")
+
+    def buffer(self, group: int, real: int, what: int, index: int = 0) -> torch.Tensor:
+        """A view of one realisation's buffer inside the batch workspace."""
+        import numpy as np
+        p = ctypes.c_void_p()
+        _check(lib().gridspt_batch_buffer(self._h, group, real, what, index, ctypes.byref(p)), "batch_buffer")
+        bg = self.groups[group]
+        g = bg.grid
+        off = p.value - self.work.data_ptr()
+        if what in (BATCH_DELTA, BATCH_THETA):
+            shape, dt = (g.n,) * 3, g.real_dtype
+        elif what == BATCH_DELTA_K:
+            shape, dt = g.cube_shape, g.real_dtype
+        elif what == BATCH_PK:
+            shape, dt = (int(np.asarray(bg.pairs).size // 2), len(bg.edges) - 1), torch.float64
+        else:
+            shape, dt = (int(np.asarray(bg.terms).size // 4),), torch.float64
+        nbytes = int(torch.tensor([], dtype=dt).element_size())
+        for d in shape:
+            nbytes *= d
+        return self.work[off: off + nbytes].view(dt).view(shape)
+
+    def tuning(self, group: int):
+        """{kind: (variant, ms)} chosen by the autotuner for a group."""
+        import numpy as np
+        m = 32
+        names = ctypes.create_string_buffer(32 * m)
+        var = np.zeros(m, dtype=np.int32)
+        ms = np.zeros(m)
+        k = _check(lib().gridspt_batch_tuning(self._h, group, m, names, var.ctypes.data, ms.ctypes.data),
+                   "batch_tuning")
+        out = {}
+        for i in range(k):
+            nm = names.raw[32 * i: 32 * (i + 1)].split(b"\0", 1)[0].decode()
+            out[nm] = (int(var[i]), float(ms[i]))
+        return out

@@ -37,6 +37,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 // own LDS accumulator.  Quantities per bin: npairs pair sums w Re[F_a F_b^*],
 // then sum w and sum w |k|.  Block partials [block][bin][q] are reduced in a
 // fixed order by k_power_reduce, so the result is bitwise reproducible.
+// Every kernel here takes a realisation stride zs (see zptr): gridDim.z
+// realisations in one launch.
 // ---------------------------------------------------------------------------
 constexpr int kPowerPairsPerLaunch = 16;
 
@@ -53,7 +55,7 @@ struct PowerArgs {
 constexpr int kPowerWaves = 4;
 
 template <typename T>
-__global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T> a, CubeDims cd) {
+__global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T> a, CubeDims cd, size_t zs) {
     constexpr int QP = kPowerPairsPerLaunch;
     extern __shared__ double acc[];  // [kPowerWaves][nbins][Q]
     __shared__ int64_t edges[kMaxBins + 1];
@@ -98,7 +100,7 @@ __global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T>
             for (int q = 0; q < QP; ++q) {
                 v[q] = 0.0;
                 if (q < a.npairs && bin >= 0) {
-                    const cpx<T> x = a.f[a.pa[q]][base + kxc], y = a.f[a.pb[q]][base + kxc];
+                    const cpx<T> x = zptr(a.f[a.pa[q]], zs)[base + kxc], y = zptr(a.f[a.pb[q]], zs)[base + kxc];
                     v[q] = w * ((double)x.x * (double)y.x + (double)x.y * (double)y.y);
                 }
             }
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T>
         }
     }
     __syncthreads();
-    double* out = a.partial + (size_t)blockIdx.x * a.nbins * Q;
+    double* out = zptr(a.partial, zs) + (size_t)blockIdx.x * a.nbins * Q;
     for (int i = threadIdx.x; i < a.nbins * Q; i += blockDim.x) {
         double s = 0.0;
         for (int wv = 0; wv < kPowerWaves; ++wv) s += acc[(size_t)wv * a.nbins * Q + i];
@@ -141,9 +143,11 @@ __global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T>
 // One block per (bin, q): sum the block partials in a fixed order (strided
 // per thread, then an LDS tree) into sums[bin][q].
 constexpr int kReduceThreads = 256;
-__global__ __launch_bounds__(kReduceThreads) void k_power_reduce(const double* partial, int nblocks, int nq,
-                                                                 double* sums) {
+static __global__ __launch_bounds__(kReduceThreads) void k_power_reduce(const double* partial, int nblocks, int nq,
+                                                                 double* sums, size_t zs) {
     __shared__ double red[kReduceThreads];
+    partial = zptr(partial, zs);
+    sums = zptr(sums, zs);
     const int item = blockIdx.x;  // bin * nq + q
     double s = 0.0;
     for (int i = threadIdx.x; i < nblocks; i += kReduceThreads) s += partial[(size_t)i * gridDim.x + item];
@@ -157,9 +161,13 @@ __global__ __launch_bounds__(kReduceThreads) void k_power_reduce(const double* p
 }
 
 // P = L^3 S / sum w, kmean = sum w |k| / sum w, nmodes = sum w.
-__global__ void k_power_final(const double* sums, int nbins, int npairs, double vol, double* pk, int pk_stride,
-                              double* kmean, double* nmodes) {
+static __global__ void k_power_final(const double* sums, int nbins, int npairs, double vol, double* pk, int pk_stride,
+                              double* kmean, double* nmodes, size_t zs) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    sums = zptr(sums, zs);
+    pk = zptr(pk, zs);
+    kmean = zptr(kmean, zs);
+    nmodes = zptr(nmodes, zs);
     if (b >= nbins) return;
     const int Q = npairs + 2;
     const double cnt = sums[(size_t)b * Q + npairs], ks = sums[(size_t)b * Q + npairs + 1];
@@ -185,8 +193,18 @@ struct TripleArgs {
 constexpr int kTripleThreads = 256;
 
 template <typename T>
-__global__ __launch_bounds__(kTripleThreads) void k_triple_partial(TripleArgs<T> t) {
+__global__ __launch_bounds__(kTripleThreads) void k_triple_partial(TripleArgs<T> t, size_t zs) {
     __shared__ double red[kTripleThreads];
+    const T* pa[8];
+    const T* pb[8];
+    const T* pc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        pa[u] = u < t.nterms ? zptr(t.a[u], zs) : nullptr;
+        pb[u] = u < t.nterms ? zptr(t.b[u], zs) : nullptr;
+        pc[u] = u < t.nterms ? zptr(t.c[u], zs) : nullptr;
+    }
+    double* partial = zptr(t.partial, zs);
     double s[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) s[u] = 0.0;
@@ -194,7 +212,7 @@ __global__ __launch_bounds__(kTripleThreads) void k_triple_partial(TripleArgs<T>
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < t.ncell; i += stride) {
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            if (u < t.nterms) s[u] += (double)t.a[u][i] * (double)t.b[u][i] * (double)t.c[u][i];
+            if (u < t.nterms) s[u] += (double)pa[u][i] * (double)pb[u][i] * (double)pc[u][i];
     }
     for (int u = 0; u < t.nterms; ++u) {
         red[threadIdx.x] = s[u];
@@ -203,17 +221,24 @@ __global__ __launch_bounds__(kTripleThreads) void k_triple_partial(TripleArgs<T>
             if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
             __syncthreads();
         }
-        if (threadIdx.x == 0) t.partial[(size_t)blockIdx.x * 8 + u] = red[0];
+        if (threadIdx.x == 0) partial[(size_t)blockIdx.x * 8 + u] = red[0];
         __syncthreads();
     }
 }
 
-__global__ void k_triple_final(const double* partial, int nblocks, int nterms, double* out) {
+// sums of the block partials, item u to out[dst.idx[u]]
+struct TripleDst {
+    int idx[8];
+};
+static __global__ void k_triple_final(const double* partial, int nblocks, int nterms, TripleDst dst, double* out,
+                               size_t zs) {
     const int u = threadIdx.x;
     if (u >= nterms) return;
+    partial = zptr(partial, zs);
+    out = zptr(out, zs);
     double s = 0.0;
     for (int i = 0; i < nblocks; ++i) s += partial[(size_t)i * 8 + u];
-    out[u] = s;
+    out[dst.idx[u]] = s;
 }
 
 // bk = L^6 T / J for terms u0 .. u0+nu-1 (both sums over x of the same grid, so
@@ -221,9 +246,13 @@ __global__ void k_triple_final(const double* partial, int nblocks, int nterms, d
 struct TriMap {
     int tri[64];
 };
-__global__ void k_bisp_final(const double* tsum, const double* jsum, TriMap m, int u0, int nu, int nt,
-                             double vol2, double invN3, double* bk, double* ntriangles) {
+static __global__ void k_bisp_final(const double* tsum, const double* jsum, TriMap m, int u0, int nu, int nt,
+                             double vol2, double invN3, double* bk, double* ntriangles, size_t zs) {
     const int i = threadIdx.x;
+    tsum = zptr(tsum, zs);
+    jsum = zptr(jsum, zs);
+    bk = zptr(bk, zs);
+    ntriangles = zptr(ntriangles, zs);
     if (i < nu) {
         const double j = jsum[m.tri[i]];
         bk[u0 + i] = j != 0.0 ? vol2 * tsum[u0 + i] / j : 0.0;
@@ -264,9 +293,26 @@ __global__ void k_sum_orders(SumArgs<T> s) {
 
 // copy a real field (theta_1 = delta_1)
 template <typename T>
-__global__ void k_copy(const T* __restrict__ src, T* __restrict__ dst, size_t n) {
+__global__ void k_copy(const T* __restrict__ src, T* __restrict__ dst, size_t n, size_t zs) {
+    src = zptr(src, zs);
+    dst = zptr(dst, zs);
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+// Mean and sample standard deviation over nreal realisations of `count`
+// doubles at byte stride zs: a fixed-order two-pass sum per item.
+static __global__ void k_batch_stats(const double* x, int nreal, int count, size_t zs, double* mean, double* sdev) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    auto at = [&](int r) { return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(x + i) + (size_t)r * zs); };
+    double s = 0.0;
+    for (int r = 0; r < nreal; ++r) s += at(r);
+    const double m = s / nreal;
+    double q = 0.0;
+    for (int r = 0; r < nreal; ++r) q += (at(r) - m) * (at(r) - m);
+    if (mean) mean[i] = m;
+    if (sdev) sdev[i] = nreal > 1 ? sqrt(q / (nreal - 1)) : 0.0;
 }
 
 }  // namespace gridspt

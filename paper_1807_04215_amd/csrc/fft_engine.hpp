@@ -1,17 +1,19 @@
 // Row FFT engine for gfx950: one row of N complex points is held by a team of
-// P = N/16 lanes of one 64-wide wavefront, 16 points per lane, and transformed
-// by Stockham autosort passes (first radix 16 in registers, later passes
-// exchanging through a per-row LDS buffer).  Rows of N <= 1024 fit in one
-// wavefront, so the exchanges only need wavefront-scope synchronisation.
+// P lanes of one 64-wide wavefront, E points per lane (E = 16 for N = 2^a,
+// E = 12 for N = 3 * 2^a), and transformed by Stockham autosort passes (first
+// radix E in registers, later passes exchanging through a per-row LDS
+// buffer).  A row never spans two wavefronts, so the exchanges only need
+// wavefront-scope synchronisation.
 //
 // Register layout ("canonical"): lane l of the team, register e holds point
 // l + P*e of the row, both before and after a transform.  This is also the
 // order in which a team reads a contiguous row from HBM (consecutive lanes,
-// consecutive addresses), so loads feed the first radix-16 pass directly.
+// consecutive addresses), so loads feed the first pass directly.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
 #include <utility>
 
 namespace gridspt {
@@ -60,43 +62,52 @@ __device__ __forceinline__ void static_for(F&& f) {
     static_for_impl(f, std::make_integer_sequence<int, Count>{});
 }
 
-// cos and sin of 2 pi m / 16, m = 0..15 (exact values of the eighth-circle
-// constants cos(pi/8), cos(pi/4), cos(3pi/8)).
+// cos of 2 pi m / 16, m = 0..15 (exact values of the eighth-circle constants
+// cos(pi/8), cos(pi/4), cos(3pi/8)), and of 2 pi m / 12 (sqrt(3)/2 and 1/2).
 __device__ constexpr double kCos16[16] = {
     1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
     0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
     -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
     0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+__device__ constexpr double kCos12[12] = {1.0, 0.86602540378443864676, 0.5, 0.0, -0.5, -0.86602540378443864676,
+                                          -1.0, -0.86602540378443864676, -0.5, 0.0, 0.5, 0.86602540378443864676};
 
-// a * exp(DIR * 2 pi i K / R) for a compile-time root of unity of order R | 16,
-// with the trivial multiples of pi/2 done by swaps and sign flips.
+// a * exp(DIR * 2 pi i K / R) for a compile-time root of unity of order
+// R | 16 or R | 12, with the multiples of pi/2 done by swaps and sign flips.
 template <int R, int K, int DIR, typename T>
 __device__ __forceinline__ cpx<T> twiddle_const(cpx<T> a) {
+    static_assert(16 % R == 0 || 12 % R == 0, "root order must divide 16 or 12");
+    constexpr int C = (16 % R == 0) ? 16 : 12;  // circle the root lives on
     constexpr int k = ((K % R) + R) % R;
-    constexpr int m = k * (16 / R);  // position on the 16-point circle
+    constexpr int m = k * (C / R);  // position on the C-point circle
     if constexpr (m == 0) {
         return a;
-    } else if constexpr (m == 8) {
+    } else if constexpr (2 * m == C) {
         return {-a.x, -a.y};
-    } else if constexpr (m == 4) {  // exp(DIR i pi/2) = DIR i
+    } else if constexpr (4 * m == C) {  // exp(DIR i pi/2) = DIR i
         if constexpr (DIR > 0) return {-a.y, a.x};
         else return {a.y, -a.x};
-    } else if constexpr (m == 12) {  // exp(DIR i 3pi/2) = -DIR i
+    } else if constexpr (4 * m == 3 * C) {  // exp(DIR i 3pi/2) = -DIR i
         if constexpr (DIR > 0) return {a.y, -a.x};
         else return {-a.y, a.x};
     } else {
-        constexpr double c = kCos16[m];
-        constexpr double s = (DIR > 0 ? 1.0 : -1.0) * kCos16[(m + 12) % 16];  // sin = cos(. - pi/2)
+        // sin(2 pi m / C) = cos(2 pi (m - C/4) / C)
+        constexpr double c = C == 16 ? kCos16[m] : kCos12[m];
+        constexpr double s0 = C == 16 ? kCos16[(m + 12) % 16] : kCos12[(m + 9) % 12];
+        constexpr double s = (DIR > 0 ? 1.0 : -1.0) * s0;
         const T cc = (T)c, ss = (T)s;
         return {a.x * cc - a.y * ss, a.x * ss + a.y * cc};
     }
 }
 
-// In-place DFT of R points in natural order: X[k] = sum_j x[j] exp(DIR 2 pi i jk/R).
-// Radix-2 decimation in time, all twiddles compile-time constants.
+// In-place DFT of R points in natural order: X[k] = sum_j x[j] exp(DIR 2 pi i jk/R),
+// for R a power of two (radix-2 decimation in time), R = 3, or R = 12
+// (four-point DFTs of the three residue classes j mod 3, twiddles w_12^(j2 k1),
+// then three-point DFTs); all twiddles are compile-time constants.
 template <int R, int DIR, typename T>
 struct Dft {
     static __device__ __forceinline__ void run(cpx<T>* x) {
+        static_assert((R & (R - 1)) == 0, "power-of-two radix expected");
         cpx<T> ev[R / 2], od[R / 2];
 #pragma unroll
         for (int i = 0; i < R / 2; ++i) {
@@ -117,6 +128,38 @@ template <int DIR, typename T>
 struct Dft<1, DIR, T> {
     static __device__ __forceinline__ void run(cpx<T>*) {}
 };
+template <int DIR, typename T>
+struct Dft<3, DIR, T> {
+    // w = exp(DIR 2 pi i / 3) = -1/2 + DIR i sqrt(3)/2
+    static __device__ __forceinline__ void run(cpx<T>* x) {
+        const cpx<T> s = cadd(x[1], x[2]), d = csub(x[1], x[2]);
+        const cpx<T> t = {x[0].x - (T)0.5 * s.x, x[0].y - (T)0.5 * s.y};
+        const T h = (T)(DIR > 0 ? 0.86602540378443864676 : -0.86602540378443864676);
+        const cpx<T> r = {-h * d.y, h * d.x};  // DIR i sqrt(3)/2 (x1 - x2)
+        x[0] = cadd(x[0], s);
+        x[1] = cadd(t, r);
+        x[2] = csub(t, r);
+    }
+};
+template <int DIR, typename T>
+struct Dft<12, DIR, T> {
+    static __device__ __forceinline__ void run(cpx<T>* x) {
+        cpx<T> y[3][4];
+#pragma unroll
+        for (int j2 = 0; j2 < 3; ++j2) {
+#pragma unroll
+            for (int j1 = 0; j1 < 4; ++j1) y[j2][j1] = x[3 * j1 + j2];
+            Dft<4, DIR, T>::run(y[j2]);
+        }
+        static_for<4>([&](auto kc) {
+            constexpr int k1 = decltype(kc)::value;
+            cpx<T> z[3] = {y[0][k1], twiddle_const<12, k1, DIR>(y[1][k1]), twiddle_const<12, 2 * k1, DIR>(y[2][k1])};
+            Dft<3, DIR, T>::run(z);
+#pragma unroll
+            for (int k2 = 0; k2 < 3; ++k2) x[k1 + 4 * k2] = z[k2];
+        });
+    }
+};
 
 // Wavefront-scope barrier: orders LDS traffic of all lanes of this wave.
 __device__ __forceinline__ void wave_sync() {
@@ -130,39 +173,53 @@ __device__ __forceinline__ void wave_sync() {
 __host__ __device__ constexpr int lds_pad(int pos) { return pos + (pos >> 4); }
 __host__ __device__ constexpr int lds_row_elems(int n) { return n + (n >> 4) + 1; }
 
-// Radix plan: the first pass is radix 16; the remaining factor of N is split
-// into at most two more passes of radix <= 16.
-template <int N>
+// Radix plan of an N-point row.  A row is held by P lanes with E points each
+// (E = 16 when N is a power of two, E = 12 when N = 3 * 2^a), so P = N / E is
+// a power of two <= 64 and a team never straddles a wavefront.  Pass 0 is a
+// radix-E DFT in registers; passes q = 1..NP have radices R_q dividing E
+// (at most 16, or at most 4 when E = 12 or SPLIT is set) and exchange through
+// LDS.  Pass q has Stockham stride S_q = E R_1 ... R_(q-1).
+template <int N_, int SPLIT = 0>
 struct Plan {
-    static constexpr int P = N / 16;  // lanes per row
-    static constexpr int R2 = (N <= 16) ? 1 : (N / 16 >= 16 ? 16 : N / 16);
-    static constexpr int R3 = (N <= 256) ? 1 : N / 256;
-    static_assert(N >= 16 && N <= 1024 && (N & (N - 1)) == 0, "N must be a power of two in [16, 1024]");
+    static constexpr int N = N_;
+    static constexpr int E = (N % 3 == 0) ? 12 : 16;
+    static constexpr int P = N / E;
+    static constexpr int CAP = (E == 12 || SPLIT != 0) ? 4 : 16;
+    static constexpr int take(int rem) { return rem <= 1 ? 1 : (rem >= CAP ? CAP : rem); }
+    static constexpr int R1 = take(P);
+    static constexpr int R2 = take(P / R1);
+    static constexpr int R3 = take(P / (R1 * R2));
+    static constexpr int NP = (R1 > 1) + (R2 > 1) + (R3 > 1);
+    static constexpr int radix(int q) { return q == 0 ? E : (q == 1 ? R1 : (q == 2 ? R2 : R3)); }
+    static constexpr int stride(int q) { return q == 0 ? 1 : (q == 1 ? E : (q == 2 ? E * R1 : E * R1 * R2)); }
+    // per-pass twiddle tables [j - 1][k], j < R_q, k < S_q, back to back
+    static constexpr int tw_off(int q) {
+        int o = 0;
+        for (int i = 1; i < q; ++i) o += (radix(i) - 1) * stride(i);
+        return o;
+    }
+    static constexpr int TW_SIZE = tw_off(NP + 1);
+    static constexpr int TW_ALLOC = TW_SIZE > 0 ? TW_SIZE : 1;
+    static_assert(E * P == N && P >= 1 && P <= 64 && (P & (P - 1)) == 0, "N must be 2^a (16..1024) or 3 2^a (12..768)");
+    static_assert(R1 * R2 * R3 == P, "radix plan does not cover N");
+    static_assert(E % R1 == 0 && E % R2 == 0 && E % R3 == 0, "later radices must divide E");
 };
 
-// Twiddles of the Stockham passes after the first: pass (R, p) multiplies
-// input j of butterfly b by w_{pR}^{j k}, k = b mod p, with w_M = exp(-2 pi i / M).
-//   LDS form (FP32): one table per pass laid out [j - 1][k], so the lanes of a
-//     wavefront (consecutive k) read consecutive words; about N entries.
-//   global form (FP64): the full table w_N^m, m < N, read through the cache.
-template <int N>
-struct TwLayout {
-    static constexpr int R2 = Plan<N>::R2, R3 = Plan<N>::R3;
-    static constexpr int PASS3 = R2 > 1 ? (R2 - 1) * 16 : 0;  // start of the third pass's table
-    static constexpr int SIZE = PASS3 + (R3 > 1 ? (R3 - 1) * 16 * R2 : 0);
-    static constexpr int ALLOC = SIZE > 0 ? SIZE : 1;
-};
-
-template <typename T, int N, bool LDS>
+// Twiddles of the passes after the first: pass q multiplies input j of
+// butterfly b by w_{S R}^{j k}, k = b mod S, with w_M = exp(-2 pi i / M).
+//   LDS form: the per-pass tables of Plan, so the lanes of a wavefront
+//     (consecutive k) read consecutive words.
+//   global form: the full table w_N^m, m < N, read through the cache.
+template <typename T, typename PL, bool LDS>
 struct Twiddles {
     const cpx<T>* t;
-    template <int R, int PSTRIDE>
+    template <int Q>
     __device__ __forceinline__ cpx<T> get(int j, int k) const {
+        constexpr int R = PL::radix(Q), S = PL::stride(Q);
         if constexpr (LDS) {
-            constexpr int base = PSTRIDE == 16 ? 0 : TwLayout<N>::PASS3;
-            return t[base + (j - 1) * PSTRIDE + k];
+            return t[PL::tw_off(Q) + (j - 1) * S + k];
         } else {
-            return t[j * k * (N / (PSTRIDE * R))];
+            return t[j * k * (PL::N / (S * R))];
         }
     }
 };
@@ -175,98 +232,87 @@ constexpr bool kLdsTwiddles = sizeof(T) == 4;
 
 // Fill the LDS tables from the global full table w_N^m; the caller
 // synchronises the block before the first transform.
-template <int N, typename T>
+template <typename PL, typename T>
 __device__ __forceinline__ void load_twiddles(cpx<T>* lds_tw, const cpx<T>* __restrict__ tw) {
-    using TL = TwLayout<N>;
-    {
-        for (int i = threadIdx.x; i < TL::SIZE; i += blockDim.x) {
-            int m;
-            if (i < TL::PASS3) {
-                const int j = i / 16 + 1, k = i % 16;             // pass 2: p = 16, R = R2
-                m = j * k * (N / (16 * TL::R2));
-            } else {
-                const int q = i - TL::PASS3, j = q / (16 * TL::R2) + 1, k = q % (16 * TL::R2);
-                m = j * k * (N / (16 * TL::R2 * TL::R3));      // pass 3: p = 16 R2, R = R3
-            }
-            lds_tw[i] = tw[m];
-        }
+    for (int i = threadIdx.x; i < PL::TW_SIZE; i += blockDim.x) {
+        int q = 1;
+        if (PL::NP >= 2 && i >= PL::tw_off(2)) q = 2;
+        if (PL::NP >= 3 && i >= PL::tw_off(3)) q = 3;
+        const int S = PL::stride(q), R = PL::radix(q), o = i - PL::tw_off(q);
+        const int j = o / S + 1, k = o % S;
+        lds_tw[i] = tw[j * k * (PL::N / (S * R))];
     }
 }
 
-// Stockham pass of radix R over a row held in LDS (not the first pass).
-// Lane l handles butterflies b = l + P t, t < 16/R; butterfly b reads points
-// b + j N/R, twiddles input j by w_{pR}^{j (b mod p)}, and writes its outputs
-// to (b - k) R + k + j p, or, on the last pass, keeps them in registers in
-// canonical order (register t + j 16/R holds point l + P (t + j 16/R)).
-template <int N, int R, int PSTRIDE, bool LAST, int DIR, typename T, bool LT>
-__device__ __forceinline__ void stockham_pass(cpx<T> (&x)[16], cpx<T>* row, Twiddles<T, N, LT> tw, int l) {
-    constexpr int P = N / 16;
-    constexpr int NB = 16 / R;
-    cpx<T> y[16];
+// Row positions in the Stockham schedule, lane l, register i of the pass:
+//   in_pos<Q>:  inputs of pass Q (butterfly b = l + P (i / R) reads b + (i mod R) N / R)
+//   out_pos<Q>: outputs of pass Q (to (b - k) R + k + (i mod R) S, k = b mod S)
+template <typename PL, int Q>
+__device__ __forceinline__ int in_pos(int l, int i) {
+    constexpr int R = PL::radix(Q);
+    return l + PL::P * (i / R) + (i % R) * (PL::N / R);
+}
+template <typename PL, int Q>
+__device__ __forceinline__ int out_pos(int l, int i) {
+    constexpr int R = PL::radix(Q), S = PL::stride(Q);
+    const int b = l + PL::P * (i / R), k = b % S;
+    return (b - k) * R + k + (i % R) * S;
+}
+
+// Pass Q >= 1 on values gathered into y (y[t R + j] = input j of butterfly t).
+template <typename PL, int Q, int DIR, typename T, bool LT>
+__device__ __forceinline__ void stockham_compute(cpx<T> (&y)[PL::E], Twiddles<T, PL, LT> tw, int l) {
+    constexpr int R = PL::radix(Q), S = PL::stride(Q), NB = PL::E / R;
 #pragma unroll
     for (int t = 0; t < NB; ++t) {
-        const int b = l + P * t;
-#pragma unroll
-        for (int j = 0; j < R; ++j) y[t * R + j] = row[lds_pad(b + j * (N / R))];
-    }
-    wave_sync();  // every lane has read before anyone overwrites
-#pragma unroll
-    for (int t = 0; t < NB; ++t) {
-        const int b = l + P * t;
-        const int k = b & (PSTRIDE - 1);
-        // w_{pR}^{jk} = w_N^{jk N/(pR)} from the forward table; conjugate for DIR > 0
+        const int k = (l + PL::P * t) % S;
 #pragma unroll
         for (int j = 1; j < R; ++j) {
-            cpx<T> w = tw.template get<R, PSTRIDE>(j, k);
+            cpx<T> w = tw.template get<Q>(j, k);
             if (DIR > 0) w.y = -w.y;
             y[t * R + j] = cmul(y[t * R + j], w);
         }
         Dft<R, DIR, T>::run(&y[t * R]);
     }
-    if constexpr (LAST) {
+}
+
+// After the last pass: butterfly t output j is point l + P (t + j NB), so the
+// canonical register order is a compile-time permutation.
+template <typename PL, typename T>
+__device__ __forceinline__ void to_canonical(const cpx<T> (&y)[PL::E], cpx<T> (&x)[PL::E]) {
+    constexpr int R = PL::radix(PL::NP), NB = PL::E / R;
 #pragma unroll
-        for (int t = 0; t < NB; ++t)
+    for (int t = 0; t < NB; ++t)
 #pragma unroll
-            for (int j = 0; j < R; ++j) x[t + j * NB] = y[t * R + j];
-    } else {
-#pragma unroll
-        for (int t = 0; t < NB; ++t) {
-            const int b = l + P * t;
-            const int k = b & (PSTRIDE - 1);
-#pragma unroll
-            for (int j = 0; j < R; ++j) row[lds_pad((b - k) * R + k + j * PSTRIDE)] = y[t * R + j];
-        }
-        wave_sync();
-    }
+        for (int j = 0; j < R; ++j) x[t + j * NB] = y[t * R + j];
 }
 
 // Transform one row held in canonical registers, in place (unnormalised).
-// `row` is this row's LDS buffer (lds_row_elems(N) elements), `tw` the
-// twiddle source (see Twiddles), and l the lane in the team.
-template <int N, int DIR, typename T, bool LT>
-__device__ __forceinline__ void fft_row(cpx<T> (&x)[16], cpx<T>* row, Twiddles<T, N, LT> tw, int l) {
-    using PL = Plan<N>;
-    Dft<16, DIR, T>::run(x);  // pass 1: butterfly b = l over points l + P j, no twiddles
-    if constexpr (N == 16) {
-        return;
-    } else {
-        // pass-1 outputs go to points 16 l + j
+// `row` is this row's LDS buffer (lds_row_elems(N) complex elements), `tw`
+// the twiddle source (see Twiddles), and l the lane in the team.
+template <typename PL, int DIR, typename T, bool LT>
+__device__ __forceinline__ void fft_row(cpx<T> (&x)[PL::E], cpx<T>* row, Twiddles<T, PL, LT> tw, int l) {
+    constexpr int E = PL::E;
+    Dft<E, DIR, T>::run(x);  // pass 0: butterfly b = l over points l + P j, no twiddles
+    cpx<T> y[E];
+    static_for<PL::NP>([&](auto qc) {
+        constexpr int Q = decltype(qc)::value + 1;
+        // outputs of pass Q - 1 out to the row, inputs of pass Q back
 #pragma unroll
-        for (int j = 0; j < 16; ++j) row[lds_pad(16 * l + j)] = x[j];
+        for (int i = 0; i < E; ++i) row[lds_pad(out_pos<PL, Q - 1>(l, i))] = (Q == 1) ? x[i] : y[i];
         wave_sync();
-        if constexpr (PL::R3 == 1) {
-            stockham_pass<N, PL::R2, 16, true, DIR, T, LT>(x, row, tw, l);
-        } else {
-            stockham_pass<N, PL::R2, 16, false, DIR, T, LT>(x, row, tw, l);
-            stockham_pass<N, PL::R3, 16 * PL::R2, true, DIR, T, LT>(x, row, tw, l);
-        }
-    }
+#pragma unroll
+        for (int i = 0; i < E; ++i) y[i] = row[lds_pad(in_pos<PL, Q>(l, i))];
+        wave_sync();  // every lane has read before the row is written again
+        stockham_compute<PL, Q, DIR, T, LT>(y, tw, l);
+    });
+    if constexpr (PL::NP > 0) to_canonical<PL, T>(y, x);
 }
 
 // ---------------------------------------------------------------------------
-// Split-exchange variant: the same Stockham passes, but every exchange moves
-// the real parts and then the imaginary parts through a real-valued row
-// buffer (lds_row_elems(N) elements of T), halving the LDS a row needs.
+// Split-exchange variant: the same passes, but every exchange moves the real
+// parts and then the imaginary parts through a real-valued row buffer
+// (lds_row_elems(N) elements of T), halving the LDS a row needs.
 // ---------------------------------------------------------------------------
 
 // Move values from register array `a` (a[i] at row position pa(i)) to
@@ -287,58 +333,35 @@ __device__ __forceinline__ void exchange_split(const cpx<T> (&a)[NA], cpx<T> (&b
     wave_sync();
 }
 
-// Stockham pass of radix R on values already gathered into y (butterfly
-// t of this lane holds inputs y[t R + j] = points b + j N/R, b = l + P t).
-template <int N, int R, int PSTRIDE, int DIR, typename T, bool LT>
-__device__ __forceinline__ void stockham_compute(cpx<T> (&y)[16], Twiddles<T, N, LT> tw, int l) {
-    constexpr int P = N / 16;
-    constexpr int NB = 16 / R;
+template <typename PL, int DIR, typename T, bool LT>
+__device__ __forceinline__ void fft_row_split(cpx<T> (&x)[PL::E], T* row, Twiddles<T, PL, LT> tw, int l) {
+    constexpr int E = PL::E;
+    Dft<E, DIR, T>::run(x);
+    cpx<T> y[E];
+    static_for<PL::NP>([&](auto qc) {
+        constexpr int Q = decltype(qc)::value + 1;
+        if constexpr (Q == 1) {
+            exchange_split<E, E, T>(x, y, row, [&](int i) { return out_pos<PL, 0>(l, i); },
+                                    [&](int i) { return in_pos<PL, 1>(l, i); });
+        } else {
+            cpx<T> z[E];
 #pragma unroll
-    for (int t = 0; t < NB; ++t) {
-        const int k = (l + P * t) & (PSTRIDE - 1);
-#pragma unroll
-        for (int j = 1; j < R; ++j) {
-            cpx<T> w = tw.template get<R, PSTRIDE>(j, k);
-            if (DIR > 0) w.y = -w.y;
-            y[t * R + j] = cmul(y[t * R + j], w);
+            for (int i = 0; i < E; ++i) z[i] = y[i];
+            exchange_split<E, E, T>(z, y, row, [&](int i) { return out_pos<PL, Q - 1>(l, i); },
+                                    [&](int i) { return in_pos<PL, Q>(l, i); });
         }
-        Dft<R, DIR, T>::run(&y[t * R]);
-    }
+        stockham_compute<PL, Q, DIR, T, LT>(y, tw, l);
+    });
+    if constexpr (PL::NP > 0) to_canonical<PL, T>(y, x);
 }
 
-template <int N, int DIR, typename T, bool LT>
-__device__ __forceinline__ void fft_row_split(cpx<T> (&x)[16], T* row, Twiddles<T, N, LT> tw, int l) {
-    using PL = Plan<N>;
-    constexpr int P = N / 16;
-    Dft<16, DIR, T>::run(x);  // pass 1: outputs at points 16 l + j
-    if constexpr (N > 16) {
-        constexpr int R2 = PL::R2, NB2 = 16 / R2;
-        cpx<T> y[16];
-        exchange_split<16, 16, T>(x, y, row, [&](int j) { return 16 * l + j; },
-                                  [&](int i) { return (l + P * (i / R2)) + (i % R2) * (N / R2); });
-        stockham_compute<N, R2, 16, DIR, T, LT>(y, tw, l);
-        if constexpr (PL::R3 == 1) {
-#pragma unroll
-            for (int t = 0; t < NB2; ++t)
-#pragma unroll
-                for (int j = 0; j < R2; ++j) x[t + j * NB2] = y[t * R2 + j];
-        } else {
-            constexpr int R3 = PL::R3, NB3 = 16 / R3, PS3 = 16 * R2;
-            cpx<T> z[16];
-            exchange_split<16, 16, T>(
-                y, z, row,
-                [&](int i) {
-                    const int b = l + P * (i / R2), k = b & 15;
-                    return (b - k) * R2 + k + (i % R2) * 16;
-                },
-                [&](int i) { return (l + P * (i / R3)) + (i % R3) * (N / R3); });
-            stockham_compute<N, R3, PS3, DIR, T, LT>(z, tw, l);
-#pragma unroll
-            for (int t = 0; t < NB3; ++t)
-#pragma unroll
-                for (int j = 0; j < R3; ++j) x[t + j * NB3] = z[t * R3 + j];
-        }
-    }
+// Realisation batching: a launch with gridDim.z = B processes B realisations
+// whose buffers all sit at a fixed byte stride zs from realisation 0's (the
+// twiddle table is shared).  zptr moves a pointer to realisation blockIdx.z.
+template <typename P>
+__device__ __forceinline__ P* zptr(P* p, size_t zs) {
+    using B = std::conditional_t<std::is_const_v<P>, const char, char>;
+    return p ? reinterpret_cast<P*>(reinterpret_cast<B*>(p) + (size_t)blockIdx.z * zs) : p;
 }
 
 // Block-index remap so that consecutive logical blocks (which write adjacent

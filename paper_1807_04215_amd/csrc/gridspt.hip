@@ -1,375 +1,270 @@
 // libgridspt: C ABI (include/gridspt.h) over the gfx950 kernels in
 // passes.hpp and estimators.hpp.  Host code validates arguments, lays out the
-// caller's workspace, and enqueues the pass sequence of each entry point on
-// the context's stream.
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
+// caller's workspace, and enqueues the pass sequences (pipeline.hpp,
+// instantiated per grid size under sizes/) on the context's stream; batches
+// of realisations are captured into one HIP graph.
 #include <array>
-#include <cmath>
-#include <cstdint>
-#include <cstring>
+#include <climits>
 #include <map>
 #include <new>
+#include <set>
 #include <string>
-#include <type_traits>
 #include <utility>
-#include <vector>
 
-#include "../../include/gridspt.h"
-#include "estimators.hpp"
-#include "passes.hpp"
+#include "runtime.hpp"
 
 using namespace gridspt;
 
-// ---------------------------------------------------------------------------
-// context and kernel timing
-// ---------------------------------------------------------------------------
-
-enum Kind {
-    KD_TWIDDLE,
-    KD_ZFWD_FIELD,
-    KD_ZFWD_NOISE,
-    KD_ZFWD_PRODUCTS,
-    KD_YFWD,
-    KD_XFUSED_LINEAR,
-    KD_XFUSED_ORDER1,
-    KD_XFUSED_ORDER,
-    KD_XFUSED_FORWARD,
-    KD_XSHELL,
-    KD_YINV,
-    KD_ZINV,
-    KD_POWER,
-    KD_POWER_FINAL,
-    KD_TRIPLE,
-    KD_TRIPLE_FINAL,
-    KD_BISP_FINAL,
-    KD_SUM_ORDERS,
-    KD_COPY,
-    KD_COUNT
-};
-
-static const char* kKindNames[KD_COUNT] = {
-    "twiddles",     "zfwd_field", "zfwd_noise",    "zfwd_products", "yfwd",         "xfused_linear",
-    "xfused_order1", "xfused_order", "xfused_forward", "xshell",       "yinv",         "zinv",
-    "power_partial", "power_final", "triple_partial", "triple_final", "bisp_final",   "sum_orders",
-    "copy"};
-
-struct Record {
-    int kind;
-    hipEvent_t start, stop;
-    double bytes;
-};
-
-struct gridspt_ctx {
-    hipStream_t stream = nullptr;
-    bool profile = false;
-    std::vector<Record> recs;
-    std::vector<hipEvent_t> pool;
-};
+#define CHECK GRIDSPT_CHECK
 
 namespace {
 
-hipEvent_t take_event(gridspt_ctx* c) {
-    if (!c->pool.empty()) {
-        hipEvent_t e = c->pool.back();
-        c->pool.pop_back();
-        return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-}
-
-// Enqueue one kernel; with profiling on, bracket it with events.
-template <typename Kern, typename... Args>
-int launch(gridspt_ctx* c, int kind, double bytes, dim3 grid, dim3 block, size_t shmem, Kern kern, Args... args) {
-    if (grid.x == 0 || grid.y == 0 || grid.z == 0) return GRIDSPT_OK;
-    Record r{kind, nullptr, nullptr, bytes};
-    if (c->profile) {
-        r.start = take_event(c);
-        r.stop = take_event(c);
-        if (!r.start || !r.stop) return GRIDSPT_EHIP;
-        if (hipEventRecord(r.start, c->stream) != hipSuccess) return GRIDSPT_EHIP;
-    }
-    hipLaunchKernelGGL(kern, grid, block, shmem, c->stream, args...);
-    if (hipGetLastError() != hipSuccess) return GRIDSPT_EHIP;
-    if (c->profile) {
-        if (hipEventRecord(r.stop, c->stream) != hipSuccess) return GRIDSPT_EHIP;
-        c->recs.push_back(r);
-    }
-    return GRIDSPT_OK;
-}
-
-#define CHECK(x)                           \
-    do {                                   \
-        const int rc_ = (x);               \
-        if (rc_ != GRIDSPT_OK) return rc_; \
-    } while (0)
-
 // ---------------------------------------------------------------------------
-// validation and sizes
+// cross spectra: enqueue for one call or a realisation batch
 // ---------------------------------------------------------------------------
 
-constexpr int64_t kAlign = 256;
-
-bool pow2_supported(int n) { return n >= 16 && n <= 1024 && (n & (n - 1)) == 0; }
-
-int64_t isqrt64(int64_t v) {
-    if (v < 0) return -1;
-    int64_t r = (int64_t)std::sqrt((double)v);
-    while (r * r > v) --r;
-    while ((r + 1) * (r + 1) <= v) ++r;
-    return r;
+// per-wave LDS accumulators: nbins * (pairs + 2) doubles, at most 1792 (56 KB per block)
+int power_chunk(int nbins) { return std::max(1, std::min(kPowerPairsPerLaunch, 1792 / nbins - 2)); }
+int power_blocks(const Dims& d) {
+    const int64_t halves = 2 * d.Kz * d.Ky;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (halves + kPowerWaves - 1) / kPowerWaves));
+}
+int64_t power_ws(const Dims& d, int npairs, int nbins) {
+    const int q = std::min(npairs, power_chunk(nbins)) + 2;
+    // block partials, then the reduced sums
+    return align_up((int64_t)power_blocks(d) * nbins * q * 8) + align_up((int64_t)nbins * q * 8);
 }
 
-int check_grid(const gridspt_grid* g) {
-    if (!g) return GRIDSPT_EINVAL;
-    if (g->dtype != GRIDSPT_F32 && g->dtype != GRIDSPT_F64) return GRIDSPT_EINVAL;
-    if (!(g->box > 0.0) || !std::isfinite(g->box)) return GRIDSPT_EINVAL;
-    if (g->n < 2 || (g->n & 1)) return GRIDSPT_EINVAL;
-    if (g->kc < 1 || 2 * (int64_t)g->kc >= g->n) return GRIDSPT_EINVAL;
-    if (!pow2_supported(g->n)) return GRIDSPT_EUNSUPPORTED;
+int check_power_args(int nfields, int npairs, const int32_t* pairs, int nbins, const int64_t* edge_n2) {
+    if (!pairs || !edge_n2) return GRIDSPT_EINVAL;
+    if (nfields < 1 || nfields > kMaxFields || npairs < 1 || npairs > kMaxPairs || nbins < 1 || nbins > kMaxBins)
+        return GRIDSPT_EINVAL;
+    for (int i = 0; i < 2 * npairs; ++i)
+        if (pairs[i] < 0 || pairs[i] >= nfields) return GRIDSPT_EINVAL;
+    if (edge_n2[0] < 1) return GRIDSPT_EINVAL;
+    for (int b = 0; b < nbins; ++b)
+        if (edge_n2[b + 1] < edge_n2[b]) return GRIDSPT_EINVAL;
     return GRIDSPT_OK;
 }
 
-int check_mask(const gridspt_grid* g, int64_t n2max) {
-    if (n2max < 1) return GRIDSPT_EINVAL;
-    const int64_t h = g->n / 2;
-    if (n2max >= h * h) return GRIDSPT_EINVAL;  // the cut must lie below Nyquist
-    if (isqrt64(n2max) > g->kc) return GRIDSPT_EINVAL;
-    return GRIDSPT_OK;
-}
-
-int check_ptr(const void* p) {
-    if (!p) return GRIDSPT_EALIGN;
-    if (reinterpret_cast<uintptr_t>(p) % kAlign) return GRIDSPT_EALIGN;
-    return GRIDSPT_OK;
-}
-
-int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-struct Dims {
-    int64_t N, Kc, Kz, Ky;
-    int64_t real_bytes, cpx_bytes;  // element sizes
-    int64_t ncell() const { return N * N * N; }
-    int64_t s1() const { return Kz * N * N; }  // complex elements per field
-    int64_t s2() const { return Kz * Ky * N; }
-    int64_t s3() const { return Kz * N * Ky; }
-    int64_t s4() const { return N * N * Kz; }
-    int64_t cube() const { return Kz * Ky * Ky; }
-};
-
-Dims dims_of(const gridspt_grid* g) {
-    Dims d;
-    d.N = g->n;
-    d.Kc = g->kc;
-    d.Kz = g->kc + 1;
-    d.Ky = 2 * (int64_t)g->kc + 1;
-    d.real_bytes = g->dtype == GRIDSPT_F64 ? 8 : 4;
-    d.cpx_bytes = 2 * d.real_bytes;
-    return d;
-}
-
-// Workspace of the transform pipeline: twiddles | buffer A (S1, S3) |
-// buffer B (S2, S4) | u_m real fields.  S1/S3 and S2/S4 are never live at once.
-struct Layout {
-    int64_t tw, a, b, u, end;
-    int64_t a_field_s1, a_field_s3, b_field_s2, b_field_s4;  // field strides (elements)
-};
-
-Layout layout_of(const Dims& d, int nmax) {
-    Layout L;
-    L.tw = 0;
-    L.a = align_up(d.N * d.cpx_bytes);
-    const int64_t asz = std::max(4 * d.s1(), 5 * d.s3()) * d.cpx_bytes;
-    L.b = align_up(L.a + asz);
-    const int64_t bsz = std::max(4 * d.s2(), 5 * d.s4()) * d.cpx_bytes;
-    L.u = align_up(L.b + bsz);
-    const int nu = std::max(nmax - 1, 0) * 3;
-    L.end = align_up(L.u + (int64_t)nu * d.ncell() * d.real_bytes);
-    L.a_field_s1 = d.s1();
-    L.a_field_s3 = d.s3();
-    L.b_field_s2 = d.s2();
-    L.b_field_s4 = d.s4();
-    return L;
-}
-
-template <typename T>
-struct tag_t {
-    using type = T;
-};
-
-template <typename F>
-int dispatch(const gridspt_grid* g, F&& f) {
-    auto on_n = [&](auto tag) -> int {
+int power_enqueue(gridspt_ctx* c, const gridspt_grid* g, const void* const* fields_k, int npairs,
+                  const int32_t* pairs, int nbins, const int64_t* edge_n2, double* pk, double* kmean, double* nmodes,
+                  void* work, Batch bt) {
+    const Dims d = dims_of(g);
+    const int nblk = power_blocks(d);
+    const int chunk = power_chunk(nbins);
+    const unsigned nz = (unsigned)bt.nreal;
+    auto go = [&](auto tag) -> int {
         using T = typename decltype(tag)::type;
-        switch (g->n) {
-            case 16: return f(tag, std::integral_constant<int, 16>{});
-            case 32: return f(tag, std::integral_constant<int, 32>{});
-            case 64: return f(tag, std::integral_constant<int, 64>{});
-            case 128: return f(tag, std::integral_constant<int, 128>{});
-            case 256: return f(tag, std::integral_constant<int, 256>{});
-            case 512: return f(tag, std::integral_constant<int, 512>{});
-            case 1024: return f(tag, std::integral_constant<int, 1024>{});
-            default: return GRIDSPT_EUNSUPPORTED;
+        double* partial = static_cast<double*>(work);
+        double* sums = reinterpret_cast<double*>(static_cast<char*>(work) +
+                                                 align_up((int64_t)nblk * nbins * (std::min(npairs, chunk) + 2) * 8));
+        for (int p0 = 0; p0 < npairs; p0 += chunk) {
+            const int np = std::min(chunk, npairs - p0);
+            PowerArgs<T> a{};
+            // distinct fields of this chunk
+            int slot_of[kMaxFields];
+            for (int i = 0; i < kMaxFields; ++i) slot_of[i] = -1;
+            int nf = 0;
+            for (int q = 0; q < np; ++q)
+                for (int k = 0; k < 2; ++k) {
+                    const int f = pairs[2 * (p0 + q) + k];
+                    if (slot_of[f] < 0) {
+                        slot_of[f] = nf;
+                        a.f[nf++] = static_cast<const cpx<T>*>(fields_k[f]);
+                    }
+                }
+            for (int q = 0; q < np; ++q) {
+                a.pa[q] = slot_of[pairs[2 * (p0 + q)]];
+                a.pb[q] = slot_of[pairs[2 * (p0 + q) + 1]];
+            }
+            for (int b = 0; b <= nbins; ++b) a.edges[b] = edge_n2[b];
+            a.nf = nf;
+            a.npairs = np;
+            a.nbins = nbins;
+            a.kF = 2.0 * M_PI / g->box;
+            a.partial = partial;
+            const int nq = np + 2;
+            const size_t shm = (size_t)kPowerWaves * nbins * nq * sizeof(double);
+            CHECK(launch(c, KD_POWER, (double)nz * nf * d.cube() * d.cpx_bytes, dim3(nblk, 1, nz),
+                         dim3(64 * kPowerWaves), shm, k_power_partial<T>, a,
+                         CubeDims{(int)d.Kc, (int)d.Kz, (int)d.Ky}, bt.zs));
+            CHECK(launch(c, KD_POWER_FINAL, (double)nz * nblk * nbins * nq * 8.0, dim3(nbins * nq, 1, nz),
+                         dim3(kReduceThreads), 0, k_power_reduce, (const double*)partial, nblk, nq, sums, bt.zs));
+            CHECK(launch(c, KD_POWER_FINAL, 0.0, dim3((nbins + 63) / 64, 1, nz), dim3(64), 0, k_power_final,
+                         (const double*)sums, nbins, np, g->box * g->box * g->box, pk + (size_t)p0 * nbins, nbins,
+                         p0 == 0 ? kmean : nullptr, p0 == 0 ? nmodes : nullptr, bt.zs));
         }
-        (void)sizeof(T);
+        return GRIDSPT_OK;
     };
-    if (g->dtype == GRIDSPT_F64) return on_n(tag_t<double>{});
-    return on_n(tag_t<float>{});
+    if (g->dtype == GRIDSPT_F64) return go(tag_t<double>{});
+    return go(tag_t<float>{});
 }
 
 // ---------------------------------------------------------------------------
-// pass sequences
+// bispectrum: slots (field or indicator restricted to a shell) are made in
+// chunks of triangles, at most `cap` distinct slots per chunk, and consumed
+// by the triple sums of that chunk's terms and triangles
 // ---------------------------------------------------------------------------
 
-template <typename T, int N>
-struct Pipe {
-    using RW = Rows<T, N>;
-    gridspt_ctx* c;
-    Dims d;
-    Layout L;
-    char* ws;
-    CubeDims cd;
-
-    Pipe(gridspt_ctx* ctx, const gridspt_grid* g, void* work, int nmax) : c(ctx), d(dims_of(g)) {
-        L = layout_of(d, nmax);
-        ws = static_cast<char*>(work);
-        cd = {(int)d.Kc, (int)d.Kz, (int)d.Ky};
-    }
-    cpx<T>* tw() const { return reinterpret_cast<cpx<T>*>(ws + L.tw); }
-    cpx<T>* A() const { return reinterpret_cast<cpx<T>*>(ws + L.a); }
-    cpx<T>* B() const { return reinterpret_cast<cpx<T>*>(ws + L.b); }
-    T* U(int m, int j) const {  // u_m component j, m >= 1
-        return reinterpret_cast<T*>(ws + L.u) + ((size_t)(m - 1) * 3 + j) * (size_t)d.ncell();
-    }
-
-    int twiddles() {
-        return launch(c, KD_TWIDDLE, (double)N * d.cpx_bytes, dim3((N + 255) / 256), dim3(256), 0, k_twiddles<T>,
-                      tw(), N);
-    }
-
-    // P1 from a real field (SRC 0) or from noise (SRC 1) -> S1 field 0 in A
-    int zfwd_single(const T* f, bool noise, uint64_t seed, uint64_t stream) {
-        ProductInputs<T> pin{};
-        const double bytes = (noise ? 0.0 : (double)d.ncell() * d.real_bytes) + (double)d.s1() * d.cpx_bytes;
-        const dim3 grid(N * (N / (2 * RW::RPB))), block(RW::THREADS);  // two rows per transform
-        if (noise)
-            return launch(c, KD_ZFWD_NOISE, bytes, grid, block, 0, k_zfwd<T, N, 1, 0>, f, pin, seed, stream, A(),
-                          (size_t)L.a_field_s1, (const cpx<T>*)tw(), (int)d.Kz);
-        return launch(c, KD_ZFWD_FIELD, bytes, grid, block, 0, k_zfwd<T, N, 0, 0>, f, pin, seed, stream, A(),
-                      (size_t)L.a_field_s1, (const cpx<T>*)tw(), (int)d.Kz);
-    }
-
-    // P1 with the products of order n -> S1 fields 0..3 (V_x, V_y, V_z, W) in A
-    int zfwd_products(int n, const ProductInputs<T>& pin) {
-        const double bytes = 4.0 * (n - 1) * d.ncell() * d.real_bytes + 4.0 * d.s1() * d.cpx_bytes;
-        const dim3 grid(N * (N / RW::RPB)), block(RW::THREADS);
-        auto go = [&](auto kern) {
-            return launch(c, KD_ZFWD_PRODUCTS, bytes, grid, block, 0, kern, (const T*)nullptr, pin, (uint64_t)0,
-                          (uint64_t)0, A(), (size_t)L.a_field_s1, (const cpx<T>*)tw(), (int)d.Kz);
-        };
-        switch (n) {
-            case 2: return go(k_zfwd<T, N, 2, 2>);
-            case 3: return go(k_zfwd<T, N, 2, 3>);
-            case 4: return go(k_zfwd<T, N, 2, 4>);
-            case 5: return go(k_zfwd<T, N, 2, 5>);
-            default: return GRIDSPT_EINVAL;
-        }
-    }
-
-    // P2: nf fields S1 (A) -> S2 (B)
-    int yfwd(int nf) {
-        const double bytes = (double)nf * (d.s1() + d.s2()) * d.cpx_bytes;
-        return launch(c, KD_YFWD, bytes, dim3((unsigned)(d.Kz * (N / RW::RPB)), nf), dim3(RW::THREADS), 0,
-                      k_yfwd<T, N>, (const cpx<T>*)A(), (size_t)L.a_field_s1, B(), (size_t)L.b_field_s2,
-                      (const cpx<T>*)tw(), cd);
-    }
-
-    // P3: S2 (B) -> S3 (A), with the k-space step of `mode`
-    int xfused(int mode, XArgs<T> a) {
-        a.s2 = B();
-        a.s2_field = (size_t)L.b_field_s2;
-        a.s3 = A();
-        a.s3_field = (size_t)L.a_field_s3;
-        const int nin = mode == XM_ORDER ? 4 : 1;
-        const int ncube = (a.cube_d ? 1 : 0) + (a.cube_t ? 1 : 0);
-        const double bytes =
-            ((double)nin * d.s2() + (double)a.nout * d.s3() + (double)ncube * d.cube()) * d.cpx_bytes;
-        const dim3 grid((unsigned)(d.Kz * ((d.Ky + RW::RPB - 1) / RW::RPB))), block(RW::THREADS);
-        const cpx<T>* t = tw();
-        switch (mode) {
-            case XM_ORDER: return launch(c, KD_XFUSED_ORDER, bytes, grid, block, 0, k_xfused<T, N, XM_ORDER>, a, t, cd);
-            case XM_ORDER1:
-                return launch(c, KD_XFUSED_ORDER1, bytes, grid, block, 0, k_xfused<T, N, XM_ORDER1>, a, t, cd);
-            case XM_LINEAR:
-                return launch(c, KD_XFUSED_LINEAR, bytes, grid, block, 0, k_xfused<T, N, XM_LINEAR>, a, t, cd);
-            default:
-                return launch(c, KD_XFUSED_FORWARD, bytes, grid, block, 0, k_xfused<T, N, XM_FORWARD>, a, t, cd);
-        }
-    }
-
-    // P3 for shells: nslot cube fields -> S3 (A)
-    int xshell(ShellSlots<T> s, int nslot) {
-        s.s3 = A();
-        s.s3_field = (size_t)L.a_field_s3;
-        int ncube = 0;
-        for (int i = 0; i < nslot; ++i) ncube += s.cube[i] ? 1 : 0;
-        const double bytes = ((double)ncube * d.cube() + (double)nslot * d.s3()) * d.cpx_bytes;
-        return launch(c, KD_XSHELL, bytes, dim3((unsigned)(d.Kz * ((d.Ky + RW::RPB - 1) / RW::RPB)), nslot),
-                      dim3(RW::THREADS), 0, k_xshell<T, N>, s, (const cpx<T>*)tw(), cd);
-    }
-
-    // P4: nf fields S3 (A) -> S4 (B)
-    int yinv(int nf) {
-        const double bytes = (double)nf * (d.s3() + d.s4()) * d.cpx_bytes;
-        return launch(c, KD_YINV, bytes, dim3((unsigned)(N * ((d.Kz + RW::RPB - 1) / RW::RPB)), nf),
-                      dim3(RW::THREADS), 0, k_yinv<T, N>, (const cpx<T>*)A(), (size_t)L.a_field_s3, B(),
-                      (size_t)L.b_field_s4, (const cpx<T>*)tw(), cd);
-    }
-
-    // P5: S4 (B) -> real outputs, two real rows per complex transform
-    int zinv(const ZJobs<T>& zj, int njobs) {
-        int nout = 0;
-        for (int i = 0; i < njobs; ++i) nout += zj.fb[i] >= 0 ? 2 : 1;
-        const double bytes = (double)nout * ((double)d.s4() * d.cpx_bytes + (double)d.ncell() * d.real_bytes);
-        return launch(c, KD_ZINV, bytes, dim3((unsigned)(N * N / RW::RPB), njobs), dim3(RW::THREADS), 0,
-                      k_zinv<T, N>, (const cpx<T>*)B(), (size_t)L.b_field_s4, zj, (const cpx<T>*)tw(), cd);
-    }
-
-    // P4 + P5 for nf fields of S3 into real outputs out[0..nf-1]: fields two
-    // by two, an odd last field two rows at a time
-    int to_real(int nf, T* const* out) {
-        CHECK(yinv(nf));
-        ZJobs<T> zj{};
-        int nj = 0;
-        for (int i = 0; i < nf; i += 2, ++nj) {
-            zj.fa[nj] = i;
-            zj.outa[nj] = out[i];
-            zj.fb[nj] = (i + 1 < nf) ? i + 1 : -1;
-            zj.outb[nj] = (i + 1 < nf) ? out[i + 1] : nullptr;
-        }
-        return zinv(zj, nj);
-    }
-
-    int copy(const T* src, T* dst) {
-        return launch(c, KD_COPY, 2.0 * d.ncell() * d.real_bytes, dim3(2048), dim3(256), 0, k_copy<T>, src, dst,
-                      (size_t)d.ncell());
-    }
+struct BispChunk {
+    std::vector<std::pair<int, int>> slots;  // (field, or -1 for the indicator; bin)
+    std::vector<std::array<int, 4>> titems;  // slots a, b, c; term index
+    std::vector<std::array<int, 4>> jitems;  // slots a, b, c; triangle index
+};
+struct BispPlan {
+    std::vector<BispChunk> chunks;
+    int max_slots = 0;
 };
 
-template <typename T>
-XArgs<T> make_xargs(const Dims& d, int n, int nout, int64_t n2max, cpx<T>* cube_d, cpx<T>* cube_t) {
-    XArgs<T> a{};
-    a.cube_d = cube_d;
-    a.cube_t = cube_t;
-    a.n = n;
-    a.nout = nout;
-    a.n2max = n2max;
-    a.kF = 2.0 * M_PI;  // replaced by the caller with 2 pi / L
-    a.invN3 = 1.0 / ((double)d.N * d.N * d.N);
-    return a;
+constexpr int kTripleBlocks = 1024;
+
+int check_bisp_args(int nfields, int ntri, const int32_t* tri_bins, int nterms, const int32_t* terms, int nbins,
+                    const int64_t* edge_n2) {
+    if (!tri_bins || !terms || !edge_n2) return GRIDSPT_EINVAL;
+    if (nfields < 1 || nfields > kMaxFields || ntri < 1 || nterms < 1 || nbins < 1 || nbins > kMaxBins)
+        return GRIDSPT_EINVAL;
+    if (ntri > 4096 || nterms > 16384) return GRIDSPT_EINVAL;
+    for (int t = 0; t < 3 * ntri; ++t)
+        if (tri_bins[t] < 0 || tri_bins[t] >= nbins) return GRIDSPT_EINVAL;
+    for (int u = 0; u < nterms; ++u) {
+        for (int i = 0; i < 3; ++i)
+            if (terms[4 * u + i] < 0 || terms[4 * u + i] >= nfields) return GRIDSPT_EINVAL;
+        if (terms[4 * u + 3] < 0 || terms[4 * u + 3] >= ntri) return GRIDSPT_EINVAL;
+    }
+    if (edge_n2[0] < 1) return GRIDSPT_EINVAL;
+    for (int b = 0; b < nbins; ++b)
+        if (edge_n2[b + 1] < edge_n2[b]) return GRIDSPT_EINVAL;
+    return GRIDSPT_OK;
+}
+
+// terms and triangles are assumed validated
+BispPlan bisp_make_plan(int ntri, const int32_t* tri_bins, int nterms, const int32_t* terms, int cap) {
+    std::vector<std::vector<int>> terms_of(ntri);
+    for (int u = 0; u < nterms; ++u) terms_of[terms[4 * u + 3]].push_back(u);
+    BispPlan bp;
+    std::map<std::pair<int, int>, int> index;
+    std::vector<int> tris;
+    auto flush = [&]() {
+        if (tris.empty()) return;
+        BispChunk ch;
+        ch.slots.resize(index.size());
+        for (auto& kv : index) ch.slots[kv.second] = kv.first;
+        for (int t : tris) {
+            const int* b = tri_bins + 3 * t;
+            ch.jitems.push_back({index[{-1, b[0]}], index[{-1, b[1]}], index[{-1, b[2]}], t});
+            for (int u : terms_of[t]) {
+                const int* f = terms + 4 * u;
+                ch.titems.push_back({index[{f[0], b[0]}], index[{f[1], b[1]}], index[{f[2], b[2]}], u});
+            }
+        }
+        bp.max_slots = std::max(bp.max_slots, (int)ch.slots.size());
+        bp.chunks.push_back(std::move(ch));
+        index.clear();
+        tris.clear();
+    };
+    for (int t = 0; t < ntri; ++t) {
+        std::set<std::pair<int, int>> need;
+        const int* b = tri_bins + 3 * t;
+        for (int i = 0; i < 3; ++i) need.insert({-1, b[i]});
+        for (int u : terms_of[t])
+            for (int i = 0; i < 3; ++i) need.insert({terms[4 * u + i], b[i]});
+        int fresh = 0;
+        for (auto& k : need) fresh += index.count(k) ? 0 : 1;
+        if (!tris.empty() && (int)index.size() + fresh > cap) flush();
+        for (auto& k : need)
+            if (!index.count(k)) {
+                const int s = (int)index.size();
+                index[k] = s;
+            }
+        tris.push_back(t);
+    }
+    flush();
+    return bp;
+}
+
+// scratch of the estimator: slots | triple partials | sums (nterms + ntri),
+// after a pipeline workspace (layout_of(d, 1)) in the single-call API
+struct BispLayout {
+    int64_t slots, partial, sums, end;
+};
+BispLayout bisp_layout(const Dims& d, const BispPlan& bp, int nterms, int ntri, int64_t start) {
+    BispLayout b;
+    b.slots = start;
+    b.partial = align_up(b.slots + (int64_t)bp.max_slots * d.ncell() * d.real_bytes);
+    b.sums = align_up(b.partial + (int64_t)kTripleBlocks * 8 * 8);
+    b.end = align_up(b.sums + (int64_t)(nterms + ntri) * 8);
+    return b;
+}
+
+// pipe: a pipeline workspace (layout_of(d, 1) or larger); scratch: the
+// estimator's own region (bisp_layout from 0)
+int bisp_enqueue(gridspt_ctx* c, const gridspt_grid* g, const void* const* fields_k, const BispPlan& bp, int ntri,
+                 int nterms, const int32_t* terms, const int64_t* edge_n2, double* bk, double* ntriangles, void* pipe,
+                 void* scratch, const Tuning& tu, Batch bt) {
+    const Dims d = dims_of(g);
+    const BispLayout bl = bisp_layout(d, bp, nterms, ntri, 0);
+    char* base = static_cast<char*>(scratch);
+    double* partial = reinterpret_cast<double*>(base + bl.partial);
+    double* sums = reinterpret_cast<double*>(base + bl.sums);
+    const unsigned nz = (unsigned)bt.nreal;
+    for (const BispChunk& ch : bp.chunks) {
+        const int ns = (int)ch.slots.size();
+        std::vector<const void*> cubes(ns);
+        std::vector<int64_t> lo(ns), hi(ns);
+        std::vector<void*> outs(ns);
+        for (int i = 0; i < ns; ++i) {
+            const auto& sl = ch.slots[i];
+            cubes[i] = sl.first >= 0 ? fields_k[sl.first] : nullptr;
+            lo[i] = edge_n2[sl.second];
+            hi[i] = edge_n2[sl.second + 1];
+            outs[i] = base + bl.slots + (int64_t)i * d.ncell() * d.real_bytes;
+        }
+        CHECK(dispatch(g, [&](auto tag, auto nc) -> int {
+            using T = typename decltype(tag)::type;
+            constexpr int N = decltype(nc)::value;
+            return run_shells<T, N>(c, g, ns, cubes.data(), lo.data(), hi.data(), outs.data(), pipe, tu, bt);
+        }));
+        auto triple = [&](const std::vector<std::array<int, 4>>& items, double* dst) -> int {
+            auto go = [&](auto tag) -> int {
+                using T = typename decltype(tag)::type;
+                for (size_t u0 = 0; u0 < items.size(); u0 += 8) {
+                    TripleArgs<T> t{};
+                    TripleDst td{};
+                    t.nterms = (int)std::min<size_t>(8, items.size() - u0);
+                    t.ncell = (size_t)d.ncell();
+                    t.partial = partial;
+                    for (int i = 0; i < t.nterms; ++i) {
+                        t.a[i] = static_cast<const T*>(outs[items[u0 + i][0]]);
+                        t.b[i] = static_cast<const T*>(outs[items[u0 + i][1]]);
+                        t.c[i] = static_cast<const T*>(outs[items[u0 + i][2]]);
+                        td.idx[i] = items[u0 + i][3];
+                    }
+                    CHECK(launch(c, KD_TRIPLE, (double)nz * 3.0 * t.nterms * d.ncell() * d.real_bytes,
+                                 dim3(kTripleBlocks, 1, nz), dim3(kTripleThreads), 0, k_triple_partial<T>, t, bt.zs));
+                    CHECK(launch(c, KD_TRIPLE_FINAL, (double)nz * kTripleBlocks * 8.0 * 8.0, dim3(1, 1, nz), dim3(64),
+                                 0, k_triple_final, (const double*)partial, kTripleBlocks, t.nterms, td, dst, bt.zs));
+                }
+                return GRIDSPT_OK;
+            };
+            if (g->dtype == GRIDSPT_F64) return go(tag_t<double>{});
+            return go(tag_t<float>{});
+        };
+        CHECK(triple(ch.titems, sums));
+        CHECK(triple(ch.jitems, sums + nterms));
+    }
+    // bk = L^6 T / J per term, the term -> triangle map in the argument buffer
+    const double vol2 = std::pow(g->box, 6);
+    const double invN3 = 1.0 / (double)d.ncell();
+    for (int u0 = 0; u0 < std::max(nterms, ntri); u0 += 64) {
+        TriMap m{};
+        const int nu = std::max(0, std::min(64, nterms - u0));
+        const int nt = std::max(0, std::min(64, ntri - u0));
+        for (int i = 0; i < nu; ++i) m.tri[i] = terms[4 * (u0 + i) + 3];
+        CHECK(launch(c, KD_BISP_FINAL, 0.0, dim3(1, 1, nz), dim3(64), 0, k_bisp_final, (const double*)sums,
+                     (const double*)(sums + nterms), m, u0, nu, nt, vol2, invN3, bk, ntriangles, bt.zs));
+    }
+    return GRIDSPT_OK;
 }
 
 }  // namespace
@@ -560,31 +455,29 @@ int64_t gridspt_workspace_bytes(const gridspt_grid* g, int32_t nmax) {
     return layout_of(dims_of(g), nmax).end;
 }
 
+static int check_linpk(const gridspt_grid* g, const gridspt_linpk* lp) {
+    if (!lp) return GRIDSPT_EINVAL;
+    CHECK(check_mask(g, lp->n2max));
+    if (!(lp->amp >= 0.0) || !(lp->gamma > 0.0) || !std::isfinite(lp->ns) || !std::isfinite(lp->growth))
+        return GRIDSPT_EINVAL;
+    return GRIDSPT_OK;
+}
+
 int gridspt_linear_field(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, void* delta1,
                          void* delta1_k, void* work, int64_t work_bytes) {
     if (!c || !lp) return GRIDSPT_EINVAL;
     CHECK(check_grid(g));
-    CHECK(check_mask(g, lp->n2max));
-    if (!(lp->amp >= 0.0) || !(lp->gamma > 0.0) || !std::isfinite(lp->ns) || !std::isfinite(lp->growth))
-        return GRIDSPT_EINVAL;
+    CHECK(check_linpk(g, lp));
     CHECK(check_ptr(delta1));
     if (delta1_k) CHECK(check_ptr(delta1_k));
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
     if (work_bytes < gridspt_workspace_bytes(g, 1)) return GRIDSPT_EWORKSPACE;
+    const Tuning tu{};
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
         constexpr int N = decltype(nc)::value;
-        Pipe<T, N> p(c, g, work, 1);
-        CHECK(p.twiddles());
-        CHECK(p.zfwd_single(nullptr, true, lp->seed, lp->stream));
-        CHECK(p.yfwd(1));
-        XArgs<T> a = make_xargs<T>(p.d, 1, 1, lp->n2max, (cpx<T>*)delta1_k, nullptr);
-        a.kF = 2.0 * M_PI / g->box;
-        a.lin = {lp->amp, lp->ns, lp->gamma, lp->growth, (double)N * N * N / (g->box * g->box * g->box)};
-        CHECK(p.xfused(XM_LINEAR, a));
-        T* out[1] = {static_cast<T*>(delta1)};
-        return p.to_real(1, out);
+        return run_linear_field<T, N>(c, g, lp, delta1, delta1_k, work, tu, Batch{});
     });
 }
 
@@ -598,16 +491,11 @@ int gridspt_forward(gridspt_ctx* c, const gridspt_grid* g, int64_t n2max, const 
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
     if (work_bytes < gridspt_workspace_bytes(g, 1)) return GRIDSPT_EWORKSPACE;
+    const Tuning tu{};
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
         constexpr int N = decltype(nc)::value;
-        Pipe<T, N> p(c, g, work, 1);
-        CHECK(p.twiddles());
-        CHECK(p.zfwd_single(static_cast<const T*>(field), false, 0, 0));
-        CHECK(p.yfwd(1));
-        XArgs<T> a = make_xargs<T>(p.d, 1, 0, n2max, (cpx<T>*)field_k, nullptr);
-        a.kF = 2.0 * M_PI / g->box;
-        return p.xfused(XM_FORWARD, a);
+        return run_forward<T, N>(c, g, n2max, field, field_k, work, tu, Batch{});
     });
 }
 
@@ -631,47 +519,12 @@ int gridspt_orders(gridspt_ctx* c, const gridspt_grid* g, int32_t nmax, int64_t 
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
     if (work_bytes < gridspt_workspace_bytes(g, nmax)) return GRIDSPT_EWORKSPACE;
+    const Tuning tu{};
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
         constexpr int N = decltype(nc)::value;
-        Pipe<T, N> p(c, g, work, nmax);
-        const double kF = 2.0 * M_PI / g->box;
-        auto dk = [&](int i) { return delta_k ? (cpx<T>*)delta_k[i] : nullptr; };
-        auto tk = [&](int i) { return theta_k ? (cpx<T>*)theta_k[i] : nullptr; };
-        CHECK(p.twiddles());
-
-        // order 1: delta_1 = theta_1 = W1 delta1_in; u_1 = (-ik/k^2) delta_1
-        CHECK(p.zfwd_single(static_cast<const T*>(delta1), false, 0, 0));
-        CHECK(p.yfwd(1));
-        {
-            const int nout = nmax > 1 ? 4 : 1;
-            cpx<T>* ct = (tk(0) && tk(0) != dk(0)) ? tk(0) : nullptr;
-            XArgs<T> a = make_xargs<T>(p.d, 1, nout, n2max1, dk(0), ct);
-            a.kF = kF;
-            CHECK(p.xfused(XM_ORDER1, a));
-            T* out[4] = {static_cast<T*>(delta[0]), p.U(1, 0), p.U(1, 1), p.U(1, 2)};
-            CHECK(p.to_real(nout, out));
-            if (theta[0] && theta[0] != delta[0]) CHECK(p.copy(static_cast<const T*>(delta[0]), static_cast<T*>(theta[0])));
-        }
-        // orders n >= 2
-        for (int n = 2; n <= nmax; ++n) {
-            ProductInputs<T> pin{};
-            for (int m = 1; m < n; ++m) {
-                pin.d[m - 1] = static_cast<const T*>(delta[m - 1]);
-                for (int j = 0; j < 3; ++j) pin.u[m - 1][j] = p.U(m, j);
-            }
-            CHECK(p.zfwd_products(n, pin));
-            CHECK(p.yfwd(4));
-            const int nout = n < nmax ? 5 : 2;
-            XArgs<T> a = make_xargs<T>(p.d, n, nout, n2max2, dk(n - 1), tk(n - 1));
-            a.kF = kF;
-            CHECK(p.xfused(XM_ORDER, a));
-            T* out[5] = {static_cast<T*>(delta[n - 1]), static_cast<T*>(theta[n - 1]), nullptr, nullptr, nullptr};
-            if (n < nmax)
-                for (int j = 0; j < 3; ++j) out[2 + j] = p.U(n, j);
-            CHECK(p.to_real(nout, out));
-        }
-        return GRIDSPT_OK;
+        return run_orders<T, N>(c, g, nmax, n2max1, n2max2, delta1, delta, theta, delta_k, theta_k, work, tu,
+                                Batch{});
     });
 }
 
@@ -700,37 +553,19 @@ int gridspt_sum_orders(gridspt_ctx* c, const gridspt_grid* g, int32_t nmax, cons
     return go(tag_t<float>{});
 }
 
-// per-wave LDS accumulators: nbins * (pairs + 2) doubles, at most 1792 (56 KB per block)
-static int power_chunk(int nbins) {
-    return std::max(1, std::min(kPowerPairsPerLaunch, 1792 / nbins - 2));
-}
-static int power_blocks(const Dims& d) {
-    const int64_t halves = 2 * d.Kz * d.Ky;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (halves + kPowerWaves - 1) / kPowerWaves));
-}
-
 int64_t gridspt_power_workspace_bytes(const gridspt_grid* g, int32_t npairs, int32_t nbins) {
     const int rc = check_grid(g);
     if (rc != GRIDSPT_OK) return rc;
     if (npairs < 1 || npairs > kMaxPairs || nbins < 1 || nbins > kMaxBins) return GRIDSPT_EINVAL;
-    const Dims d = dims_of(g);
-    const int q = std::min(npairs, power_chunk(nbins)) + 2;
-    // block partials, then the reduced sums
-    return align_up((int64_t)power_blocks(d) * nbins * q * 8) + align_up((int64_t)nbins * q * 8);
+    return power_ws(dims_of(g), npairs, nbins);
 }
 
 int gridspt_power(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, const void* const* fields_k,
                   int32_t npairs, const int32_t* pairs, int32_t nbins, const int64_t* edge_n2, double* pk,
                   double* kmean, double* nmodes, void* work, int64_t work_bytes) {
-    if (!c || !fields_k || !pairs || !edge_n2) return GRIDSPT_EINVAL;
+    if (!c || !fields_k) return GRIDSPT_EINVAL;
     CHECK(check_grid(g));
-    if (nfields < 1 || nfields > kMaxFields || npairs < 1 || npairs > kMaxPairs || nbins < 1 || nbins > kMaxBins)
-        return GRIDSPT_EINVAL;
-    for (int i = 0; i < 2 * npairs; ++i)
-        if (pairs[i] < 0 || pairs[i] >= nfields) return GRIDSPT_EINVAL;
-    if (edge_n2[0] < 1) return GRIDSPT_EINVAL;
-    for (int b = 0; b < nbins; ++b)
-        if (edge_n2[b + 1] < edge_n2[b]) return GRIDSPT_EINVAL;
+    CHECK(check_power_args(nfields, npairs, pairs, nbins, edge_n2));
     for (int i = 0; i < nfields; ++i) CHECK(check_ptr(fields_k[i]));
     CHECK(check_ptr(pk));
     if (kmean) CHECK(check_ptr(kmean));
@@ -738,205 +573,436 @@ int gridspt_power(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, const 
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
     if (work_bytes < gridspt_power_workspace_bytes(g, npairs, nbins)) return GRIDSPT_EWORKSPACE;
-    const Dims d = dims_of(g);
-    const int nblk = power_blocks(d);
-    const int chunk = power_chunk(nbins);
-    auto go = [&](auto tag) -> int {
-        using T = typename decltype(tag)::type;
-        double* partial = static_cast<double*>(work);
-        double* sums = reinterpret_cast<double*>(static_cast<char*>(work) +
-                                                 align_up((int64_t)nblk * nbins * (std::min(npairs, chunk) + 2) * 8));
-        for (int p0 = 0; p0 < npairs; p0 += chunk) {
-            const int np = std::min(chunk, npairs - p0);
-            PowerArgs<T> a{};
-            // distinct fields of this chunk
-            int slot_of[kMaxFields];
-            for (int i = 0; i < kMaxFields; ++i) slot_of[i] = -1;
-            int nf = 0;
-            for (int q = 0; q < np; ++q)
-                for (int k = 0; k < 2; ++k) {
-                    const int f = pairs[2 * (p0 + q) + k];
-                    if (slot_of[f] < 0) {
-                        slot_of[f] = nf;
-                        a.f[nf++] = static_cast<const cpx<T>*>(fields_k[f]);
-                    }
-                }
-            for (int q = 0; q < np; ++q) {
-                a.pa[q] = slot_of[pairs[2 * (p0 + q)]];
-                a.pb[q] = slot_of[pairs[2 * (p0 + q) + 1]];
-            }
-            for (int b = 0; b <= nbins; ++b) a.edges[b] = edge_n2[b];
-            a.nf = nf;
-            a.npairs = np;
-            a.nbins = nbins;
-            a.kF = 2.0 * M_PI / g->box;
-            a.partial = partial;
-            const int nq = np + 2;
-            const size_t shm = (size_t)kPowerWaves * nbins * nq * sizeof(double);
-            CHECK(launch(c, KD_POWER, (double)nf * d.cube() * d.cpx_bytes, dim3(nblk), dim3(64 * kPowerWaves), shm,
-                         k_power_partial<T>, a, CubeDims{(int)d.Kc, (int)d.Kz, (int)d.Ky}));
-            CHECK(launch(c, KD_POWER_FINAL, (double)nblk * nbins * nq * 8.0, dim3(nbins * nq), dim3(kReduceThreads),
-                         0, k_power_reduce, (const double*)partial, nblk, nq, sums));
-            CHECK(launch(c, KD_POWER_FINAL, 0.0, dim3((nbins + 63) / 64), dim3(64), 0, k_power_final,
-                         (const double*)sums, nbins, np, g->box * g->box * g->box, pk + (size_t)p0 * nbins, nbins,
-                         p0 == 0 ? kmean : nullptr, p0 == 0 ? nmodes : nullptr));
-        }
-        return GRIDSPT_OK;
-    };
-    if (g->dtype == GRIDSPT_F64) return go(tag_t<double>{});
-    return go(tag_t<float>{});
+    return power_enqueue(c, g, fields_k, npairs, pairs, nbins, edge_n2, pk, kmean, nmodes, work, Batch{});
 }
-
-// ---------------------------------------------------------------------------
-// bispectrum
-// ---------------------------------------------------------------------------
-
-namespace {
-
-struct BispPlan {
-    std::vector<std::pair<int, int>> slots;  // (field or -1 for the indicator, bin)
-    std::map<std::pair<int, int>, int> index;
-    int slot(int f, int b) {
-        auto key = std::make_pair(f, b);
-        auto it = index.find(key);
-        if (it != index.end()) return it->second;
-        const int s = (int)slots.size();
-        slots.push_back(key);
-        index[key] = s;
-        return s;
-    }
-};
-
-constexpr int kTripleBlocks = 1024;
-
-int bisp_plan(int ntri, const int32_t* tri_bins, int nterms, const int32_t* terms, BispPlan& bp) {
-    for (int t = 0; t < ntri; ++t)
-        for (int i = 0; i < 3; ++i) bp.slot(-1, tri_bins[3 * t + i]);
-    for (int u = 0; u < nterms; ++u) {
-        const int t = terms[4 * u + 3];
-        for (int i = 0; i < 3; ++i) bp.slot(terms[4 * u + i], tri_bins[3 * t + i]);
-    }
-    return GRIDSPT_OK;
-}
-
-int64_t bisp_bytes(const Dims& d, int nslots) {
-    const Layout L = layout_of(d, 1);
-    int64_t off = L.end;
-    off = align_up(off + (int64_t)nslots * d.ncell() * d.real_bytes);
-    off = align_up(off + (int64_t)kTripleBlocks * 8 * 8);
-    return off;
-}
-
-}  // namespace
 
 int64_t gridspt_bispectrum_workspace_bytes(const gridspt_grid* g, int32_t ntri, const int32_t* tri_bins,
                                            int32_t nterms, const int32_t* terms) {
     const int rc = check_grid(g);
     if (rc != GRIDSPT_OK) return rc;
-    if (ntri < 1 || nterms < 1 || !tri_bins || !terms) return GRIDSPT_EINVAL;
-    BispPlan bp;
+    if (ntri < 1 || nterms < 1 || !tri_bins || !terms || ntri > 4096 || nterms > 16384) return GRIDSPT_EINVAL;
+    for (int t = 0; t < 3 * ntri; ++t)
+        if (tri_bins[t] < 0) return GRIDSPT_EINVAL;
     for (int u = 0; u < nterms; ++u)
         if (terms[4 * u + 3] < 0 || terms[4 * u + 3] >= ntri) return GRIDSPT_EINVAL;
-    bisp_plan(ntri, tri_bins, nterms, terms, bp);
-    return bisp_bytes(dims_of(g), (int)bp.slots.size());
+    const BispPlan bp = bisp_make_plan(ntri, tri_bins, nterms, terms, INT_MAX);
+    const Dims d = dims_of(g);
+    return bisp_layout(d, bp, nterms, ntri, layout_of(d, 1).end).end;
 }
 
 int gridspt_bispectrum(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, const void* const* fields_k,
                        int32_t ntri, const int32_t* tri_bins, int32_t nterms, const int32_t* terms, int32_t nbins,
                        const int64_t* edge_n2, double* bk, double* ntriangles, void* work, int64_t work_bytes) {
-    if (!c || !fields_k || !tri_bins || !terms || !edge_n2) return GRIDSPT_EINVAL;
+    if (!c || !fields_k) return GRIDSPT_EINVAL;
     CHECK(check_grid(g));
-    if (nfields < 1 || nfields > kMaxFields || ntri < 1 || nterms < 1 || nbins < 1 || nbins > kMaxBins)
-        return GRIDSPT_EINVAL;
-    if (ntri > 4096 || nterms > 16384) return GRIDSPT_EINVAL;
-    for (int t = 0; t < 3 * ntri; ++t)
-        if (tri_bins[t] < 0 || tri_bins[t] >= nbins) return GRIDSPT_EINVAL;
-    for (int u = 0; u < nterms; ++u) {
-        for (int i = 0; i < 3; ++i)
-            if (terms[4 * u + i] < 0 || terms[4 * u + i] >= nfields) return GRIDSPT_EINVAL;
-        if (terms[4 * u + 3] < 0 || terms[4 * u + 3] >= ntri) return GRIDSPT_EINVAL;
-    }
-    if (edge_n2[0] < 1) return GRIDSPT_EINVAL;
-    for (int b = 0; b < nbins; ++b)
-        if (edge_n2[b + 1] < edge_n2[b]) return GRIDSPT_EINVAL;
+    CHECK(check_bisp_args(nfields, ntri, tri_bins, nterms, terms, nbins, edge_n2));
     if (isqrt64(edge_n2[nbins] - 1) > g->kc) return GRIDSPT_EINVAL;  // shells must lie inside the cube
     for (int i = 0; i < nfields; ++i) CHECK(check_ptr(fields_k[i]));
     CHECK(check_ptr(bk));
     CHECK(check_ptr(ntriangles));
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
-    BispPlan bp;
-    bisp_plan(ntri, tri_bins, nterms, terms, bp);
+    const BispPlan bp = bisp_make_plan(ntri, tri_bins, nterms, terms, INT_MAX);
     const Dims d = dims_of(g);
-    if (work_bytes < bisp_bytes(d, (int)bp.slots.size())) return GRIDSPT_EWORKSPACE;
-    return dispatch(g, [&](auto tag, auto nc) -> int {
+    const int64_t pipe = layout_of(d, 1).end;
+    if (work_bytes < bisp_layout(d, bp, nterms, ntri, pipe).end) return GRIDSPT_EWORKSPACE;
+    return bisp_enqueue(c, g, fields_k, bp, ntri, nterms, terms, edge_n2, bk, ntriangles, work,
+                        static_cast<char*>(work) + pipe, Tuning{}, Batch{});
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// distinct slots per bispectrum chunk of a batch (bounds the slot memory of
+// every realisation to this many real fields)
+constexpr int kBatchSlotCap = 32;
+
+struct GroupPlan {
+    gridspt_batch_group g;  // host arrays below replace the caller's
+    std::vector<int32_t> pairs, tri_bins, terms;
+    std::vector<int64_t> edges;
+    gridspt_batch_out out;
+    Dims d;
+    BispPlan bp;
+    // offsets inside one realisation's arena
+    int64_t o_pipe, o_delta, o_theta, o_cube, o_pws, o_pk, o_kmean, o_nmodes, o_bws, o_bk, o_ntri, zs;
+    int64_t base;  // offset of realisation 0's arena in work
+    Tuning tu;
+    double tune_ms[KD_COUNT] = {};
+};
+
+int64_t plan_group(GroupPlan& p) {
+    const Dims& d = p.d;
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    const int nmax = p.g.nmax;
+    p.o_pipe = take(layout_of(d, nmax).end);
+    p.o_delta = take((int64_t)nmax * d.ncell() * d.real_bytes);
+    p.o_theta = take((int64_t)std::max(nmax - 1, 0) * d.ncell() * d.real_bytes);
+    p.o_cube = take((int64_t)nmax * d.cube() * d.cpx_bytes);
+    p.o_pws = take(power_ws(d, p.g.npairs, p.g.nbins));
+    p.o_pk = take((int64_t)p.g.npairs * p.g.nbins * 8);
+    p.o_kmean = take((int64_t)p.g.nbins * 8);
+    p.o_nmodes = take((int64_t)p.g.nbins * 8);
+    if (p.g.ntri > 0) {
+        // the bispectrum's transforms reuse the pipeline workspace (the orders are done)
+        p.o_bws = take(bisp_layout(d, p.bp, p.g.nterms, p.g.ntri, 0).end);
+        p.o_bk = take((int64_t)p.g.nterms * 8);
+        p.o_ntri = take((int64_t)p.g.ntri * 8);
+    } else {
+        p.o_bws = p.o_bk = p.o_ntri = 0;
+    }
+    p.zs = o;
+    return (int64_t)p.g.nreal * o;
+}
+
+int check_group(const gridspt_batch_group& g) {
+    CHECK(check_grid(&g.grid));
+    if (g.nreal < 1 || g.nmax < 1 || g.nmax > 5) return GRIDSPT_EINVAL;
+    CHECK(check_linpk(&g.grid, &g.lin));
+    if (g.nmax > 1) CHECK(check_mask(&g.grid, g.n2max2));
+    CHECK(check_power_args(g.nmax, g.npairs, g.pairs, g.nbins, g.edge_n2));
+    if (g.ntri < 0) return GRIDSPT_EINVAL;
+    if (g.ntri > 0) {
+        CHECK(check_bisp_args(g.nmax, g.ntri, g.tri_bins, g.nterms, g.terms, g.nbins, g.edge_n2));
+        if (isqrt64(g.edge_n2[g.nbins] - 1) > g.grid.kc) return GRIDSPT_EINVAL;
+    }
+    return GRIDSPT_OK;
+}
+
+int make_group(const gridspt_batch_group& src, GroupPlan& p) {
+    CHECK(check_group(src));
+    p.g = src;
+    p.pairs.assign(src.pairs, src.pairs + 2 * src.npairs);
+    p.edges.assign(src.edge_n2, src.edge_n2 + src.nbins + 1);
+    if (src.ntri > 0) {
+        p.tri_bins.assign(src.tri_bins, src.tri_bins + 3 * src.ntri);
+        p.terms.assign(src.terms, src.terms + 4 * src.nterms);
+    }
+    p.g.pairs = p.pairs.data();
+    p.g.edge_n2 = p.edges.data();
+    p.g.tri_bins = p.tri_bins.empty() ? nullptr : p.tri_bins.data();
+    p.g.terms = p.terms.empty() ? nullptr : p.terms.data();
+    p.d = dims_of(&p.g.grid);
+    if (src.ntri > 0) p.bp = bisp_make_plan(src.ntri, p.g.tri_bins, src.nterms, p.g.terms, kBatchSlotCap);
+    return GRIDSPT_OK;
+}
+
+}  // namespace
+
+struct gridspt_batch {
+    gridspt_ctx* ctx = nullptr;
+    char* work = nullptr;
+    uint32_t flags = 0;
+    std::vector<GroupPlan> groups;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipStream_t> streams;  // capture stream + one per group
+    std::vector<hipEvent_t> events;
+};
+
+namespace {
+
+char* arena(const gridspt_batch* b, const GroupPlan& p, int64_t off) { return b->work + p.base + off; }
+
+// Everything one group does, enqueued on c's stream over all its realisations.
+// stats: also the spectra, bispectra and the realisation statistics.
+int enqueue_group(gridspt_ctx* c, gridspt_batch* b, GroupPlan& p, const Tuning& tu, bool stats) {
+    const gridspt_batch_group& g = p.g;
+    const Dims& d = p.d;
+    const Batch bt{g.nreal, (size_t)p.zs};
+    const int nmax = g.nmax;
+    void* work = arena(b, p, p.o_pipe);
+    void* delta[5] = {};
+    void* theta[5] = {};
+    void* cube[5] = {};
+    for (int i = 0; i < nmax; ++i) {
+        delta[i] = arena(b, p, p.o_delta + (int64_t)i * d.ncell() * d.real_bytes);
+        theta[i] = i == 0 ? delta[0] : arena(b, p, p.o_theta + (int64_t)(i - 1) * d.ncell() * d.real_bytes);
+        cube[i] = arena(b, p, p.o_cube + (int64_t)i * d.cube() * d.cpx_bytes);
+    }
+    const gridspt_grid* gr = &g.grid;
+    CHECK(dispatch(gr, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
         constexpr int N = decltype(nc)::value;
-        Pipe<T, N> p(c, g, work, 1);
-        const int ns = (int)bp.slots.size();
-        char* base = static_cast<char*>(work);
-        T* slotmem = reinterpret_cast<T*>(base + p.L.end);
-        double* partial = reinterpret_cast<double*>(base + align_up(p.L.end + (int64_t)ns * d.ncell() * d.real_bytes));
-        auto slot_ptr = [&](int s) { return slotmem + (size_t)s * d.ncell(); };
-        CHECK(p.twiddles());
-        // shell-filtered fields, five at a time
-        for (int s0 = 0; s0 < ns; s0 += 5) {
-            const int nb = std::min(5, ns - s0);
-            ShellSlots<T> sh{};
-            for (int i = 0; i < nb; ++i) {
-                const auto& sl = bp.slots[s0 + i];
-                sh.cube[i] = sl.first >= 0 ? static_cast<const cpx<T>*>(fields_k[sl.first]) : nullptr;
-                sh.lo[i] = edge_n2[sl.second];
-                sh.hi[i] = edge_n2[sl.second + 1];
+        CHECK((run_linear_field<T, N>(c, gr, &g.lin, delta[0], nullptr, work, tu, bt)));
+        return run_orders<T, N>(c, gr, nmax, g.lin.n2max, g.n2max2, delta[0], delta, theta, cube, nullptr, work, tu,
+                                bt);
+    }));
+    const unsigned one = 1;
+    if (stats) {
+        double* pk = reinterpret_cast<double*>(arena(b, p, p.o_pk));
+        double* km = reinterpret_cast<double*>(arena(b, p, p.o_kmean));
+        double* nm = reinterpret_cast<double*>(arena(b, p, p.o_nmodes));
+        CHECK(power_enqueue(c, gr, cube, g.npairs, g.pairs, g.nbins, g.edge_n2, pk, km, nm, arena(b, p, p.o_pws), bt));
+        const int npk = g.npairs * g.nbins;
+        CHECK(launch(c, KD_BATCH_STATS, 0.0, dim3((npk + 63) / 64), dim3(64), 0, k_batch_stats, (const double*)pk,
+                     g.nreal, npk, (size_t)p.zs, p.out.pk_mean, p.out.pk_std));
+        CHECK(launch(c, KD_BATCH_STATS, 0.0, dim3((g.nbins + 63) / 64), dim3(64), 0, k_batch_stats, (const double*)km,
+                     (int)one, g.nbins, (size_t)p.zs, p.out.kmean, (double*)nullptr));
+        CHECK(launch(c, KD_BATCH_STATS, 0.0, dim3((g.nbins + 63) / 64), dim3(64), 0, k_batch_stats, (const double*)nm,
+                     (int)one, g.nbins, (size_t)p.zs, p.out.nmodes, (double*)nullptr));
+    }
+    if (g.ntri > 0) {
+        double* bk = reinterpret_cast<double*>(arena(b, p, p.o_bk));
+        double* nt = reinterpret_cast<double*>(arena(b, p, p.o_ntri));
+        if (stats) {
+            CHECK(bisp_enqueue(c, gr, cube, p.bp, g.ntri, g.nterms, g.terms, g.edge_n2, bk, nt, work,
+                               arena(b, p, p.o_bws), tu, bt));
+            CHECK(launch(c, KD_BATCH_STATS, 0.0, dim3((g.nterms + 63) / 64), dim3(64), 0, k_batch_stats,
+                         (const double*)bk, g.nreal, g.nterms, (size_t)p.zs, p.out.bk_mean, p.out.bk_std));
+            CHECK(launch(c, KD_BATCH_STATS, 0.0, dim3((g.ntri + 63) / 64), dim3(64), 0, k_batch_stats,
+                         (const double*)nt, (int)one, g.ntri, (size_t)p.zs, p.out.ntriangles, (double*)nullptr));
+        } else {
+            // the tuner times the shell transforms of the first chunk
+            const BispChunk& ch = p.bp.chunks.front();
+            const int ns = (int)ch.slots.size();
+            const BispLayout bl = bisp_layout(d, p.bp, g.nterms, g.ntri, 0);
+            std::vector<const void*> cubes(ns);
+            std::vector<int64_t> lo(ns), hi(ns);
+            std::vector<void*> outs(ns);
+            for (int i = 0; i < ns; ++i) {
+                cubes[i] = ch.slots[i].first >= 0 ? cube[ch.slots[i].first] : nullptr;
+                lo[i] = g.edge_n2[ch.slots[i].second];
+                hi[i] = g.edge_n2[ch.slots[i].second + 1];
+                outs[i] = arena(b, p, p.o_bws + bl.slots + (int64_t)i * d.ncell() * d.real_bytes);
             }
-            CHECK(p.xshell(sh, nb));
-            T* outs[5];
-            for (int i = 0; i < nb; ++i) outs[i] = slot_ptr(s0 + i);
-            CHECK(p.to_real(nb, outs));
+            CHECK(dispatch(gr, [&](auto tag, auto nc) -> int {
+                using T = typename decltype(tag)::type;
+                constexpr int N = decltype(nc)::value;
+                return run_shells<T, N>(c, gr, ns, cubes.data(), lo.data(), hi.data(), outs.data(), work, tu, bt);
+            }));
         }
-        // triple products: the terms, then the triangle counts; sums land in
-        // the first nterms + ntri doubles after the partials
-        double* sums = reinterpret_cast<double*>(p.B());  // S2/S4 buffer is free now
-        auto triple = [&](const std::vector<std::array<int, 3>>& items, double* dst) -> int {
-            for (size_t u0 = 0; u0 < items.size(); u0 += 8) {
-                TripleArgs<T> t{};
-                t.nterms = (int)std::min<size_t>(8, items.size() - u0);
-                t.ncell = (size_t)d.ncell();
-                t.partial = partial;
-                for (int i = 0; i < t.nterms; ++i) {
-                    t.a[i] = slot_ptr(items[u0 + i][0]);
-                    t.b[i] = slot_ptr(items[u0 + i][1]);
-                    t.c[i] = slot_ptr(items[u0 + i][2]);
-                }
-                CHECK(launch(c, KD_TRIPLE, 3.0 * t.nterms * d.ncell() * d.real_bytes, dim3(kTripleBlocks),
-                             dim3(kTripleThreads), 0, k_triple_partial<T>, t));
-                CHECK(launch(c, KD_TRIPLE_FINAL, kTripleBlocks * 8.0 * 8.0, dim3(1), dim3(64), 0, k_triple_final,
-                             (const double*)partial, kTripleBlocks, t.nterms, dst + u0));
+    }
+    return GRIDSPT_OK;
+}
+
+constexpr int kTunedKinds[] = {KD_ZFWD_NOISE, KD_ZFWD_FIELD, KD_ZFWD_PRODUCTS, KD_YFWD, KD_XFUSED_LINEAR,
+                               KD_XFUSED_ORDER1, KD_XFUSED_ORDER, KD_XSHELL, KD_YINV, KD_ZINV};
+
+// per kind: milliseconds of one trial run of the group with every kind in variant v
+int trial(gridspt_batch* b, GroupPlan& p, int v, double (&ms)[KD_COUNT]) {
+    gridspt_ctx c;
+    c.stream = b->ctx->stream;
+    c.profile = true;
+    Tuning tu;
+    for (int k = 0; k < KD_COUNT; ++k) tu.v[k] = v;
+    const int rc = enqueue_group(&c, b, p, tu, false);
+    for (int k = 0; k < KD_COUNT; ++k) ms[k] = 0.0;
+    if (hipStreamSynchronize(c.stream) != hipSuccess) return GRIDSPT_EHIP;
+    for (auto& r : c.recs) {
+        float t = 0.f;
+        if (rc == GRIDSPT_OK && hipEventElapsedTime(&t, r.start, r.stop) != hipSuccess) return GRIDSPT_EHIP;
+        ms[r.kind] += t;
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    for (auto e : c.pool) (void)hipEventDestroy(e);
+    return rc;
+}
+
+int tune_group(gridspt_batch* b, GroupPlan& p) {
+    int vl[8];
+    const int nv = variant_list(p.g.grid.dtype, p.g.grid.n, vl);
+    double best[KD_COUNT];
+    for (int k = 0; k < KD_COUNT; ++k) best[k] = 1e300;
+    double ms[KD_COUNT];
+    CHECK(trial(b, p, 0, ms));  // warm-up
+    for (int i = 0; i < nv; ++i) {
+        CHECK(trial(b, p, vl[i], ms));
+        for (int k : kTunedKinds)
+            if (ms[k] > 0.0 && ms[k] < best[k]) {
+                best[k] = ms[k];
+                p.tu.v[k] = vl[i];
+                p.tune_ms[k] = ms[k];
             }
-            return GRIDSPT_OK;
-        };
-        std::vector<std::array<int, 3>> titems(nterms), jitems(ntri);
-        for (int u = 0; u < nterms; ++u) {
-            const int t = terms[4 * u + 3];
-            for (int i = 0; i < 3; ++i) titems[u][i] = bp.index[{terms[4 * u + i], tri_bins[3 * t + i]}];
+    }
+    return GRIDSPT_OK;
+}
+
+void release(gridspt_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (auto e : b->events) (void)hipEventDestroy(e);
+    for (auto s : b->streams) (void)hipStreamDestroy(s);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->events.clear();
+    b->streams.clear();
+}
+
+int capture(gridspt_batch* b) {
+    const int ng = (int)b->groups.size();
+    b->streams.assign(ng + 1, nullptr);
+    for (auto& s : b->streams)
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return GRIDSPT_EHIP;
+    b->events.assign(ng + 1, nullptr);
+    for (auto& e : b->events)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return GRIDSPT_EHIP;
+    hipStream_t cs = b->streams[0];
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return GRIDSPT_EHIP;
+    int rc = GRIDSPT_OK;
+    if (hipEventRecord(b->events[0], cs) != hipSuccess) rc = GRIDSPT_EHIP;
+    for (int i = 0; i < ng && rc == GRIDSPT_OK; ++i) {
+        gridspt_ctx c;
+        c.stream = b->streams[i + 1];
+        if (hipStreamWaitEvent(c.stream, b->events[0], 0) != hipSuccess) {
+            rc = GRIDSPT_EHIP;
+            break;
         }
-        for (int t = 0; t < ntri; ++t)
-            for (int i = 0; i < 3; ++i) jitems[t][i] = bp.index[{-1, tri_bins[3 * t + i]}];
-        CHECK(triple(titems, sums));
-        CHECK(triple(jitems, sums + nterms));
-        // bk = L^6 T / J per term, the term -> triangle map in the argument buffer
-        const double vol2 = std::pow(g->box, 6);
-        const double invN3 = 1.0 / (double)d.ncell();
-        for (int u0 = 0; u0 < std::max(nterms, ntri); u0 += 64) {
-            TriMap m{};
-            const int nu = std::max(0, std::min(64, nterms - u0));
-            const int nt = std::max(0, std::min(64, ntri - u0));
-            for (int i = 0; i < nu; ++i) m.tri[i] = terms[4 * (u0 + i) + 3];
-            CHECK(launch(c, KD_BISP_FINAL, 0.0, dim3(1), dim3(64), 0, k_bisp_final, (const double*)sums,
-                         (const double*)(sums + nterms), m, u0, nu, nt, vol2, invN3, bk, ntriangles));
-        }
+        rc = enqueue_group(&c, b, b->groups[i], b->groups[i].tu, true);
+        if (rc == GRIDSPT_OK && hipEventRecord(b->events[i + 1], c.stream) != hipSuccess) rc = GRIDSPT_EHIP;
+        if (rc == GRIDSPT_OK && hipStreamWaitEvent(cs, b->events[i + 1], 0) != hipSuccess) rc = GRIDSPT_EHIP;
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    if (rc != GRIDSPT_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (ec != hipSuccess || !graph) return GRIDSPT_EHIP;
+    b->graph = graph;
+    if (hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0) != hipSuccess) return GRIDSPT_EHIP;
+    return GRIDSPT_OK;
+}
+
+int64_t batch_layout(std::vector<GroupPlan>& gp) {
+    int64_t total = 0;
+    for (auto& p : gp) {
+        const int64_t bytes = plan_group(p);
+        p.base = total;
+        total = align_up(total + bytes);
+    }
+    return total;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t gridspt_batch_workspace_bytes(int32_t ngroups, const gridspt_batch_group* groups) {
+    if (ngroups < 1 || ngroups > 64 || !groups) return GRIDSPT_EINVAL;
+    std::vector<GroupPlan> gp(ngroups);
+    for (int i = 0; i < ngroups; ++i) CHECK(make_group(groups[i], gp[i]));
+    return batch_layout(gp);
+}
+
+int gridspt_batch_create(gridspt_ctx* c, int32_t ngroups, const gridspt_batch_group* groups,
+                         const gridspt_batch_out* outs, void* work, int64_t work_bytes, uint32_t flags,
+                         gridspt_batch** out) {
+    if (!c || !out || !outs || ngroups < 1 || ngroups > 64 || !groups) return GRIDSPT_EINVAL;
+    if (flags & ~(uint32_t)(GRIDSPT_BATCH_TUNE | GRIDSPT_BATCH_EAGER)) return GRIDSPT_EINVAL;
+    *out = nullptr;
+    gridspt_batch* b = new (std::nothrow) gridspt_batch();
+    if (!b) return GRIDSPT_EINVAL;
+    b->groups.resize(ngroups);
+    int rc = GRIDSPT_OK;
+    for (int i = 0; i < ngroups && rc == GRIDSPT_OK; ++i) rc = make_group(groups[i], b->groups[i]);
+    for (int i = 0; i < ngroups && rc == GRIDSPT_OK; ++i) {
+        const gridspt_batch_out& o = outs[i];
+        const gridspt_batch_group& g = groups[i];
+        b->groups[i].out = o;
+        for (double* p : {o.pk_mean, o.pk_std, o.kmean, o.nmodes, o.bk_mean, o.bk_std, o.ntriangles})
+            if (p && check_ptr(p) != GRIDSPT_OK) rc = GRIDSPT_EALIGN;
+        if (!o.pk_mean || (g.ntri > 0 && !o.bk_mean)) rc = GRIDSPT_EINVAL;
+    }
+    const int64_t need = rc == GRIDSPT_OK ? batch_layout(b->groups) : 0;
+    if (rc == GRIDSPT_OK && (!work || work_bytes < need)) rc = GRIDSPT_EWORKSPACE;
+    if (rc == GRIDSPT_OK) rc = check_ptr(work);
+    if (rc != GRIDSPT_OK) {
+        delete b;
+        return rc;
+    }
+    b->ctx = c;
+    b->work = static_cast<char*>(work);
+    b->flags = flags;
+    if (flags & GRIDSPT_BATCH_TUNE)
+        for (auto& p : b->groups)
+            if (rc == GRIDSPT_OK) rc = tune_group(b, p);
+    if (rc == GRIDSPT_OK && !(flags & GRIDSPT_BATCH_EAGER)) rc = capture(b);
+    if (rc != GRIDSPT_OK) {
+        release(b);
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return GRIDSPT_OK;
+}
+
+int gridspt_batch_run(gridspt_batch* b) {
+    if (!b) return GRIDSPT_EINVAL;
+    if (b->flags & GRIDSPT_BATCH_EAGER) {
+        for (auto& p : b->groups) CHECK(enqueue_group(b->ctx, b, p, p.tu, true));
         return GRIDSPT_OK;
-    });
+    }
+    if (hipGraphLaunch(b->exec, b->ctx->stream) != hipSuccess) return GRIDSPT_EHIP;
+    return GRIDSPT_OK;
+}
+
+void gridspt_batch_destroy(gridspt_batch* b) {
+    if (!b) return;
+    release(b);
+    delete b;
+}
+
+int gridspt_batch_buffer(const gridspt_batch* b, int32_t group, int32_t real, int32_t what, int32_t index,
+                         void** ptr) {
+    if (!b || !ptr || group < 0 || group >= (int)b->groups.size()) return GRIDSPT_EINVAL;
+    const GroupPlan& p = b->groups[group];
+    if (real < 0 || real >= p.g.nreal) return GRIDSPT_EINVAL;
+    const int64_t r0 = (int64_t)real * p.zs;
+    const Dims& d = p.d;
+    int64_t off;
+    switch (what) {
+        case GRIDSPT_BATCH_DELTA:
+        case GRIDSPT_BATCH_THETA:
+            if (index < 0 || index >= p.g.nmax) return GRIDSPT_EINVAL;
+            if (what == GRIDSPT_BATCH_DELTA || index == 0) off = p.o_delta + (int64_t)index * d.ncell() * d.real_bytes;
+            else off = p.o_theta + (int64_t)(index - 1) * d.ncell() * d.real_bytes;
+            break;
+        case GRIDSPT_BATCH_DELTA_K:
+            if (index < 0 || index >= p.g.nmax) return GRIDSPT_EINVAL;
+            off = p.o_cube + (int64_t)index * d.cube() * d.cpx_bytes;
+            break;
+        case GRIDSPT_BATCH_PK:
+            if (index != 0) return GRIDSPT_EINVAL;
+            off = p.o_pk;
+            break;
+        case GRIDSPT_BATCH_BK:
+            if (index != 0 || p.g.ntri == 0) return GRIDSPT_EINVAL;
+            off = p.o_bk;
+            break;
+        default: return GRIDSPT_EINVAL;
+    }
+    *ptr = b->work + p.base + r0 + off;
+    return GRIDSPT_OK;
+}
+
+int gridspt_batch_tuning(const gridspt_batch* b, int32_t group, int32_t max, char* names, int32_t* variant,
+                         double* ms) {
+    if (!b || group < 0 || group >= (int)b->groups.size() || max < 0) return GRIDSPT_EINVAL;
+    const GroupPlan& p = b->groups[group];
+    int k = 0;
+    for (int kind : kTunedKinds) {
+        if (k >= max) break;
+        if (names) {
+            std::memset(names + 32 * k, 0, 32);
+            std::strncpy(names + 32 * k, kKindNames[kind], 31);
+        }
+        if (variant) variant[k] = p.tu.v[kind];
+        if (ms) ms[k] = p.tune_ms[kind];
+        ++k;
+    }
+    return k;
 }
 
 }  // extern "C"

@@ -30,15 +30,28 @@
 
 namespace gridspt {
 
-template <typename T, int N>
+constexpr int pow2_floor(int v) {
+    int p = 1;
+    while (2 * p <= v) p *= 2;
+    return p;
+}
+
+// Block shape of a pass kernel.  Variant V (a launch-time choice of the
+// autotuner): bits 0-1 divide the rows per block by 2^(V & 3), bit 2 caps the
+// later FFT radices at 4.  Rows per block: about 64 KB of LDS, at most 32,
+// a power of two dividing N/2 (so blocks of 2 RPB rows tile an axis).
+template <typename T, int N, int V = 0>
 struct Rows {
-    // rows per block: about 64 KB of LDS, at most 32 rows, at most N/2 rows
+    using PL = Plan<N, (V >> 2) & 1>;
     static constexpr int bytes = 65536 / (N * (int)sizeof(cpx<T>));
-    static constexpr int RPB0 = bytes < 1 ? 1 : (bytes > 32 ? 32 : bytes);
-    static constexpr int RPB = RPB0 > N / 2 ? N / 2 : RPB0;
-    static constexpr int P = N / 16;
+    static constexpr int RPB0 = pow2_floor(bytes < 1 ? 1 : (bytes > 32 ? 32 : bytes)) >> (V & 3);
+    static constexpr int HALF = (N / 2) & -(N / 2);  // largest power of two dividing N/2
+    static constexpr int RPB1 = RPB0 < 1 ? 1 : RPB0;
+    static constexpr int RPB = RPB1 > HALF ? HALF : RPB1;
+    static constexpr int P = PL::P, E = PL::E;
     static constexpr int THREADS = RPB * P;
     static constexpr int ROWE = lds_row_elems(N);
+    static_assert(THREADS <= 1024, "block too large");
 };
 
 // element at a 32-bit element offset from a block-uniform base
@@ -114,37 +127,37 @@ __device__ __forceinline__ double lin_amplitude(double k, const LinParams& p) {
 }
 
 // canonical registers of one row -> this row's LDS buffer in natural order
-template <int N, typename T>
-__device__ __forceinline__ void stage_row(const cpx<T> (&v)[16], cpx<T>* row, int l) {
-    constexpr int P = N / 16;
+template <typename PL, typename T>
+__device__ __forceinline__ void stage_row(const cpx<T> (&v)[PL::E], cpx<T>* row, int l) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) row[lds_pad(l + P * e)] = v[e];
+    for (int e = 0; e < PL::E; ++e) row[lds_pad(l + PL::P * e)] = v[e];
 }
 
 // Transposed store of the block's rows through real-valued LDS rows (split
 // exchange): output item idx < count is (o, rr) = (idx / RPB, idx % RPB) and
 // takes position pos(o) of row rr; store(o, rr, value) writes it.  Real parts
-// travel first and wait in registers (at most N / P = 16 items per thread).
-template <int N, typename T, typename PosF, typename StoreF>
-__device__ __forceinline__ void transpose_out_split(const cpx<T> (&v)[16], const T* lds, T* row, int l, int count,
+// travel first and wait in registers (at most N / P = E items per thread).
+template <typename T, int N, int V, typename PosF, typename StoreF, int E>
+__device__ __forceinline__ void transpose_out_split(const cpx<T> (&v)[E], const T* lds, T* row, int l, int count,
                                                     PosF pos, StoreF store) {
-    using RW = Rows<T, N>;
+    using RW = Rows<T, N, V>;
     constexpr int RPB = RW::RPB, ROWE = RW::ROWE, P = RW::P;
-    T re[16];
+    static_assert(E == RW::E, "register count of the row");
+    T re[E];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) row[lds_pad(l + P * e)] = v[e].x;
+    for (int e = 0; e < E; ++e) row[lds_pad(l + P * e)] = v[e].x;
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < 16; ++it) {
+    for (int it = 0; it < E; ++it) {
         const int idx = threadIdx.x + RW::THREADS * it;
         if (idx < count) re[it] = lds[(idx % RPB) * ROWE + lds_pad(pos(idx / RPB))];
     }
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 16; ++e) row[lds_pad(l + P * e)] = v[e].y;
+    for (int e = 0; e < E; ++e) row[lds_pad(l + P * e)] = v[e].y;
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < 16; ++it) {
+    for (int it = 0; it < E; ++it) {
         const int idx = threadIdx.x + RW::THREADS * it;
         if (idx < count) store(idx / RPB, idx % RPB, cpx<T>{re[it], lds[(idx % RPB) * ROWE + lds_pad(pos(idx / RPB))]});
     }
@@ -195,21 +208,33 @@ __device__ __forceinline__ void load_products(const ProductInputs<T>& pin, size_
     b = {vz, w};
 }
 
-template <typename T, int N, int SRC, int NORD>
-__global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zfwd(const T* __restrict__ f, ProductInputs<T> pin,
-                                                                 uint64_t seed, uint64_t stream,
-                                                                 cpx<T>* __restrict__ s1, size_t s1_field,
-                                                                 const cpx<T>* __restrict__ tw, int Kz) {
-    using RW = Rows<T, N>;
-    constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
+template <typename T, int N, int V, int SRC, int NORD>
+__global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __restrict__ f, ProductInputs<T> pin,
+                                                                    uint64_t seed, uint64_t stream,
+                                                                    cpx<T>* __restrict__ s1, size_t s1_field,
+                                                                    const cpx<T>* __restrict__ tw, int Kz, size_t zs) {
+    using RW = Rows<T, N, V>;
+    using PL = typename RW::PL;
+    constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
     constexpr int YB = (SRC == 2) ? RPB : 2 * RPB;  // rows of y per block
     __shared__ cpx<T> lds[RPB * ROWE];
     // twiddles in LDS for FP32 (this pass's LDS traffic is light), else from the cache
     constexpr bool LT = kLdsTwiddles<T> && true;
-    __shared__ cpx<T> twl[LT ? TwLayout<N>::ALLOC : 1];
-    if constexpr (LT) load_twiddles<N, T>(twl, tw);
+    __shared__ cpx<T> twl[LT ? PL::TW_ALLOC : 1];
+    if constexpr (LT) load_twiddles<PL, T>(twl, tw);
     __syncthreads();
-    const Twiddles<T, N, LT> tws{LT ? twl : tw};
+    const Twiddles<T, PL, LT> tws{LT ? twl : tw};
+    f = zptr(f, zs);
+    s1 = zptr(s1, zs);
+    if constexpr (SRC == 2) {
+#pragma unroll
+        for (int m = 0; m < NORD - 1; ++m) {
+            pin.d[m] = zptr(pin.d[m], zs);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) pin.u[m][j] = zptr(pin.u[m][j], zs);
+        }
+    }
+    stream += blockIdx.z;  // realisation r of a batch draws Philox stream `stream + r`
     constexpr uint32_t groups = N / YB;
     const uint32_t blk = xcd_block(blockIdx.x, N * groups);
     const int x = blk / groups, y0 = (blk % groups) * YB;
@@ -217,14 +242,14 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zfwd(const T* __restr
     const size_t blockbase = ((size_t)x * N + y0) * N;  // first cell of the block
     cpx<T>* row = lds + r * ROWE;
 
-    cpx<T> a[16], b[16];
+    cpx<T> a[E], b[E];
     if constexpr (SRC == 1) {
-        // 2 RPB N consecutive cells: each thread draws 8 groups of 4 cells
+        // 2 RPB N consecutive cells: each thread draws E / 2 groups of 4 cells
         // straight into the LDS rows (row y0 + rr goes to team rr % RPB, real
         // part for rr < RPB, imaginary part otherwise)
         T* words = reinterpret_cast<T*>(lds);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < E / 2; ++i) {
             const int grp = threadIdx.x + RW::THREADS * i;  // < 2 RPB N / 4
             double gs[4];
             group_gaussians(seed, stream, (blockbase >> 2) + grp, gs);
@@ -235,12 +260,12 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zfwd(const T* __restr
         }
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < 16; ++e) a[e] = row[lds_pad(l + P * e)];
+        for (int e = 0; e < E; ++e) a[e] = row[lds_pad(l + P * e)];
         wave_sync();
     } else if constexpr (SRC == 0) {
         const T* f0 = f + blockbase;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
+        for (int e = 0; e < E; ++e) {
             const uint32_t o = (uint32_t)(r * N + l + P * e);
             a[e] = {ldo(f0, o), ldo(f0, o + (uint32_t)(RPB * N))};
         }
@@ -248,7 +273,7 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zfwd(const T* __restr
         // the packed products are formed here, not after the first transform,
         // so the raw inputs are dead before the FFTs start
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
+        for (int e = 0; e < E; ++e) {
             load_products<T, NORD>(pin, blockbase, (uint32_t)(r * N + l + P * e), a[e], b[e]);
             keep_here(a[e]);
             keep_here(b[e]);
@@ -258,12 +283,12 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zfwd(const T* __restr
     constexpr int NPACK = (SRC == 2) ? 2 : 1;
     static_for<NPACK>([&](auto pkc) {
         constexpr int pk = decltype(pkc)::value;
-        cpx<T> v[16];
+        cpx<T> v[E];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = pk == 0 ? a[e] : b[e];
+        for (int e = 0; e < E; ++e) v[e] = pk == 0 ? a[e] : b[e];
         if constexpr (pk > 0) __syncthreads();  // previous read-out has finished with LDS
-        fft_row<N, -1, T>(v, row, tws, l);
-        stage_row<N, T>(v, row, l);
+        fft_row<PL, -1, T>(v, row, tws, l);
+        stage_row<PL, T>(v, row, l);
         __syncthreads();
         // read-out: S1[kz][x][y0 + rr] for every kept kz
         cpx<T>* out = s1 + ((size_t)x * N + y0);
@@ -271,7 +296,7 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zfwd(const T* __restr
             const int kz = idx / YB, rr = idx % YB;
             const int team = (SRC == 2) ? rr : rr % RPB;
             const cpx<T> c = lds[team * ROWE + lds_pad(kz)];
-            const cpx<T> m = lds[team * ROWE + lds_pad((N - kz) & (N - 1))];
+            const cpx<T> m = lds[team * ROWE + lds_pad(kz == 0 ? 0 : N - kz)];
             const size_t o = (size_t)kz * N * N + rr;
             if constexpr (SRC == 2) {
                 out[(size_t)(2 * pk) * s1_field + o] = unpack_real_pair(c, m, 0);
@@ -287,31 +312,35 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zfwd(const T* __restr
 // P2: y pass, forward.  Rows (kz, x) of S1; block = RPB consecutive x at one
 // kz; grid.y = field.  Keeps |ky| <= Kc and writes S2 [kz][ky'][x].
 // --------------------------------------------------------------------------
-template <typename T, int N>
-__global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_yfwd(const cpx<T>* __restrict__ s1, size_t s1_field,
-                                                                 cpx<T>* __restrict__ s2, size_t s2_field,
-                                                                 const cpx<T>* __restrict__ tw, CubeDims cd) {
-    using RW = Rows<T, N>;
-    constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
+template <typename T, int N, int V>
+__global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yfwd(const cpx<T>* __restrict__ s1, size_t s1_field,
+                                                                    cpx<T>* __restrict__ s2, size_t s2_field,
+                                                                    const cpx<T>* __restrict__ tw, CubeDims cd,
+                                                                    size_t zs) {
+    using RW = Rows<T, N, V>;
+    using PL = typename RW::PL;
+    constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
     __shared__ T lds[RPB * ROWE];  // real-valued rows (split exchange)
     // twiddles in LDS for FP32 (this pass's LDS traffic is light), else from the cache
     constexpr bool LT = kLdsTwiddles<T> && true;
-    __shared__ cpx<T> twl[LT ? TwLayout<N>::ALLOC : 1];
-    if constexpr (LT) load_twiddles<N, T>(twl, tw);
+    __shared__ cpx<T> twl[LT ? PL::TW_ALLOC : 1];
+    if constexpr (LT) load_twiddles<PL, T>(twl, tw);
     __syncthreads();
-    const Twiddles<T, N, LT> tws{LT ? twl : tw};
+    const Twiddles<T, PL, LT> tws{LT ? twl : tw};
+    s1 = zptr(s1, zs);
+    s2 = zptr(s2, zs);
     constexpr uint32_t groups = N / RPB;
     const uint32_t blk = xcd_block(blockIdx.x, cd.Kz * groups);
     const int kz = blk / groups, x0 = (blk % groups) * RPB;
     const int r = threadIdx.x / P, l = threadIdx.x % P;
     const cpx<T>* in = s1 + (size_t)blockIdx.y * s1_field + ((size_t)kz * N + x0) * N;
     T* row = lds + r * ROWE;
-    cpx<T> v[16];
+    cpx<T> v[E];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) v[e] = ldo(in, (uint32_t)(r * N + l + P * e));
-    fft_row_split<N, -1, T>(v, row, tws, l);
+    for (int e = 0; e < E; ++e) v[e] = ldo(in, (uint32_t)(r * N + l + P * e));
+    fft_row_split<PL, -1, T>(v, row, tws, l);
     cpx<T>* out = s2 + (size_t)blockIdx.y * s2_field + (size_t)kz * cd.Ky * N + x0;
-    transpose_out_split<N, T>(
+    transpose_out_split<T, N, V>(
         v, lds, row, l, cd.Ky * RPB, [&](int ky) { return compact_to_pos(ky, cd.Kc, N); },
         [&](int ky, int rr, cpx<T> val) { sto(out, (uint32_t)(ky * N + rr), val); });
 }
@@ -338,14 +367,16 @@ struct XArgs {
 };
 
 // inverse x transform of one output row and its transposed store into S3
-template <typename T, int N, bool LT>
-__device__ __forceinline__ void x_inverse_store(cpx<T> (&v)[16], cpx<T>* lds, cpx<T>* row, Twiddles<T, N, LT> tw,
-                                                int l, cpx<T>* out, int Ky, int nrows) {
-    using RW = Rows<T, N>;
+template <typename T, int N, int V, typename TW, int E>
+__device__ __forceinline__ void x_inverse_store(cpx<T> (&v)[E], cpx<T>* lds, cpx<T>* row, TW tw, int l, cpx<T>* out,
+                                                int Ky, int nrows) {
+    using RW = Rows<T, N, V>;
+    using PL = typename RW::PL;
+    static_assert(E == PL::E, "register count of the row");
     constexpr int RPB = RW::RPB, ROWE = RW::ROWE;
     __syncthreads();  // the previous read-out is done with LDS
-    fft_row<N, +1, T>(v, row, tw, l);
-    stage_row<N, T>(v, row, l);
+    fft_row<PL, +1, T>(v, row, tw, l);
+    stage_row<PL, T>(v, row, l);
     __syncthreads();
     for (int idx = threadIdx.x; idx < N * RPB; idx += RW::THREADS) {
         const int x = idx / RPB, rr = idx % RPB;
@@ -353,18 +384,23 @@ __device__ __forceinline__ void x_inverse_store(cpx<T> (&v)[16], cpx<T>* lds, cp
     }
 }
 
-template <typename T, int N, int MODE>
-__global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xfused(XArgs<T> a, const cpx<T>* __restrict__ tw,
-                                                                   CubeDims cd) {
-    using RW = Rows<T, N>;
-    constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
+template <typename T, int N, int V, int MODE>
+__global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a, const cpx<T>* __restrict__ tw,
+                                                                      CubeDims cd, size_t zs) {
+    using RW = Rows<T, N, V>;
+    using PL = typename RW::PL;
+    constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
     __shared__ cpx<T> lds[RPB * ROWE];
     // twiddles from the cache: this pass's LDS is busy with exchanges and staging
     constexpr bool LT = kLdsTwiddles<T> && false;
-    __shared__ cpx<T> twl[LT ? TwLayout<N>::ALLOC : 1];
-    if constexpr (LT) load_twiddles<N, T>(twl, tw);
+    __shared__ cpx<T> twl[LT ? PL::TW_ALLOC : 1];
+    if constexpr (LT) load_twiddles<PL, T>(twl, tw);
     __syncthreads();
-    const Twiddles<T, N, LT> tws{LT ? twl : tw};
+    const Twiddles<T, PL, LT> tws{LT ? twl : tw};
+    a.s2 = zptr(a.s2, zs);
+    a.s3 = zptr(a.s3, zs);
+    a.cube_d = zptr(a.cube_d, zs);
+    a.cube_t = zptr(a.cube_t, zs);
     const uint32_t groups = (cd.Ky + RPB - 1) / RPB;
     const uint32_t blk = xcd_block(blockIdx.x, cd.Kz * groups);
     const int kz = blk / groups, ky0 = (blk % groups) * RPB;
@@ -377,44 +413,44 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xfused(XArgs<T> a, co
     const size_t inbase = ((size_t)kz * cd.Ky + ky0) * N;
 
     // k-space step: sd holds delta_n(k), st holds theta_n(k) afterwards
-    cpx<T> sd[16], st[16];
+    cpx<T> sd[E], st[E];
     constexpr int NIN = (MODE == XM_ORDER) ? 4 : 1;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) sd[e] = st[e] = {(T)0, (T)0};
+    for (int e = 0; e < E; ++e) sd[e] = st[e] = {(T)0, (T)0};
     static_for<NIN>([&](auto fc) {
         constexpr int f = decltype(fc)::value;
-        cpx<T> v[16];
+        cpx<T> v[E];
         const cpx<T>* in = a.s2 + (size_t)f * a.s2_field + inbase;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = active ? ldo(in, (uint32_t)(r * N + l + P * e)) : cpx<T>{(T)0, (T)0};
-        fft_row<N, -1, T>(v, row, tws, l);
+        for (int e = 0; e < E; ++e) v[e] = active ? ldo(in, (uint32_t)(r * N + l + P * e)) : cpx<T>{(T)0, (T)0};
+        fft_row<PL, -1, T>(v, row, tws, l);
         if constexpr (MODE == XM_ORDER) {
             if constexpr (f < 3) {
                 // S_delta += i k_f V_f(k)  (kF and N^-3 applied below)
 #pragma unroll
-                for (int e = 0; e < 16; ++e) {
+                for (int e = 0; e < E; ++e) {
                     const int kx = signed_pos(l + P * e, N);
                     const T kf = (T)(f == 0 ? kx : (f == 1 ? ky : kz));
                     sd[e] = cadd(sd[e], cscale(cmul_i(v[e]), kf));
                 }
             } else {
 #pragma unroll
-                for (int e = 0; e < 16; ++e) st[e] = v[e];
+                for (int e = 0; e < E; ++e) st[e] = v[e];
             }
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
+            for (int e = 0; e < E; ++e) {
                 keep_here(sd[e]);
                 keep_here(st[e]);
             }
         } else {
 #pragma unroll
-            for (int e = 0; e < 16; ++e) sd[e] = v[e];
+            for (int e = 0; e < E; ++e) sd[e] = v[e];
         }
     });
 
     const T kF = (T)a.kF, invN3 = (T)a.invN3;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
+    for (int e = 0; e < E; ++e) {
         const int kx = signed_pos(l + P * e, N);
         const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
         const bool keep = active && n2 > 0 && n2 <= a.n2max;
@@ -439,14 +475,14 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xfused(XArgs<T> a, co
     // theta_1 = delta_1 below order 2
     if constexpr (MODE != XM_ORDER) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) st[e] = sd[e];
+        for (int e = 0; e < E; ++e) st[e] = sd[e];
     }
 
     // cube stores (masked spectra), kept kx only
     if (active && (a.cube_d || a.cube_t)) {
         const size_t cbase = ((size_t)kz * cd.Ky + kyc) * cd.Ky;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
+        for (int e = 0; e < E; ++e) {
             const int ic = pos_to_compact(l + P * e, cd.Kc, N);
             if (ic >= 0) {
                 if (a.cube_d) a.cube_d[cbase + ic] = sd[e];
@@ -462,15 +498,15 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xfused(XArgs<T> a, co
         static_for<NOUT_MAX>([&](auto oc) {
             constexpr int o = decltype(oc)::value;
             if (o < a.nout) {
-                cpx<T> v[16];
+                cpx<T> v[E];
                 if constexpr (o < FIRST_U) {
 #pragma unroll
-                    for (int e = 0; e < 16; ++e) v[e] = (o == 0) ? sd[e] : st[e];
+                    for (int e = 0; e < E; ++e) v[e] = (o == 0) ? sd[e] : st[e];
                 } else {
                     // u_j(k) = (-i k_j / k^2) theta(k)
                     constexpr int comp = o - FIRST_U;
 #pragma unroll
-                    for (int e = 0; e < 16; ++e) {
+                    for (int e = 0; e < E; ++e) {
                         const int kx = signed_pos(l + P * e, N);
                         const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
                         const int kj = comp == 0 ? kx : (comp == 1 ? ky : kz);
@@ -478,7 +514,8 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xfused(XArgs<T> a, co
                         v[e] = {st[e].y * s, -st[e].x * s};
                     }
                 }
-                x_inverse_store<T, N, LT>(v, lds, row, tws, l, a.s3 + (size_t)o * a.s3_field + outbase, cd.Ky, nrows);
+                x_inverse_store<T, N, V>(v, lds, row, tws, l, a.s3 + (size_t)o * a.s3_field + outbase, cd.Ky,
+                                             nrows);
             }
         });
     }
@@ -497,18 +534,19 @@ struct ShellSlots {
     size_t s3_field;
 };
 
-template <typename T, int N>
-__global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xshell(ShellSlots<T> a, const cpx<T>* __restrict__ tw,
-                                                                   CubeDims cd) {
-    using RW = Rows<T, N>;
-    constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
+template <typename T, int N, int V>
+__global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xshell(ShellSlots<T> a, const cpx<T>* __restrict__ tw,
+                                                                      CubeDims cd, size_t zs) {
+    using RW = Rows<T, N, V>;
+    using PL = typename RW::PL;
+    constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
     __shared__ cpx<T> lds[RPB * ROWE];
     // twiddles from the cache: this pass's LDS is busy with exchanges and staging
     constexpr bool LT = kLdsTwiddles<T> && false;
-    __shared__ cpx<T> twl[LT ? TwLayout<N>::ALLOC : 1];
-    if constexpr (LT) load_twiddles<N, T>(twl, tw);
+    __shared__ cpx<T> twl[LT ? PL::TW_ALLOC : 1];
+    if constexpr (LT) load_twiddles<PL, T>(twl, tw);
     __syncthreads();
-    const Twiddles<T, N, LT> tws{LT ? twl : tw};
+    const Twiddles<T, PL, LT> tws{LT ? twl : tw};
     const uint32_t groups = (cd.Ky + RPB - 1) / RPB;
     const uint32_t blk = xcd_block(blockIdx.x, cd.Kz * groups);
     const int kz = blk / groups, ky0 = (blk % groups) * RPB;
@@ -517,12 +555,12 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xshell(ShellSlots<T> 
     const bool active = kyc < cd.Ky;
     const int ky = active ? (kyc <= cd.Kc ? kyc : kyc - cd.Ky) : 0;
     const int slot = blockIdx.y;
-    const cpx<T>* cube = a.cube[slot];
+    const cpx<T>* cube = zptr(a.cube[slot], zs);
     const size_t cbase = ((size_t)kz * cd.Ky + ky0) * cd.Ky;
     cpx<T>* row = lds + r * ROWE;
-    cpx<T> v[16];
+    cpx<T> v[E];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
+    for (int e = 0; e < E; ++e) {
         const int p = l + P * e;
         const int ic = pos_to_compact(p, cd.Kc, N);
         const int kx = signed_pos(p, N);
@@ -532,27 +570,32 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_xshell(ShellSlots<T> 
         if (in) c = cube ? cube[cbase + (size_t)r * cd.Ky + ic] : cpx<T>{(T)1, (T)0};
         v[e] = c;
     }
-    x_inverse_store<T, N, LT>(v, lds, row, tws, l, a.s3 + (size_t)slot * a.s3_field + (size_t)kz * N * cd.Ky + ky0, cd.Ky,
-                          min(RPB, cd.Ky - ky0));
+    x_inverse_store<T, N, V>(v, lds, row, tws, l,
+                                 zptr(a.s3, zs) + (size_t)slot * a.s3_field + (size_t)kz * N * cd.Ky + ky0, cd.Ky,
+                                 min(RPB, cd.Ky - ky0));
 }
 
 // --------------------------------------------------------------------------
 // P4: y pass, inverse.  Rows (kz, x) of S3 (Ky values, zero-extended to N);
 // block = RPB consecutive kz at one x; grid.y = field.  Writes S4 [x][y][kz].
 // --------------------------------------------------------------------------
-template <typename T, int N>
-__global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_yinv(const cpx<T>* __restrict__ s3, size_t s3_field,
-                                                                 cpx<T>* __restrict__ s4, size_t s4_field,
-                                                                 const cpx<T>* __restrict__ tw, CubeDims cd) {
-    using RW = Rows<T, N>;
-    constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
+template <typename T, int N, int V>
+__global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yinv(const cpx<T>* __restrict__ s3, size_t s3_field,
+                                                                    cpx<T>* __restrict__ s4, size_t s4_field,
+                                                                    const cpx<T>* __restrict__ tw, CubeDims cd,
+                                                                    size_t zs) {
+    using RW = Rows<T, N, V>;
+    using PL = typename RW::PL;
+    constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
     __shared__ T lds[RPB * ROWE];  // real-valued rows (split exchange)
     // twiddles from the cache: this pass's LDS is busy with exchanges and staging
     constexpr bool LT = kLdsTwiddles<T> && false;
-    __shared__ cpx<T> twl[LT ? TwLayout<N>::ALLOC : 1];
-    if constexpr (LT) load_twiddles<N, T>(twl, tw);
+    __shared__ cpx<T> twl[LT ? PL::TW_ALLOC : 1];
+    if constexpr (LT) load_twiddles<PL, T>(twl, tw);
     __syncthreads();
-    const Twiddles<T, N, LT> tws{LT ? twl : tw};
+    const Twiddles<T, PL, LT> tws{LT ? twl : tw};
+    s3 = zptr(s3, zs);
+    s4 = zptr(s4, zs);
     const uint32_t groups = (cd.Kz + RPB - 1) / RPB;
     const uint32_t blk = xcd_block(blockIdx.x, N * groups);
     const int x = blk / groups, kz0 = (blk % groups) * RPB;
@@ -561,16 +604,16 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_yinv(const cpx<T>* __
     const cpx<T>* in = s3 + (size_t)blockIdx.y * s3_field + ((size_t)kz0 * N + x) * cd.Ky;
     const uint32_t rowoff = (uint32_t)(r * N * cd.Ky);
     T* row = lds + r * ROWE;
-    cpx<T> v[16];
+    cpx<T> v[E];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
+    for (int e = 0; e < E; ++e) {
         const int ic = pos_to_compact(l + P * e, cd.Kc, N);
         v[e] = (active && ic >= 0) ? ldo(in, rowoff + (uint32_t)ic) : cpx<T>{(T)0, (T)0};
     }
-    fft_row_split<N, +1, T>(v, row, tws, l);
+    fft_row_split<PL, +1, T>(v, row, tws, l);
     cpx<T>* out = s4 + (size_t)blockIdx.y * s4_field + (size_t)x * N * cd.Kz + kz0;
     const int nrows = min(RPB, cd.Kz - kz0);
-    transpose_out_split<N, T>(v, lds, row, l, N * RPB, [](int y) { return y; }, [&](int y, int rr, cpx<T> val) {
+    transpose_out_split<T, N, V>(v, lds, row, l, N * RPB, [](int y) { return y; }, [&](int y, int rr, cpx<T> val) {
         if (rr < nrows) sto(out, (uint32_t)(y * cd.Kz + rr), val);
     });
 }
@@ -588,19 +631,21 @@ struct ZJobs {
     T* outb[3];
 };
 
-template <typename T, int N>
-__global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zinv(const cpx<T>* __restrict__ s4, size_t s4_field,
-                                                                 ZJobs<T> zj, const cpx<T>* __restrict__ tw,
-                                                                 CubeDims cd) {
-    using RW = Rows<T, N>;
-    constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE;
+template <typename T, int N, int V>
+__global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zinv(const cpx<T>* __restrict__ s4, size_t s4_field,
+                                                                    ZJobs<T> zj, const cpx<T>* __restrict__ tw,
+                                                                    CubeDims cd, size_t zs) {
+    using RW = Rows<T, N, V>;
+    using PL = typename RW::PL;
+    constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
     __shared__ T lds[RPB * ROWE];  // real-valued exchange rows (split exchange)
     // twiddles in LDS for FP32 (this pass's LDS traffic is light), else from the cache
     constexpr bool LT = kLdsTwiddles<T> && true;
-    __shared__ cpx<T> twl[LT ? TwLayout<N>::ALLOC : 1];
-    if constexpr (LT) load_twiddles<N, T>(twl, tw);
+    __shared__ cpx<T> twl[LT ? PL::TW_ALLOC : 1];
+    if constexpr (LT) load_twiddles<PL, T>(twl, tw);
     __syncthreads();
-    const Twiddles<T, N, LT> tws{LT ? twl : tw};
+    const Twiddles<T, PL, LT> tws{LT ? twl : tw};
+    s4 = zptr(s4, zs);
     const int job = blockIdx.y;
     const bool tworows = zj.fb[job] < 0;
     const uint32_t nblk = (uint32_t)((size_t)N * N / RPB);
@@ -612,9 +657,9 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zinv(const cpx<T>* __
     const cpx<T>* B = tworows ? A : s4 + (size_t)zj.fb[job] * s4_field + q0 * cd.Kz;
     const uint32_t ra = (uint32_t)(r * cd.Kz), rb = (uint32_t)((tworows ? r + RPB : r) * cd.Kz);
     T* row = lds + r * ROWE;
-    cpx<T> v[16];
+    cpx<T> v[E];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
+    for (int e = 0; e < E; ++e) {
         const int p = l + P * e;
         cpx<T> c = {(T)0, (T)0};
         if (p < cd.Kz) {
@@ -626,14 +671,14 @@ __global__ __launch_bounds__((Rows<T, N>::THREADS)) void k_zinv(const cpx<T>* __
         }
         v[e] = c;
     }
-    fft_row_split<N, +1, T>(v, row, tws, l);
-    T* oa = zj.outa[job] + q0 * N;
-    T* ob = (tworows ? zj.outa[job] : zj.outb[job]) + q0 * N;
+    fft_row_split<PL, +1, T>(v, row, tws, l);
+    T* oa = zptr(zj.outa[job], zs) + q0 * N;
+    T* ob = zptr(tworows ? zj.outa[job] : zj.outb[job], zs) + q0 * N;
     const uint32_t wa = (uint32_t)(r * N), wb = (uint32_t)((tworows ? r + RPB : r) * N);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) sto(oa, wa + (uint32_t)(l + P * e), v[e].x);
+    for (int e = 0; e < E; ++e) sto(oa, wa + (uint32_t)(l + P * e), v[e].x);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) sto(ob, wb + (uint32_t)(l + P * e), v[e].y);
+    for (int e = 0; e < E; ++e) sto(ob, wb + (uint32_t)(l + P * e), v[e].y);
 }
 
 }  // namespace gridspt

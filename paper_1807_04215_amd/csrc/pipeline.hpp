@@ -1,0 +1,330 @@
+// Pass sequences of the entry points (Sec. II C): the five-pass transform
+// pipeline of one grid size, with each pass launched in the variant the
+// tuning table names and over a batch of realisations (gridDim.z).
+// Included once per grid size by the files under sizes/, which instantiate
+// the run_* functions declared in runtime.hpp.
+#pragma once
+#include "runtime.hpp"
+
+namespace gridspt {
+
+// Launch variants compiled per (precision, size) (see variant_list): the
+// autotuner chooses among these per pass kind.
+template <typename T, int N>
+struct Variants {
+    static constexpr bool two = tuned_pow2(sizeof(T) == 4, N);
+    static constexpr bool three = tuned_three(sizeof(T) == 4, N);
+    using list = std::conditional_t<two, std::integer_sequence<int, 0, 1, 4, 5>,
+                                    std::conditional_t<three, std::integer_sequence<int, 0, 1, 2>,
+                                                       std::integer_sequence<int, 0>>>;
+};
+
+template <typename F, int... Vs>
+int with_variant_impl(int v, F&& f, std::integer_sequence<int, Vs...>) {
+    int rc = GRIDSPT_EUNSUPPORTED;
+    (void)((v == Vs ? (rc = f(std::integral_constant<int, Vs>{}), true) : false) || ...);
+    return rc;
+}
+template <typename T, int N, typename F>
+int with_variant(int v, F&& f) {
+    return with_variant_impl(v, f, typename Variants<T, N>::list{});
+}
+
+template <typename T, int N>
+struct Pipe {
+    gridspt_ctx* c;
+    Dims d;
+    Layout L;
+    char* ws;  // realisation 0's workspace
+    CubeDims cd;
+    const Tuning& tu;
+    Batch bt;
+
+    Pipe(gridspt_ctx* ctx, const gridspt_grid* g, void* work, int nmax, const Tuning& t, Batch b)
+        : c(ctx), d(dims_of(g)), tu(t), bt(b) {
+        L = layout_of(d, nmax);
+        ws = static_cast<char*>(work);
+        cd = {(int)d.Kc, (int)d.Kz, (int)d.Ky};
+    }
+    cpx<T>* tw() const { return reinterpret_cast<cpx<T>*>(ws + L.tw); }
+    cpx<T>* A() const { return reinterpret_cast<cpx<T>*>(ws + L.a); }
+    cpx<T>* B() const { return reinterpret_cast<cpx<T>*>(ws + L.b); }
+    T* U(int m, int j) const {  // u_m component j, m >= 1
+        return reinterpret_cast<T*>(ws + L.u) + ((size_t)(m - 1) * 3 + j) * (size_t)d.ncell();
+    }
+    double nb() const { return (double)bt.nreal; }
+    unsigned nz() const { return (unsigned)bt.nreal; }
+
+    // the shared table, computed once (realisation 0's workspace)
+    int twiddles() {
+        return launch(c, KD_TWIDDLE, (double)N * d.cpx_bytes, dim3((N + 255) / 256), dim3(256), 0, k_twiddles<T>,
+                      tw(), N);
+    }
+
+    // P1 from a real field (SRC 0) or from noise (SRC 1) -> S1 field 0 in A
+    int zfwd_single(const T* f, bool noise, uint64_t seed, uint64_t stream) {
+        const int kind = noise ? KD_ZFWD_NOISE : KD_ZFWD_FIELD;
+        return with_variant<T, N>(tu.v[kind], [&](auto vc) {
+            constexpr int V = decltype(vc)::value;
+            using RW = Rows<T, N, V>;
+            ProductInputs<T> pin{};
+            const double bytes = nb() * ((noise ? 0.0 : (double)d.ncell() * d.real_bytes) + (double)d.s1() * d.cpx_bytes);
+            const dim3 grid(N * (N / (2 * RW::RPB)), 1, nz()), block(RW::THREADS);  // two rows per transform
+            if (noise)
+                return launch(c, kind, bytes, grid, block, 0, k_zfwd<T, N, V, 1, 0>, f, pin, seed, stream, A(),
+                              (size_t)L.a_field_s1, (const cpx<T>*)tw(), (int)d.Kz, bt.zs);
+            return launch(c, kind, bytes, grid, block, 0, k_zfwd<T, N, V, 0, 0>, f, pin, seed, stream, A(),
+                          (size_t)L.a_field_s1, (const cpx<T>*)tw(), (int)d.Kz, bt.zs);
+        });
+    }
+
+    // P1 with the products of order n -> S1 fields 0..3 (V_x, V_y, V_z, W) in A
+    int zfwd_products(int n, const ProductInputs<T>& pin) {
+        return with_variant<T, N>(tu.v[KD_ZFWD_PRODUCTS], [&](auto vc) {
+            constexpr int V = decltype(vc)::value;
+            using RW = Rows<T, N, V>;
+            const double bytes = nb() * (4.0 * (n - 1) * d.ncell() * d.real_bytes + 4.0 * d.s1() * d.cpx_bytes);
+            const dim3 grid(N * (N / RW::RPB), 1, nz()), block(RW::THREADS);
+            auto go = [&](auto kern) {
+                return launch(c, KD_ZFWD_PRODUCTS, bytes, grid, block, 0, kern, (const T*)nullptr, pin, (uint64_t)0,
+                              (uint64_t)0, A(), (size_t)L.a_field_s1, (const cpx<T>*)tw(), (int)d.Kz, bt.zs);
+            };
+            switch (n) {
+                case 2: return go(k_zfwd<T, N, V, 2, 2>);
+                case 3: return go(k_zfwd<T, N, V, 2, 3>);
+                case 4: return go(k_zfwd<T, N, V, 2, 4>);
+                case 5: return go(k_zfwd<T, N, V, 2, 5>);
+                default: return (int)GRIDSPT_EINVAL;
+            }
+        });
+    }
+
+    // P2: nf fields S1 (A) -> S2 (B)
+    int yfwd(int nf) {
+        return with_variant<T, N>(tu.v[KD_YFWD], [&](auto vc) {
+            constexpr int V = decltype(vc)::value;
+            using RW = Rows<T, N, V>;
+            const double bytes = nb() * nf * (d.s1() + d.s2()) * d.cpx_bytes;
+            return launch(c, KD_YFWD, bytes, dim3((unsigned)(d.Kz * (N / RW::RPB)), nf, nz()), dim3(RW::THREADS), 0,
+                          k_yfwd<T, N, V>, (const cpx<T>*)A(), (size_t)L.a_field_s1, B(), (size_t)L.b_field_s2,
+                          (const cpx<T>*)tw(), cd, bt.zs);
+        });
+    }
+
+    // P3: S2 (B) -> S3 (A), with the k-space step of `mode`
+    int xfused(int mode, XArgs<T> a) {
+        a.s2 = B();
+        a.s2_field = (size_t)L.b_field_s2;
+        a.s3 = A();
+        a.s3_field = (size_t)L.a_field_s3;
+        const int kind = mode == XM_ORDER ? KD_XFUSED_ORDER
+                                          : (mode == XM_ORDER1 ? KD_XFUSED_ORDER1
+                                                               : (mode == XM_LINEAR ? KD_XFUSED_LINEAR : KD_XFUSED_FORWARD));
+        return with_variant<T, N>(tu.v[kind], [&](auto vc) {
+            constexpr int V = decltype(vc)::value;
+            using RW = Rows<T, N, V>;
+            const int nin = mode == XM_ORDER ? 4 : 1;
+            const int ncube = (a.cube_d ? 1 : 0) + (a.cube_t ? 1 : 0);
+            const double bytes =
+                nb() * ((double)nin * d.s2() + (double)a.nout * d.s3() + (double)ncube * d.cube()) * d.cpx_bytes;
+            const dim3 grid((unsigned)(d.Kz * ((d.Ky + RW::RPB - 1) / RW::RPB)), 1, nz()), block(RW::THREADS);
+            const cpx<T>* t = tw();
+            switch (mode) {
+                case XM_ORDER: return launch(c, kind, bytes, grid, block, 0, k_xfused<T, N, V, XM_ORDER>, a, t, cd, bt.zs);
+                case XM_ORDER1:
+                    return launch(c, kind, bytes, grid, block, 0, k_xfused<T, N, V, XM_ORDER1>, a, t, cd, bt.zs);
+                case XM_LINEAR:
+                    return launch(c, kind, bytes, grid, block, 0, k_xfused<T, N, V, XM_LINEAR>, a, t, cd, bt.zs);
+                default:
+                    return launch(c, kind, bytes, grid, block, 0, k_xfused<T, N, V, XM_FORWARD>, a, t, cd, bt.zs);
+            }
+        });
+    }
+
+    // P3 for shells: nslot cube fields -> S3 (A)
+    int xshell(ShellSlots<T> s, int nslot) {
+        s.s3 = A();
+        s.s3_field = (size_t)L.a_field_s3;
+        return with_variant<T, N>(tu.v[KD_XSHELL], [&](auto vc) {
+            constexpr int V = decltype(vc)::value;
+            using RW = Rows<T, N, V>;
+            int ncube = 0;
+            for (int i = 0; i < nslot; ++i) ncube += s.cube[i] ? 1 : 0;
+            const double bytes = nb() * ((double)ncube * d.cube() + (double)nslot * d.s3()) * d.cpx_bytes;
+            return launch(c, KD_XSHELL, bytes, dim3((unsigned)(d.Kz * ((d.Ky + RW::RPB - 1) / RW::RPB)), nslot, nz()),
+                          dim3(RW::THREADS), 0, k_xshell<T, N, V>, s, (const cpx<T>*)tw(), cd, bt.zs);
+        });
+    }
+
+    // P4: nf fields S3 (A) -> S4 (B)
+    int yinv(int nf) {
+        return with_variant<T, N>(tu.v[KD_YINV], [&](auto vc) {
+            constexpr int V = decltype(vc)::value;
+            using RW = Rows<T, N, V>;
+            const double bytes = nb() * nf * (d.s3() + d.s4()) * d.cpx_bytes;
+            return launch(c, KD_YINV, bytes, dim3((unsigned)(N * ((d.Kz + RW::RPB - 1) / RW::RPB)), nf, nz()),
+                          dim3(RW::THREADS), 0, k_yinv<T, N, V>, (const cpx<T>*)A(), (size_t)L.a_field_s3, B(),
+                          (size_t)L.b_field_s4, (const cpx<T>*)tw(), cd, bt.zs);
+        });
+    }
+
+    // P5: S4 (B) -> real outputs, two real rows per complex transform
+    int zinv(const ZJobs<T>& zj, int njobs) {
+        return with_variant<T, N>(tu.v[KD_ZINV], [&](auto vc) {
+            constexpr int V = decltype(vc)::value;
+            using RW = Rows<T, N, V>;
+            int nout = 0;
+            for (int i = 0; i < njobs; ++i) nout += zj.fb[i] >= 0 ? 2 : 1;
+            const double bytes =
+                nb() * nout * ((double)d.s4() * d.cpx_bytes + (double)d.ncell() * d.real_bytes);
+            return launch(c, KD_ZINV, bytes, dim3((unsigned)(N * N / RW::RPB), njobs, nz()), dim3(RW::THREADS), 0,
+                          k_zinv<T, N, V>, (const cpx<T>*)B(), (size_t)L.b_field_s4, zj, (const cpx<T>*)tw(), cd,
+                          bt.zs);
+        });
+    }
+
+    // P4 + P5 for nf fields of S3 into real outputs out[0..nf-1]: fields two
+    // by two, an odd last field two rows at a time
+    int to_real(int nf, T* const* out) {
+        GRIDSPT_CHECK(yinv(nf));
+        ZJobs<T> zj{};
+        int nj = 0;
+        for (int i = 0; i < nf; i += 2, ++nj) {
+            zj.fa[nj] = i;
+            zj.outa[nj] = out[i];
+            zj.fb[nj] = (i + 1 < nf) ? i + 1 : -1;
+            zj.outb[nj] = (i + 1 < nf) ? out[i + 1] : nullptr;
+        }
+        return zinv(zj, nj);
+    }
+
+    int copy(const T* src, T* dst) {
+        return launch(c, KD_COPY, nb() * 2.0 * d.ncell() * d.real_bytes, dim3(2048, 1, nz()), dim3(256), 0, k_copy<T>,
+                      src, dst, (size_t)d.ncell(), bt.zs);
+    }
+};
+
+template <typename T>
+XArgs<T> make_xargs(const Dims& d, const gridspt_grid* g, int n, int nout, int64_t n2max, cpx<T>* cube_d,
+                    cpx<T>* cube_t) {
+    XArgs<T> a{};
+    a.cube_d = cube_d;
+    a.cube_t = cube_t;
+    a.n = n;
+    a.nout = nout;
+    a.n2max = n2max;
+    a.kF = 2.0 * M_PI / g->box;
+    a.invN3 = 1.0 / ((double)d.N * d.N * d.N);
+    return a;
+}
+
+// Step 1: Gaussian noise -> masked linear field delta_1 (and its cube)
+template <typename T, int N>
+int run_linear_field(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, void* delta1, void* delta1_k,
+                     void* work, const Tuning& tu, Batch b) {
+    Pipe<T, N> p(c, g, work, 1, tu, b);
+    GRIDSPT_CHECK(p.twiddles());
+    GRIDSPT_CHECK(p.zfwd_single(nullptr, true, lp->seed, lp->stream));
+    GRIDSPT_CHECK(p.yfwd(1));
+    XArgs<T> a = make_xargs<T>(p.d, g, 1, 1, lp->n2max, (cpx<T>*)delta1_k, nullptr);
+    a.lin = {lp->amp, lp->ns, lp->gamma, lp->growth, (double)N * N * N / (g->box * g->box * g->box)};
+    GRIDSPT_CHECK(p.xfused(XM_LINEAR, a));
+    T* out[1] = {static_cast<T*>(delta1)};
+    return p.to_real(1, out);
+}
+
+// Masked forward transform of a real field into the cube layout
+template <typename T, int N>
+int run_forward(gridspt_ctx* c, const gridspt_grid* g, int64_t n2max, const void* field, void* field_k, void* work,
+                const Tuning& tu, Batch b) {
+    Pipe<T, N> p(c, g, work, 1, tu, b);
+    GRIDSPT_CHECK(p.twiddles());
+    GRIDSPT_CHECK(p.zfwd_single(static_cast<const T*>(field), false, 0, 0));
+    GRIDSPT_CHECK(p.yfwd(1));
+    XArgs<T> a = make_xargs<T>(p.d, g, 1, 0, n2max, (cpx<T>*)field_k, nullptr);
+    return p.xfused(XM_FORWARD, a);
+}
+
+// Orders 1..nmax of the recursion (Eq. 10 in the divergence form)
+template <typename T, int N>
+int run_orders(gridspt_ctx* c, const gridspt_grid* g, int nmax, int64_t n2max1, int64_t n2max2, const void* delta1,
+               void* const* delta, void* const* theta, void* const* delta_k, void* const* theta_k, void* work,
+               const Tuning& tu, Batch b) {
+    Pipe<T, N> p(c, g, work, nmax, tu, b);
+    auto dk = [&](int i) { return delta_k ? (cpx<T>*)delta_k[i] : nullptr; };
+    auto tk = [&](int i) { return theta_k ? (cpx<T>*)theta_k[i] : nullptr; };
+    GRIDSPT_CHECK(p.twiddles());
+
+    // order 1: delta_1 = theta_1 = W1 delta1_in; u_1 = (-ik/k^2) delta_1
+    GRIDSPT_CHECK(p.zfwd_single(static_cast<const T*>(delta1), false, 0, 0));
+    GRIDSPT_CHECK(p.yfwd(1));
+    {
+        const int nout = nmax > 1 ? 4 : 1;
+        cpx<T>* ct = (tk(0) && tk(0) != dk(0)) ? tk(0) : nullptr;
+        XArgs<T> a = make_xargs<T>(p.d, g, 1, nout, n2max1, dk(0), ct);
+        GRIDSPT_CHECK(p.xfused(XM_ORDER1, a));
+        T* out[4] = {static_cast<T*>(delta[0]), p.U(1, 0), p.U(1, 1), p.U(1, 2)};
+        GRIDSPT_CHECK(p.to_real(nout, out));
+        if (theta[0] && theta[0] != delta[0])
+            GRIDSPT_CHECK(p.copy(static_cast<const T*>(delta[0]), static_cast<T*>(theta[0])));
+    }
+    // orders n >= 2
+    for (int n = 2; n <= nmax; ++n) {
+        ProductInputs<T> pin{};
+        for (int m = 1; m < n; ++m) {
+            pin.d[m - 1] = static_cast<const T*>(delta[m - 1]);
+            for (int j = 0; j < 3; ++j) pin.u[m - 1][j] = p.U(m, j);
+        }
+        GRIDSPT_CHECK(p.zfwd_products(n, pin));
+        GRIDSPT_CHECK(p.yfwd(4));
+        const int nout = n < nmax ? 5 : 2;
+        XArgs<T> a = make_xargs<T>(p.d, g, n, nout, n2max2, dk(n - 1), tk(n - 1));
+        GRIDSPT_CHECK(p.xfused(XM_ORDER, a));
+        T* out[5] = {static_cast<T*>(delta[n - 1]), static_cast<T*>(theta[n - 1]), nullptr, nullptr, nullptr};
+        if (n < nmax)
+            for (int j = 0; j < 3; ++j) out[2 + j] = p.U(n, j);
+        GRIDSPT_CHECK(p.to_real(nout, out));
+    }
+    return GRIDSPT_OK;
+}
+
+// Shell-filtered inverse transforms of the bispectrum estimator, five slots
+// per pass sequence
+template <typename T, int N>
+int run_shells(gridspt_ctx* c, const gridspt_grid* g, int nslots, const void* const* cubes, const int64_t* lo,
+               const int64_t* hi, void* const* out, void* work, const Tuning& tu, Batch b) {
+    Pipe<T, N> p(c, g, work, 1, tu, b);
+    GRIDSPT_CHECK(p.twiddles());
+    for (int s0 = 0; s0 < nslots; s0 += 5) {
+        const int nb = std::min(5, nslots - s0);
+        ShellSlots<T> sh{};
+        T* outs[5];
+        for (int i = 0; i < nb; ++i) {
+            sh.cube[i] = static_cast<const cpx<T>*>(cubes[s0 + i]);
+            sh.lo[i] = lo[s0 + i];
+            sh.hi[i] = hi[s0 + i];
+            outs[i] = static_cast<T*>(out[s0 + i]);
+        }
+        GRIDSPT_CHECK(p.xshell(sh, nb));
+        GRIDSPT_CHECK(p.to_real(nb, outs));
+    }
+    return GRIDSPT_OK;
+}
+
+}  // namespace gridspt
+
+// explicit instantiations for one grid size, both precisions
+#define GRIDSPT_INSTANTIATE_T(T, N)                                                                                \
+    template int gridspt::run_linear_field<T, N>(gridspt_ctx*, const gridspt_grid*, const gridspt_linpk*, void*,  \
+                                                 void*, void*, const gridspt::Tuning&, gridspt::Batch);            \
+    template int gridspt::run_forward<T, N>(gridspt_ctx*, const gridspt_grid*, int64_t, const void*, void*, void*, \
+                                            const gridspt::Tuning&, gridspt::Batch);                               \
+    template int gridspt::run_orders<T, N>(gridspt_ctx*, const gridspt_grid*, int, int64_t, int64_t, const void*,  \
+                                           void* const*, void* const*, void* const*, void* const*, void*,          \
+                                           const gridspt::Tuning&, gridspt::Batch);                                \
+    template int gridspt::run_shells<T, N>(gridspt_ctx*, const gridspt_grid*, int, const void* const*,             \
+                                           const int64_t*, const int64_t*, void* const*, void*,                    \
+                                           const gridspt::Tuning&, gridspt::Batch);
+#define GRIDSPT_INSTANTIATE(N)        \
+    GRIDSPT_INSTANTIATE_T(float, N)   \
+    GRIDSPT_INSTANTIATE_T(double, N)

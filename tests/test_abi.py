@@ -118,7 +118,10 @@ def test_validation_before_any_gpu_work():
         assert lib.gridspt_orders(h, ctypes.byref(G), 3, 455, 455, ws, d, d, None, None, None, 1 << 40) == -3
         # grid: odd, non power of two, kc too large, bad dtype, bad box
         assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(n=63)), 3) == -1
-        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(n=192, kc=60)), 3) == -2
+        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(n=144, kc=47)), 3) == -2  # 9 * 16: not built
+        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(n=200, kc=60)), 3) == -2  # factor 5
+        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(n=192, kc=63)), 3) > 0    # 3 * 64: radix-3 plan
+        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(n=48, kc=15)), 3) > 0
         assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(kc=32)), 3) == -1
         assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(dtype=7)), 3) == -1
         assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(box=-1.0)), 3) == -1
@@ -156,3 +159,57 @@ def test_workspace_sizes_follow_layout():
     got = g.lib().gridspt_workspace_bytes(ctypes.byref(G), 5)
     assert a + b + u <= got <= a + b + u + 4 * 256 + n * 8
     assert g.lib().gridspt_cube_elems(ctypes.byref(G)) == kz * ky * ky
+
+
+def _bgroup(n=32, kc=10, nreal=2, nmax=3, n2=100, pairs=(0, 0), edges=(1, 10, 50, 101), tris=None, terms=None):
+    import numpy as np
+    keep = [np.asarray(pairs, dtype=np.int32), np.asarray(edges, dtype=np.int64)]
+    tb = np.asarray(tris if tris is not None else [], dtype=np.int32)
+    tt = np.asarray(terms if terms is not None else [], dtype=np.int32)
+    keep += [tb, tt]
+    grp = g._BatchGroup(g._Grid(n, 0, 200.0, kc, 0), nreal, nmax, n2, g._LinPk(1.0, 0.96, 0.21, 1.0, n2, 1, 0),
+                        keep[0].size // 2, keep[0].ctypes.data, keep[1].size - 1, keep[1].ctypes.data,
+                        tb.size // 3, tb.ctypes.data if tb.size else None, tt.size // 4,
+                        tt.ctypes.data if tt.size else None)
+    return grp, keep
+
+
+def test_batch_validation_and_layout():
+    """Batch plans are validated and laid out on the host (no device work)."""
+    lib = g.lib()
+    grp, keep = _bgroup()
+    one = lib.gridspt_batch_workspace_bytes(1, ctypes.byref(grp))
+    assert one > 0 and one % 256 == 0
+    # twice the realisations: twice the arena
+    grp2, keep2 = _bgroup(nreal=4)
+    assert lib.gridspt_batch_workspace_bytes(1, ctypes.byref(grp2)) == 2 * one
+    # the per-realisation arena holds at least the fields, workspace and spectra
+    n, nmax = 32, 3
+    assert one // 2 >= g.lib().gridspt_workspace_bytes(ctypes.byref(g._Grid(n, 0, 200.0, 10, 0)), nmax) \
+        + (2 * nmax - 1) * n ** 3 * 4
+    arr = (g._BatchGroup * 2)(grp, grp2)
+    assert lib.gridspt_batch_workspace_bytes(2, arr) == 3 * one
+    # invalid: pair index beyond nmax, nreal 0, nmax 6, mask beyond the cube, bad size, bad term
+    for kw in (dict(pairs=(0, 3)), dict(nreal=0), dict(nmax=6), dict(n2=200), dict(n=144, kc=10),
+               dict(tris=(0, 0, 1), terms=(0, 0, 0, 1))):
+        bad, k = _bgroup(**kw)
+        rc = lib.gridspt_batch_workspace_bytes(1, ctypes.byref(bad))
+        assert rc in (-1, -2), (kw, rc)
+    assert lib.gridspt_batch_workspace_bytes(0, ctypes.byref(grp)) == -1
+    # create: missing outputs or workspace are rejected before any device work
+    h = ctypes.c_void_p()
+    assert lib.gridspt_create(ctypes.byref(h), None) == 0
+    try:
+        out = g._BatchOut()
+        b = ctypes.c_void_p()
+        ws = ctypes.c_void_p(4096 * 256)
+        assert lib.gridspt_batch_create(h, 1, ctypes.byref(grp), ctypes.byref(out), ws, one, 0, ctypes.byref(b)) == -1
+        out.pk_mean = 4096 * 512
+        assert lib.gridspt_batch_create(h, 1, ctypes.byref(grp), ctypes.byref(out), ws, one - 256, 0,
+                                        ctypes.byref(b)) == -3
+        out.pk_std = 4096 * 512 + 8
+        assert lib.gridspt_batch_create(h, 1, ctypes.byref(grp), ctypes.byref(out), ws, one, 0, ctypes.byref(b)) == -4
+        assert lib.gridspt_batch_create(h, 1, ctypes.byref(grp), ctypes.byref(out), ws, one, 8, ctypes.byref(b)) == -1
+        assert not b.value
+    finally:
+        lib.gridspt_destroy(h)
