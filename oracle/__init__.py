@@ -79,6 +79,13 @@ def _load():
                                         ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64,
                                         ctypes.c_uint64, ctypes.c_int, c_dp, c_dp]
         lib.or_linear_modes.restype = ctypes.c_int
+        lib.or_noise_field.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_int64, c_dp, c_dp]
+        lib.or_noise_field.restype = ctypes.c_int
+        lib.or_adjoint_dform.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int64,
+                                         ctypes.c_int64, c_dp, c_dp, c_dp]
+        lib.or_adjoint_dform.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -171,6 +178,30 @@ def linear_field(n: int, box: float, amp: float, ns: float, gamma: float, growth
                                  int(stream), _ptr(out))
     if rc != 0:
         raise MemoryError("oracle linear_field failed")
+    return out
+
+
+def noise_field(w: np.ndarray, box: float, amp: float, ns: float, gamma: float, growth_d: float,
+                n2max1: int) -> np.ndarray:
+    """Step (1) of Sec. II C from a given white-noise field w(x)."""
+    wc = np.ascontiguousarray(w, dtype=np.float64)
+    out = np.zeros_like(wc)
+    if _load().or_noise_field(wc.shape[0], box, amp, ns, gamma, growth_d, int(n2max1), _ptr(wc), _ptr(out)) != 0:
+        raise MemoryError("oracle noise_field failed")
+    return out
+
+
+def adjoint(w: np.ndarray, box: float, amp: float, ns: float, gamma: float, growth_d: float, nmax: int,
+            n2max1: int, n2max2: int, gdelta) -> np.ndarray:
+    """Reverse mode of noise -> delta_1..delta_nmax (linear field and D-form
+    recursion): the gradient dJ/dw(x) of a scalar J given gdelta[n-1] = dJ/d delta_n(x)."""
+    wc = np.ascontiguousarray(w, dtype=np.float64)
+    n = wc.shape[0]
+    g = np.ascontiguousarray(np.asarray(gdelta, dtype=np.float64).reshape(nmax, n, n, n))
+    out = np.zeros_like(wc)
+    if _load().or_adjoint_dform(n, box, amp, ns, gamma, growth_d, nmax, int(n2max1), int(n2max2), _ptr(wc),
+                                _ptr(g), _ptr(out)) != 0:
+        raise MemoryError("oracle adjoint failed")
     return out
 
 

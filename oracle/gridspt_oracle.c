@@ -629,6 +629,185 @@ int or_orders_pform(int N, double L, int nmax, int64_t n2max1, int64_t n2max2,
 }
 
 /* ------------------------------------------------------------------------ */
+/* linear field from a given noise field, and the reverse-mode gradient      */
+/* ------------------------------------------------------------------------ */
+
+/* W1(k) sqrt(P0(k) N^3 / L^3) D at integer mode n2 (zero at k = 0 and outside W1) */
+static double noise_amplitude(long long n2, double kF, double A, double ns, double gamma, double growth,
+                              double vol, int64_t n2max1)
+{
+    if (n2 == 0 || n2 > n2max1) return 0.0;
+    return sqrt(or_p0(kF * sqrt((double)n2), A, ns, gamma) * vol) * growth;
+}
+
+/* Step (1) of Sec. II C with the white noise w(x) given instead of drawn:
+ * delta1 = inverse of W1(k) sqrt(P0(k) N^3 / L^3) D F[w](k). */
+int or_noise_field(int N, double L, double A, double ns, double gamma, double growth, int64_t n2max1,
+                   const double *w, double *delta1)
+{
+    const long M = (long)N * N * N;
+    cplx *F = cnew(N), *tmp = cnew(N);
+    if (!F || !tmp) { free(F); free(tmp); return -1; }
+    const double kF = TWO_PI / L, vol = (double)M / (L * L * L);
+    forward_real(w, F, N);
+    for (long c = 0; c < M; ++c) {
+        const int ix = (int)(c / ((long)N * N)), iy = (int)((c / N) % N), iz = (int)(c % N);
+        F[c] *= noise_amplitude(mode_n2(ix, iy, iz, N), kF, A, ns, gamma, growth, vol, n2max1);
+    }
+    inverse_real(F, delta1, tmp, N);
+    free(F); free(tmp);
+    return 0;
+}
+
+/*
+ * Reverse mode of (noise -> delta_1 -> D-form orders 2..nmax).  Given
+ * gdelta = dJ/d delta_n(x) (nmax consecutive N^3 real fields) for a scalar J,
+ * returns gw = dJ/dw(x).  Every step of the forward map is a real-linear
+ * spectral multiply x -> F^-1[m(k) F[x]] (adjoint: the multiplier conj(m(k)),
+ * since m(-k) = conj(m(k)) for real output) or a pointwise product:
+ *   order n >= 2:  (delta_n, theta_n)^ = W2 c_n M (S_delta, S_theta),
+ *                  M = [[n + 1/2, 1], [3/2, n]], S_delta = i k.V^, S_theta = -(k^2/2) W^,
+ *                  u_n = F^-1[(-i k / k^2) theta_n^]
+ *   adjoint:       G_d = F[g delta_n], G_t = sum_j (+i k_j / k^2) F[g u_n,j],
+ *                  (a, b) = W2 c_n M^T (G_d, G_t),
+ *                  g V_j = F^-1[-i k_j a],  g W = F^-1[-(k^2/2) b]
+ *   products:      V = sum_m delta_m u_{n-m}, W = sum_m u_m . u_{n-m}, so for j < n
+ *                  g delta_j += gV . u_{n-j},  g u_{n-j} += gV delta_j,  g u_j += 2 gW u_{n-j}
+ *   order 1:       delta_1 = theta_1 = F^-1[a1(k) F[w]], a1 = noise_amplitude;
+ *                  gw = F^-1[a1 (F[g delta_1] + sum_j (+i k_j / k^2) F[g u_1,j])]
+ * The forward fields delta_m, u_m (m < nmax) are recomputed here first.
+ */
+int or_adjoint_dform(int N, double L, double A, double ns, double gamma, double growth, int nmax,
+                     int64_t n2max1, int64_t n2max2, const double *w, const double *gdelta, double *gw)
+{
+    if (nmax < 1) return -1;
+    const long M = (long)N * N * N;
+    const double kF = TWO_PI / L, vol = (double)M / (L * L * L);
+    const int nm = nmax - 1;                       /* orders with stored delta_m, u_m */
+    double **dl = calloc((size_t)(nm + 1), sizeof(double *));
+    double **u = calloc((size_t)(3 * nm + 3), sizeof(double *));
+    double **gd = calloc((size_t)(nmax + 1), sizeof(double *));
+    double **gu = calloc((size_t)(3 * nm + 3), sizeof(double *));
+    cplx *dk = cnew(N), *tk = cnew(N), *tmp = cnew(N), *tmp2 = cnew(N), *Gd = cnew(N), *Gt = cnew(N);
+    cplx *Vk[3] = {cnew(N), cnew(N), cnew(N)}, *Wk = cnew(N);
+    double *V = rnew(N), *W = rnew(N), *gV[3] = {rnew(N), rnew(N), rnew(N)}, *gW = rnew(N);
+    for (int m = 1; m <= nm; ++m) {
+        dl[m] = rnew(N);
+        for (int j = 0; j < 3; ++j) { u[3 * m + j] = rnew(N); gu[3 * m + j] = rnew(N); }
+    }
+    for (int m = 1; m <= nmax; ++m) {
+        gd[m] = rnew(N);
+        memcpy(gd[m], gdelta + (long)(m - 1) * M, sizeof(double) * (size_t)M);
+    }
+
+    /* ---- forward: delta_m and u_m for m < nmax ---- */
+    if (nm >= 1) {
+        forward_real(w, dk, N);
+        for (long c = 0; c < M; ++c) {
+            const int ix = (int)(c / ((long)N * N)), iy = (int)((c / N) % N), iz = (int)(c % N);
+            dk[c] *= noise_amplitude(mode_n2(ix, iy, iz, N), kF, A, ns, gamma, growth, vol, n2max1);
+        }
+        inverse_real(dk, dl[1], tmp, N);
+        velocity_from_theta(dk, u + 3, tmp, tmp2, N, kF);
+    }
+    for (int n = 2; n <= nm; ++n) {
+        for (int j = 0; j < 3; ++j) {
+            memset(V, 0, sizeof(double) * (size_t)M);
+            for (int m = 1; m <= n - 1; ++m)
+                for (long c = 0; c < M; ++c) V[c] += dl[m][c] * u[3 * (n - m) + j][c];
+            forward_real(V, Vk[j], N);
+        }
+        memset(W, 0, sizeof(double) * (size_t)M);
+        for (int m = 1; m <= n - 1; ++m)
+            for (int j = 0; j < 3; ++j)
+                for (long c = 0; c < M; ++c) W[c] += u[3 * m + j][c] * u[3 * (n - m) + j][c];
+        forward_real(W, Wk, N);
+        for (long c = 0; c < M; ++c) {
+            const int ix = (int)(c / ((long)N * N)), iy = (int)((c / N) % N), iz = (int)(c % N);
+            const long long n2 = mode_n2(ix, iy, iz, N);
+            if (n2 == 0 || n2 > n2max2) { dk[c] = 0; tk[c] = 0; continue; }
+            const double kx = kF * der_index(ix, N), ky = kF * der_index(iy, N), kz = kF * der_index(iz, N);
+            const cplx sd = I * (kx * Vk[0][c] + ky * Vk[1][c] + kz * Vk[2][c]);
+            const cplx st = -0.5 * kF * kF * (double)n2 * Wk[c];
+            order_combine(n, sd, st, &dk[c], &tk[c]);
+        }
+        inverse_real(dk, dl[n], tmp, N);
+        velocity_from_theta(tk, u + 3 * n, tmp, tmp2, N, kF);
+    }
+
+    /* ---- reverse ---- */
+    for (int n = nmax; n >= 2; --n) {
+        forward_real(gd[n], Gd, N);
+        memset(Gt, 0, sizeof(cplx) * (size_t)M);
+        if (n <= nm)
+            for (int j = 0; j < 3; ++j) {
+                forward_real(gu[3 * n + j], tmp2, N);
+                for (long c = 0; c < M; ++c) {
+                    const int ix = (int)(c / ((long)N * N)), iy = (int)((c / N) % N), iz = (int)(c % N);
+                    Gt[c] += conj(uvec_mult(ix, iy, iz, j, N, kF)) * tmp2[c];
+                }
+            }
+        const double cn = 2.0 / ((2.0 * n + 3.0) * (n - 1.0));
+        for (long c = 0; c < M; ++c) {       /* a -> dk, b -> tk */
+            const int ix = (int)(c / ((long)N * N)), iy = (int)((c / N) % N), iz = (int)(c % N);
+            const long long n2 = mode_n2(ix, iy, iz, N);
+            if (n2 == 0 || n2 > n2max2) { dk[c] = 0; tk[c] = 0; continue; }
+            dk[c] = cn * ((n + 0.5) * Gd[c] + 1.5 * Gt[c]);
+            tk[c] = cn * (Gd[c] + n * Gt[c]);
+        }
+        for (int j = 0; j < 3; ++j) {
+            for (long c = 0; c < M; ++c) {
+                const int ix = (int)(c / ((long)N * N)), iy = (int)((c / N) % N), iz = (int)(c % N);
+                const int d[3] = {der_index(ix, N), der_index(iy, N), der_index(iz, N)};
+                tmp2[c] = -I * kF * d[j] * dk[c];
+            }
+            inverse_real(tmp2, gV[j], tmp, N);
+        }
+        for (long c = 0; c < M; ++c) {
+            const int ix = (int)(c / ((long)N * N)), iy = (int)((c / N) % N), iz = (int)(c % N);
+            tmp2[c] = -0.5 * kF * kF * (double)mode_n2(ix, iy, iz, N) * tk[c];
+        }
+        inverse_real(tmp2, gW, tmp, N);
+        for (int j = 1; j <= n - 1; ++j)
+            for (long c = 0; c < M; ++c) {
+                double s = 0.0;
+                for (int q = 0; q < 3; ++q) {
+                    s += gV[q][c] * u[3 * (n - j) + q][c];
+                    gu[3 * (n - j) + q][c] += gV[q][c] * dl[j][c];
+                    gu[3 * j + q][c] += 2.0 * gW[c] * u[3 * (n - j) + q][c];
+                }
+                gd[j][c] += s;
+            }
+    }
+    /* order 1 */
+    forward_real(gd[1], Gd, N);
+    if (nm >= 1)
+        for (int j = 0; j < 3; ++j) {
+            forward_real(gu[3 + j], tmp2, N);
+            for (long c = 0; c < M; ++c) {
+                const int ix = (int)(c / ((long)N * N)), iy = (int)((c / N) % N), iz = (int)(c % N);
+                Gd[c] += conj(uvec_mult(ix, iy, iz, j, N, kF)) * tmp2[c];
+            }
+        }
+    for (long c = 0; c < M; ++c) {
+        const int ix = (int)(c / ((long)N * N)), iy = (int)((c / N) % N), iz = (int)(c % N);
+        Gd[c] *= noise_amplitude(mode_n2(ix, iy, iz, N), kF, A, ns, gamma, growth, vol, n2max1);
+    }
+    inverse_real(Gd, gw, tmp, N);
+
+    for (int m = 1; m <= nm; ++m) {
+        free(dl[m]);
+        for (int j = 0; j < 3; ++j) { free(u[3 * m + j]); free(gu[3 * m + j]); }
+    }
+    for (int m = 1; m <= nmax; ++m) free(gd[m]);
+    free(dl); free(u); free(gd); free(gu);
+    free(dk); free(tk); free(tmp); free(tmp2); free(Gd); free(Gt);
+    for (int j = 0; j < 3; ++j) { free(Vk[j]); free(gV[j]); }
+    free(Wk); free(V); free(W); free(gW);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* estimators                                                                 */
 /* ------------------------------------------------------------------------ */
 
