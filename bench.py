@@ -189,7 +189,11 @@ def batch_bench(args) -> int:
     torch.cuda.synchronize()
     ms_step = (time.perf_counter() - t0) * 1000.0 / args.steps
     cells = sum(n ** 3 * nreal for n, nreal in BATCH_C4)
-    # one eager, profiled run of the same plan for the per-kernel figures
+    tuning = [b.tuning(i) for i in range(len(groups))]
+    pk_mean = b.out[0]["pk_mean"][0].cpu().tolist()
+    del b
+    torch.cuda.empty_cache()
+    # one eager, profiled run of the same batch for the per-kernel figures
     eager = g.Batch(ctx, groups, tune=not args.no_tune, eager=True)
     eager.run()
     torch.cuda.synchronize()
@@ -210,7 +214,8 @@ def batch_bench(args) -> int:
             print("%-16s launches %4d  %9.3f ms  %8.1f GB/s" % (
                 k, v["launches"], v["ms"], v["bytes"] / max(v["ms"], 1e-9) / 1e6), file=sys.stderr)
         for i, bg in enumerate(groups):
-            print("tuning N=%d: %s" % (bg.grid.n, b.tuning(i)), file=sys.stderr)
+            print("tuning N=%d: %s" % (bg.grid.n, tuning[i]), file=sys.stderr)
+        print("P_11 mean, N=128 group: %s" % ["%.4g" % v for v in pk_mean], file=sys.stderr)
     res = {
         "metric": "Mcells/s to 4th order, batched realisations (cells of all realisations per second)",
         "value": round(cells / (ms_step / 1000.0) / 1e6, 3),

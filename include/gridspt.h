@@ -198,6 +198,35 @@ int gridspt_bispectrum(gridspt_ctx* ctx, const gridspt_grid* g, int32_t nfields,
                        int32_t ntri, const int32_t* tri_bins, int32_t nterms, const int32_t* terms, int32_t nbins,
                        const int64_t* edge_n2, double* bk, double* ntriangles, void* work, int64_t work_bytes);
 
+/* ---- reverse mode (gradients with respect to the white noise) ---- */
+
+/* Step (1) of Sec. II C from a given white-noise field: as
+ * gridspt_linear_field, with w(x) = noise (N^3 real, device) instead of the
+ * Philox draw (lp->seed and lp->stream are unused). */
+int gridspt_noise_field(gridspt_ctx* ctx, const gridspt_grid* g, const gridspt_linpk* lp, const void* noise,
+                        void* delta1, void* delta1_k, void* work, int64_t work_bytes);
+
+/* Device scratch of gridspt_adjoint: the transform buffers plus
+ * 8 (nmax - 1) + 4 real fields. */
+int64_t gridspt_adjoint_workspace_bytes(const gridspt_grid* g, int32_t nmax);
+
+/* Reverse mode of noise -> delta_1 .. delta_nmax, i.e. gridspt_noise_field
+ * followed by gridspt_orders(nmax, lp->n2max, n2max2): for a scalar objective
+ * J of the delta_n alone, given gdelta[n-1] = dJ/d delta_n(x) (host array of
+ * nmax device N^3 real fields), writes gnoise = dJ/dw(x) (N^3 real).  Every
+ * step of the recursion is a spectral multiply, whose adjoint multiplies by
+ * the complex-conjugate multiplier, or a pointwise product, whose adjoint is
+ * the transposed product; the order-n step (Eq. 10) uses the transposed
+ * matrix [[n + 1/2, 3/2], [1, n]].
+ * Checkpoints: delta_k[m], theta_k[m] for m < nmax - 1 are the cube-layout
+ * spectra of delta_(m+1), theta_(m+1) as gridspt_orders stored them in the
+ * forward run (theta_k[0] is unused: theta_1 = delta_1; theta_k may be NULL
+ * when nmax <= 2); delta_m and u_m are regenerated from them.  Inputs are
+ * not modified. */
+int gridspt_adjoint(gridspt_ctx* ctx, const gridspt_grid* g, const gridspt_linpk* lp, int32_t nmax, int64_t n2max2,
+                    const void* const* delta_k, const void* const* theta_k, const void* const* gdelta, void* gnoise,
+                    void* work, int64_t work_bytes);
+
 /* ---- batched realisations in one captured graph ----
  * Many independent realisations, of several grid sizes, computed by one HIP
  * graph: every pass of a size class is one launch over all its realisations

@@ -99,6 +99,9 @@ def lib():
             "gridspt_batch_destroy": ([vp], None),
             "gridspt_batch_buffer": ([vp, i32, i32, i32, i32, ctypes.POINTER(vp)], ctypes.c_int),
             "gridspt_batch_tuning": ([vp, i32, i32, vp, vp, vp], ctypes.c_int),
+            "gridspt_noise_field": ([vp, gp, ctypes.POINTER(_LinPk), vp, vp, vp, vp, i64], ctypes.c_int),
+            "gridspt_adjoint_workspace_bytes": ([gp, i32], i64),
+            "gridspt_adjoint": ([vp, gp, ctypes.POINTER(_LinPk), i32, i64, vp, vp, vp, vp, vp, i64], ctypes.c_int),
             "gridspt_set_profiling": ([vp, i32], ctypes.c_int),
             "gridspt_profile_read": ([vp, i32, vp, vp, vp, vp], ctypes.c_int),
         }
@@ -277,6 +280,74 @@ def linear_field(ctx: Context, grid: Grid, lp: LinearSpectrum, out: Optional[tor
     _check(lib().gridspt_linear_field(ctx.handle, ctypes.byref(g), ctypes.byref(c), _ptr(out), _ptr(out_k),
                                       _ptr(ws), ws.numel()), "linear_field")
     return (out, out_k) if (spectrum or out_k is not None) else out
+
+
+def _linpk(lp: LinearSpectrum) -> _LinPk:
+    return _LinPk(lp.amp, lp.ns, lp.gamma, lp.growth, lp.n2max, lp.seed, lp.stream)
+
+
+def noise_field(ctx: Context, grid: Grid, lp: LinearSpectrum, noise: torch.Tensor,
+                out: Optional[torch.Tensor] = None, out_k: Optional[torch.Tensor] = None):
+    """delta_1 from a given white-noise field (step 1 of Sec. II C without the draw)."""
+    out = out if out is not None else _new_real(grid)
+    g = grid.cstruct
+    c = _linpk(lp)
+    ws = ctx.workspace(workspace_bytes(grid, 1))
+    _check(lib().gridspt_noise_field(ctx.handle, ctypes.byref(g), ctypes.byref(c), _ptr(noise), _ptr(out),
+                                     _ptr(out_k), _ptr(ws), ws.numel()), "noise_field")
+    return out
+
+
+def adjoint(ctx: Context, grid: Grid, lp: LinearSpectrum, nmax: int, n2max2: int, delta_k, theta_k, gdelta,
+            out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """dJ/dw for a scalar J of delta_1..delta_nmax, given gdelta[n-1] = dJ/d delta_n
+    and the forward run's spectra delta_k, theta_k (orders < nmax)."""
+    out = out if out is not None else _new_real(grid)
+    g = grid.cstruct
+    c = _linpk(lp)
+    need = _check(lib().gridspt_adjoint_workspace_bytes(ctypes.byref(g), nmax), "adjoint_workspace_bytes")
+    ws = ctx.workspace(need)
+    nk = max(nmax - 1, 1)
+    dk = _ptr_array(list(delta_k[:nk])) if nmax > 1 else None
+    tk = _ptr_array([None] + list(theta_k[1:nk])) if nmax > 2 else None
+    gd = _ptr_array(list(gdelta))
+    _check(lib().gridspt_adjoint(ctx.handle, ctypes.byref(g), ctypes.byref(c), nmax, n2max2, dk, tk, gd, _ptr(out),
+                                 _ptr(ws), ws.numel()), "adjoint")
+    return out
+
+
+class NoiseToOrders(torch.autograd.Function):
+    """w -> (delta_1, ..., delta_nmax): the linear field from the noise w and
+    the recursion, differentiable in w.  The forward keeps only the spectra
+    of orders < nmax (per-order checkpoints); the backward regenerates the
+    real fields from them and runs the hand-written reverse mode."""
+
+    @staticmethod
+    def forward(fctx, w, gctx, grid, lp, nmax, n2max2):
+        d1 = noise_field(gctx, grid, lp, w.contiguous())
+        out = orders(gctx, grid, nmax, lp.n2max, n2max2, d1, spectra=nmax > 1)
+        keep = []
+        if nmax > 1:
+            keep = list(out.delta_k[:nmax - 1]) + list(out.theta_k[1:nmax - 1])
+        fctx.save_for_backward(*keep)
+        fctx.meta = (gctx, grid, lp, nmax, n2max2)
+        return tuple(out.delta)
+
+    @staticmethod
+    def backward(fctx, *grads):
+        gctx, grid, lp, nmax, n2max2 = fctx.meta
+        saved = fctx.saved_tensors
+        dk = list(saved[:nmax - 1]) if nmax > 1 else []
+        tk = ([dk[0]] + list(saved[nmax - 1:])) if nmax > 2 else dk
+        gdelta = [(g.contiguous() if g is not None else torch.zeros((grid.n,) * 3, dtype=grid.real_dtype,
+                                                                    device="cuda")) for g in grads]
+        gw = adjoint(gctx, grid, lp, nmax, n2max2, dk, tk, gdelta)
+        return gw, None, None, None, None, None
+
+
+def orders_from_noise(w: torch.Tensor, ctx: Context, grid: Grid, lp: LinearSpectrum, nmax: int, n2max2: int):
+    """Differentiable (delta_1, ..., delta_nmax) of the white-noise field w."""
+    return NoiseToOrders.apply(w, ctx, grid, lp, nmax, n2max2)
 
 
 def forward(ctx: Context, grid: Grid, n2max: int, field: torch.Tensor, out_k: Optional[torch.Tensor] = None):

@@ -226,19 +226,29 @@ __global__ __launch_bounds__(kTripleThreads) void k_triple_partial(TripleArgs<T>
     }
 }
 
-// sums of the block partials, item u to out[dst.idx[u]]
+// sums of the block partials, item u to out[dst.idx[u]]: per item a strided
+// sum per thread, then a fixed-order LDS tree (one block of kReduceThreads)
 struct TripleDst {
     int idx[8];
 };
-static __global__ void k_triple_final(const double* partial, int nblocks, int nterms, TripleDst dst, double* out,
-                               size_t zs) {
-    const int u = threadIdx.x;
-    if (u >= nterms) return;
+static __global__ __launch_bounds__(kReduceThreads) void k_triple_final(const double* partial, int nblocks,
+                                                                        int nterms, TripleDst dst, double* out,
+                                                                        size_t zs) {
+    __shared__ double red[kReduceThreads];
     partial = zptr(partial, zs);
     out = zptr(out, zs);
-    double s = 0.0;
-    for (int i = 0; i < nblocks; ++i) s += partial[(size_t)i * 8 + u];
-    out[dst.idx[u]] = s;
+    for (int u = 0; u < nterms; ++u) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < nblocks; i += kReduceThreads) s += partial[(size_t)i * 8 + u];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[dst.idx[u]] = red[0];
+        __syncthreads();
+    }
 }
 
 // bk = L^6 T / J for terms u0 .. u0+nu-1 (both sums over x of the same grid, so
@@ -298,6 +308,51 @@ __global__ void k_copy(const T* __restrict__ src, T* __restrict__ dst, size_t n,
     dst = zptr(dst, zs);
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+// Reverse mode of the products of order NORD (V = sum_m delta_m u_{n-m},
+// W = sum_m u_m . u_{n-m}): with g V, g W the gradients of the sources, for
+// every i < n
+//   g delta_i += g V . u_{n-i},   g u_i += g V delta_{n-i} + 2 g W u_{n-i}.
+// first: the accumulators start from g delta_in (the objective's gradient)
+// and zero instead of their stored values.
+template <typename T>
+struct AdjProducts {
+    const T* gv[4];     // g V_x, g V_y, g V_z, g W
+    const T* d[4];      // delta_1 .. delta_{n-1}
+    const T* u[4][3];   // u_1 .. u_{n-1}
+    const T* gd_in[4];  // objective gradients of delta_1 .. delta_{n-1}
+    T* gd[4];           // accumulators
+    T* gu[4][3];
+    size_t ncell;
+};
+
+template <typename T, int NORD>
+__global__ __launch_bounds__(256) void k_adj_products(AdjProducts<T> a, int first) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell; c += stride) {
+        const T gx = a.gv[0][c], gy = a.gv[1][c], gz = a.gv[2][c], gw = a.gv[3][c];
+#pragma unroll
+        for (int i = 1; i < NORD; ++i) {
+            const int j = NORD - i;  // partner order
+            const T dj = a.d[j - 1][c];
+            const T ux = a.u[j - 1][0][c], uy = a.u[j - 1][1][c], uz = a.u[j - 1][2][c];
+            T gdi = gx * ux + gy * uy + gz * uz;
+            T g0 = gx * dj + (T)2 * gw * ux, g1 = gy * dj + (T)2 * gw * uy, g2 = gz * dj + (T)2 * gw * uz;
+            if (first) {
+                gdi += a.gd_in[i - 1][c];
+            } else {
+                gdi += a.gd[i - 1][c];
+                g0 += a.gu[i - 1][0][c];
+                g1 += a.gu[i - 1][1][c];
+                g2 += a.gu[i - 1][2][c];
+            }
+            a.gd[i - 1][c] = gdi;
+            a.gu[i - 1][0][c] = g0;
+            a.gu[i - 1][1][c] = g1;
+            a.gu[i - 1][2][c] = g2;
+        }
+    }
 }
 
 // Mean and sample standard deviation over nreal realisations of `count`

@@ -242,8 +242,9 @@ int bisp_enqueue(gridspt_ctx* c, const gridspt_grid* g, const void* const* field
                     }
                     CHECK(launch(c, KD_TRIPLE, (double)nz * 3.0 * t.nterms * d.ncell() * d.real_bytes,
                                  dim3(kTripleBlocks, 1, nz), dim3(kTripleThreads), 0, k_triple_partial<T>, t, bt.zs));
-                    CHECK(launch(c, KD_TRIPLE_FINAL, (double)nz * kTripleBlocks * 8.0 * 8.0, dim3(1, 1, nz), dim3(64),
-                                 0, k_triple_final, (const double*)partial, kTripleBlocks, t.nterms, td, dst, bt.zs));
+                    CHECK(launch(c, KD_TRIPLE_FINAL, (double)nz * kTripleBlocks * 8.0 * 8.0, dim3(1, 1, nz),
+                                 dim3(kReduceThreads), 0, k_triple_final, (const double*)partial, kTripleBlocks,
+                                 t.nterms, td, dst, bt.zs));
                 }
                 return GRIDSPT_OK;
             };
@@ -477,7 +478,64 @@ int gridspt_linear_field(gridspt_ctx* c, const gridspt_grid* g, const gridspt_li
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
         constexpr int N = decltype(nc)::value;
-        return run_linear_field<T, N>(c, g, lp, delta1, delta1_k, work, tu, Batch{});
+        return run_linear_field<T, N>(c, g, lp, nullptr, delta1, delta1_k, work, tu, Batch{});
+    });
+}
+
+int gridspt_noise_field(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, const void* noise,
+                        void* delta1, void* delta1_k, void* work, int64_t work_bytes) {
+    if (!c || !lp) return GRIDSPT_EINVAL;
+    CHECK(check_grid(g));
+    CHECK(check_linpk(g, lp));
+    CHECK(check_ptr(noise));
+    CHECK(check_ptr(delta1));
+    if (delta1_k) CHECK(check_ptr(delta1_k));
+    if (!work) return GRIDSPT_EWORKSPACE;
+    CHECK(check_ptr(work));
+    if (work_bytes < gridspt_workspace_bytes(g, 1)) return GRIDSPT_EWORKSPACE;
+    const Tuning tu{};
+    return dispatch(g, [&](auto tag, auto nc) -> int {
+        using T = typename decltype(tag)::type;
+        constexpr int N = decltype(nc)::value;
+        return run_linear_field<T, N>(c, g, lp, noise, delta1, delta1_k, work, tu, Batch{});
+    });
+}
+
+int64_t gridspt_adjoint_workspace_bytes(const gridspt_grid* g, int32_t nmax) {
+    const int rc = check_grid(g);
+    if (rc != GRIDSPT_OK) return rc;
+    if (nmax < 1 || nmax > 5) return GRIDSPT_EINVAL;
+    return adjoint_layout(dims_of(g), nmax).end;
+}
+
+int gridspt_adjoint(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, int32_t nmax, int64_t n2max2,
+                    const void* const* delta_k, const void* const* theta_k, const void* const* gdelta, void* gnoise,
+                    void* work, int64_t work_bytes) {
+    if (!c || !lp || !gdelta) return GRIDSPT_EINVAL;
+    CHECK(check_grid(g));
+    if (nmax < 1 || nmax > 5) return GRIDSPT_EINVAL;
+    CHECK(check_linpk(g, lp));
+    if (nmax > 1) {
+        CHECK(check_mask(g, n2max2));
+        if (!delta_k) return GRIDSPT_EINVAL;
+        for (int m = 0; m < nmax - 1; ++m) {
+            CHECK(check_ptr(delta_k[m]));
+            if (m > 0) {
+                if (!theta_k) return GRIDSPT_EINVAL;
+                CHECK(check_ptr(theta_k[m]));
+            }
+        }
+    }
+    for (int m = 0; m < nmax; ++m) CHECK(check_ptr(gdelta[m]));
+    CHECK(check_ptr(gnoise));
+    if (!work) return GRIDSPT_EWORKSPACE;
+    CHECK(check_ptr(work));
+    if (work_bytes < gridspt_adjoint_workspace_bytes(g, nmax)) return GRIDSPT_EWORKSPACE;
+    const Tuning tu{};
+    return dispatch(g, [&](auto tag, auto nc) -> int {
+        using T = typename decltype(tag)::type;
+        constexpr int N = decltype(nc)::value;
+        return run_adjoint<T, N>(c, g, lp, nmax, n2max2, delta_k, theta_k, gdelta, gnoise, work, tu, Batch{});
     });
 }
 
@@ -734,7 +792,7 @@ int enqueue_group(gridspt_ctx* c, gridspt_batch* b, GroupPlan& p, const Tuning& 
     CHECK(dispatch(gr, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
         constexpr int N = decltype(nc)::value;
-        CHECK((run_linear_field<T, N>(c, gr, &g.lin, delta[0], nullptr, work, tu, bt)));
+        CHECK((run_linear_field<T, N>(c, gr, &g.lin, nullptr, delta[0], nullptr, work, tu, bt)));
         return run_orders<T, N>(c, gr, nmax, g.lin.n2max, g.n2max2, delta[0], delta, theta, cube, nullptr, work, tu,
                                 bt);
     }));

@@ -179,6 +179,8 @@ __device__ __forceinline__ cpx<T> unpack_real_pair(cpx<T> c, cpx<T> m, int which
 // SRC 2: the products of order NORD, V = sum_m delta_m u_{n-m} and
 //   W = sum_m u_m . u_{n-m} (the divergence form of the sources of Eq. 10),
 //   packed as V_x + i V_y and V_z + i W; a block covers RPB consecutive y.
+// SRC 3: four real fields pin.d[0..3] (the reverse mode's g delta, g u),
+//   packed as d0 + i d1 and d2 + i d3; a block covers RPB consecutive y.
 // --------------------------------------------------------------------------
 template <typename T>
 struct ProductInputs {
@@ -216,7 +218,8 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __re
     using RW = Rows<T, N, V>;
     using PL = typename RW::PL;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
-    constexpr int YB = (SRC == 2) ? RPB : 2 * RPB;  // rows of y per block
+    constexpr bool PACK4 = SRC == 2 || SRC == 3;       // four real fields per row
+    constexpr int YB = PACK4 ? RPB : 2 * RPB;  // rows of y per block
     __shared__ cpx<T> lds[RPB * ROWE];
     // twiddles in LDS for FP32 (this pass's LDS traffic is light), else from the cache
     constexpr bool LT = kLdsTwiddles<T> && true;
@@ -226,6 +229,10 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __re
     const Twiddles<T, PL, LT> tws{LT ? twl : tw};
     f = zptr(f, zs);
     s1 = zptr(s1, zs);
+    if constexpr (SRC == 3) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) pin.d[m] = zptr(pin.d[m], zs);
+    }
     if constexpr (SRC == 2) {
 #pragma unroll
         for (int m = 0; m < NORD - 1; ++m) {
@@ -269,6 +276,13 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __re
             const uint32_t o = (uint32_t)(r * N + l + P * e);
             a[e] = {ldo(f0, o), ldo(f0, o + (uint32_t)(RPB * N))};
         }
+    } else if constexpr (SRC == 3) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t o = (uint32_t)(r * N + l + P * e);
+            a[e] = {ldo(pin.d[0] + blockbase, o), ldo(pin.d[1] + blockbase, o)};
+            b[e] = {ldo(pin.d[2] + blockbase, o), ldo(pin.d[3] + blockbase, o)};
+        }
     } else {
         // the packed products are formed here, not after the first transform,
         // so the raw inputs are dead before the FFTs start
@@ -280,7 +294,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __re
         }
     }
 
-    constexpr int NPACK = (SRC == 2) ? 2 : 1;
+    constexpr int NPACK = PACK4 ? 2 : 1;
     static_for<NPACK>([&](auto pkc) {
         constexpr int pk = decltype(pkc)::value;
         cpx<T> v[E];
@@ -294,11 +308,11 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __re
         cpx<T>* out = s1 + ((size_t)x * N + y0);
         for (int idx = threadIdx.x; idx < Kz * YB; idx += RW::THREADS) {
             const int kz = idx / YB, rr = idx % YB;
-            const int team = (SRC == 2) ? rr : rr % RPB;
+            const int team = PACK4 ? rr : rr % RPB;
             const cpx<T> c = lds[team * ROWE + lds_pad(kz)];
             const cpx<T> m = lds[team * ROWE + lds_pad(kz == 0 ? 0 : N - kz)];
             const size_t o = (size_t)kz * N * N + rr;
-            if constexpr (SRC == 2) {
+            if constexpr (PACK4) {
                 out[(size_t)(2 * pk) * s1_field + o] = unpack_real_pair(c, m, 0);
                 out[(size_t)(2 * pk + 1) * s1_field + o] = unpack_real_pair(c, m, 1);
             } else {
@@ -350,7 +364,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yfwd(const cpx<T>*
 // kz.  Forward x transform, the k-space step, optional cube stores, then the
 // inverse x transform of every output field, written transposed to S3.
 // --------------------------------------------------------------------------
-enum XMode { XM_ORDER = 0, XM_ORDER1 = 1, XM_LINEAR = 2, XM_FORWARD = 3 };
+enum XMode { XM_ORDER = 0, XM_ORDER1 = 1, XM_LINEAR = 2, XM_FORWARD = 3, XM_ADJ = 4, XM_ADJ1 = 5 };
 
 template <typename T>
 struct XArgs {
@@ -361,6 +375,7 @@ struct XArgs {
     cpx<T>* cube_d;  // may be null
     cpx<T>* cube_t;  // may be null
     int n, nout;     // order; number of output fields (written as S3 fields 0..nout-1)
+    int nin;         // reverse modes: input fields (1: g delta only, 4: g delta, g u)
     int64_t n2max;   // mask of this order
     double kF, invN3;
     LinParams lin;
@@ -414,11 +429,13 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
 
     // k-space step: sd holds delta_n(k), st holds theta_n(k) afterwards
     cpx<T> sd[E], st[E];
-    constexpr int NIN = (MODE == XM_ORDER) ? 4 : 1;
+    constexpr bool ADJ = MODE == XM_ADJ || MODE == XM_ADJ1;
+    constexpr int NIN = (MODE == XM_ORDER || ADJ) ? 4 : 1;
 #pragma unroll
     for (int e = 0; e < E; ++e) sd[e] = st[e] = {(T)0, (T)0};
     static_for<NIN>([&](auto fc) {
         constexpr int f = decltype(fc)::value;
+        if (ADJ && f >= a.nin) return;
         cpx<T> v[E];
         const cpx<T>* in = a.s2 + (size_t)f * a.s2_field + inbase;
 #pragma unroll
@@ -436,6 +453,26 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
             } else {
 #pragma unroll
                 for (int e = 0; e < E; ++e) st[e] = v[e];
+            }
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                keep_here(sd[e]);
+                keep_here(st[e]);
+            }
+        } else if constexpr (ADJ) {
+            if constexpr (f == 0) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) sd[e] = v[e];  // G_delta (unnormalised)
+            } else {
+                // G_theta += (+i k_f / k^2) F[g u_f]: the adjoint of u = (-i k / k^2) theta
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int kx = signed_pos(l + P * e, N);
+                    const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
+                    const int kf = f == 1 ? kx : (f == 2 ? ky : kz);
+                    const T s = n2 > 0 ? (T)((double)kf / (a.kF * (double)n2)) : (T)0;
+                    st[e] = cadd(st[e], cpx<T>{-v[e].y * s, v[e].x * s});
+                }
             }
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -468,12 +505,26 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
             T s = (T)0;
             if (keep) s = (T)(lin_amplitude(a.kF * sqrt((double)n2), a.lin) * a.invN3);
             sd[e] = cscale(sd[e], s);
+        } else if constexpr (MODE == XM_ADJ) {
+            // (a, b) = W2 c_n M^T (G_delta, G_theta), M = [[n + 1/2, 1], [3/2, n]]
+            const T cn = (T)(2.0 / ((2.0 * a.n + 3.0) * (a.n - 1.0)));
+            const cpx<T> gd = cscale(sd[e], invN3), gt = cscale(st[e], invN3);
+            const T m00 = cn * (T)(a.n + 0.5), m10 = cn * (T)1.5, m01 = cn, m11 = cn * (T)a.n;
+            const cpx<T> av = {m00 * gd.x + m10 * gt.x, m00 * gd.y + m10 * gt.y};
+            const cpx<T> bv = {m01 * gd.x + m11 * gt.x, m01 * gd.y + m11 * gt.y};
+            sd[e] = keep ? av : cpx<T>{(T)0, (T)0};
+            st[e] = keep ? bv : cpx<T>{(T)0, (T)0};
+        } else if constexpr (MODE == XM_ADJ1) {
+            // g w(k) = W1 A(k) (G_delta + G_theta): the transpose of the linear field
+            T s = (T)0;
+            if (keep) s = (T)(lin_amplitude(a.kF * sqrt((double)n2), a.lin) * a.invN3);
+            sd[e] = cscale(cadd(sd[e], st[e]), s);
         } else {
             sd[e] = keep ? cscale(sd[e], invN3) : cpx<T>{(T)0, (T)0};
         }
     }
     // theta_1 = delta_1 below order 2
-    if constexpr (MODE != XM_ORDER) {
+    if constexpr (MODE != XM_ORDER && !ADJ) {
 #pragma unroll
         for (int e = 0; e < E; ++e) st[e] = sd[e];
     }
@@ -491,15 +542,32 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
         }
     }
     if constexpr (MODE != XM_FORWARD) {
-        // outputs.  ORDER: delta, theta, u_x, u_y, u_z;  ORDER1: delta, u_x, u_y, u_z;  LINEAR: delta
-        constexpr int NOUT_MAX = (MODE == XM_ORDER) ? 5 : (MODE == XM_ORDER1 ? 4 : 1);
+        // outputs.  ORDER: delta, theta, u_x, u_y, u_z;  ORDER1: delta, u_x, u_y, u_z;  LINEAR: delta;
+        // ADJ: g V_x, g V_y, g V_z, g W;  ADJ1: g w
+        constexpr int NOUT_MAX = (MODE == XM_ORDER) ? 5 : ((MODE == XM_ORDER1 || MODE == XM_ADJ) ? 4 : 1);
         constexpr int FIRST_U = (MODE == XM_ORDER) ? 2 : 1;
         const size_t outbase = (size_t)kz * N * cd.Ky + ky0;
         static_for<NOUT_MAX>([&](auto oc) {
             constexpr int o = decltype(oc)::value;
             if (o < a.nout) {
                 cpx<T> v[E];
-                if constexpr (o < FIRST_U) {
+                if constexpr (MODE == XM_ADJ) {
+                    // g V_j = F^-1[-i k_j a],  g W = F^-1[-(k^2/2) b]
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const int kx = signed_pos(l + P * e, N);
+                        if constexpr (o < 3) {
+                            const T kj = (T)(a.kF * (double)(o == 0 ? kx : (o == 1 ? ky : kz)));
+                            v[e] = {sd[e].y * kj, -sd[e].x * kj};
+                        } else {
+                            const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
+                            v[e] = cscale(st[e], (T)(-0.5 * a.kF * a.kF * (double)n2));
+                        }
+                    }
+                } else if constexpr (MODE == XM_ADJ1) {
+#pragma unroll
+                    for (int e = 0; e < E; ++e) v[e] = sd[e];
+                } else if constexpr (o < FIRST_U) {
 #pragma unroll
                     for (int e = 0; e < E; ++e) v[e] = (o == 0) ? sd[e] : st[e];
                 } else {
@@ -573,6 +641,68 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xshell(ShellSlots<
     x_inverse_store<T, N, V>(v, lds, row, tws, l,
                                  zptr(a.s3, zs) + (size_t)slot * a.s3_field + (size_t)kz * N * cd.Ky + ky0, cd.Ky,
                                  min(RPB, cd.Ky - ky0));
+}
+
+// --------------------------------------------------------------------------
+// P3 from stored spectra (reverse mode): rows (kz, ky') of the cubes of
+// delta_m and theta_m; inverse x transforms of delta_m and
+// u_m = (-i k / k^2) theta_m, written transposed to S3 fields 0..3.
+// --------------------------------------------------------------------------
+template <typename T>
+struct RegenArgs {
+    const cpx<T>* cube_d;
+    const cpx<T>* cube_t;
+    cpx<T>* s3;
+    size_t s3_field;
+    double kF;
+};
+
+template <typename T, int N, int V>
+__global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xregen(RegenArgs<T> a, const cpx<T>* __restrict__ tw,
+                                                                      CubeDims cd, size_t zs) {
+    using RW = Rows<T, N, V>;
+    using PL = typename RW::PL;
+    constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
+    __shared__ cpx<T> lds[RPB * ROWE];
+    const Twiddles<T, PL, false> tws{tw};
+    const uint32_t groups = (cd.Ky + RPB - 1) / RPB;
+    const uint32_t blk = xcd_block(blockIdx.x, cd.Kz * groups);
+    const int kz = blk / groups, ky0 = (blk % groups) * RPB;
+    const int r = threadIdx.x / P, l = threadIdx.x % P;
+    const int kyc = ky0 + r;
+    const bool active = kyc < cd.Ky;
+    const int ky = active ? (kyc <= cd.Kc ? kyc : kyc - cd.Ky) : 0;
+    const int nrows = min(RPB, cd.Ky - ky0);
+    const size_t cbase = ((size_t)kz * cd.Ky + kyc) * cd.Ky;
+    const cpx<T>* cdl = zptr(a.cube_d, zs);
+    const cpx<T>* ctl = zptr(a.cube_t, zs);
+    cpx<T>* s3 = zptr(a.s3, zs);
+    cpx<T>* row = lds + r * ROWE;
+    const size_t outbase = (size_t)kz * N * cd.Ky + ky0;
+    static_for<4>([&](auto oc) {
+        constexpr int o = decltype(oc)::value;
+        cpx<T> v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = l + P * e;
+            const int ic = pos_to_compact(p, cd.Kc, N);
+            cpx<T> c = {(T)0, (T)0};
+            if (active && ic >= 0) {
+                if constexpr (o == 0) {
+                    c = cdl[cbase + ic];
+                } else {
+                    const int kx = signed_pos(p, N);
+                    const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
+                    const int kj = o == 1 ? kx : (o == 2 ? ky : kz);
+                    const T sc = n2 > 0 ? (T)((double)kj / (a.kF * (double)n2)) : (T)0;
+                    const cpx<T> t = ctl[cbase + ic];
+                    c = {t.y * sc, -t.x * sc};
+                }
+            }
+            v[e] = c;
+        }
+        x_inverse_store<T, N, V>(v, lds, row, tws, l, s3 + (size_t)o * a.s3_field + outbase, cd.Ky, nrows);
+    });
 }
 
 // --------------------------------------------------------------------------

@@ -78,6 +78,33 @@ struct Pipe {
         });
     }
 
+    // P1 of four real fields (packed two per transform) -> S1 fields 0..3 in A
+    int zfwd_four(const T* const* f) {
+        return with_variant<T, N>(tu.v[KD_ZFWD_ADJ], [&](auto vc) {
+            constexpr int V = decltype(vc)::value;
+            using RW = Rows<T, N, V>;
+            ProductInputs<T> pin{};
+            for (int i = 0; i < 4; ++i) pin.d[i] = f[i];
+            const double bytes = nb() * (4.0 * d.ncell() * d.real_bytes + 4.0 * d.s1() * d.cpx_bytes);
+            return launch(c, KD_ZFWD_ADJ, bytes, dim3(N * (N / RW::RPB), 1, nz()), dim3(RW::THREADS), 0,
+                          k_zfwd<T, N, V, 3, 0>, (const T*)nullptr, pin, (uint64_t)0, (uint64_t)0, A(),
+                          (size_t)L.a_field_s1, (const cpx<T>*)tw(), (int)d.Kz, bt.zs);
+        });
+    }
+
+    // P3 from stored spectra: delta_m, u_m (4 fields) -> S3 (A)
+    int xregen(RegenArgs<T> r) {
+        r.s3 = A();
+        r.s3_field = (size_t)L.a_field_s3;
+        return with_variant<T, N>(tu.v[KD_XREGEN], [&](auto vc) {
+            constexpr int V = decltype(vc)::value;
+            using RW = Rows<T, N, V>;
+            const double bytes = nb() * (2.0 * d.cube() + 4.0 * d.s3()) * d.cpx_bytes;
+            return launch(c, KD_XREGEN, bytes, dim3((unsigned)(d.Kz * ((d.Ky + RW::RPB - 1) / RW::RPB)), 1, nz()),
+                          dim3(RW::THREADS), 0, k_xregen<T, N, V>, r, (const cpx<T>*)tw(), cd, bt.zs);
+        });
+    }
+
     // P1 with the products of order n -> S1 fields 0..3 (V_x, V_y, V_z, W) in A
     int zfwd_products(int n, const ProductInputs<T>& pin) {
         return with_variant<T, N>(tu.v[KD_ZFWD_PRODUCTS], [&](auto vc) {
@@ -117,13 +144,16 @@ struct Pipe {
         a.s2_field = (size_t)L.b_field_s2;
         a.s3 = A();
         a.s3_field = (size_t)L.a_field_s3;
-        const int kind = mode == XM_ORDER ? KD_XFUSED_ORDER
-                                          : (mode == XM_ORDER1 ? KD_XFUSED_ORDER1
-                                                               : (mode == XM_LINEAR ? KD_XFUSED_LINEAR : KD_XFUSED_FORWARD));
+        const int kind = mode == XM_ORDER    ? KD_XFUSED_ORDER
+                         : mode == XM_ORDER1 ? KD_XFUSED_ORDER1
+                         : mode == XM_LINEAR ? KD_XFUSED_LINEAR
+                         : mode == XM_ADJ    ? KD_XFUSED_ADJ
+                         : mode == XM_ADJ1   ? KD_XFUSED_ADJ1
+                                             : KD_XFUSED_FORWARD;
         return with_variant<T, N>(tu.v[kind], [&](auto vc) {
             constexpr int V = decltype(vc)::value;
             using RW = Rows<T, N, V>;
-            const int nin = mode == XM_ORDER ? 4 : 1;
+            const int nin = mode == XM_ORDER ? 4 : ((mode == XM_ADJ || mode == XM_ADJ1) ? a.nin : 1);
             const int ncube = (a.cube_d ? 1 : 0) + (a.cube_t ? 1 : 0);
             const double bytes =
                 nb() * ((double)nin * d.s2() + (double)a.nout * d.s3() + (double)ncube * d.cube()) * d.cpx_bytes;
@@ -135,6 +165,9 @@ struct Pipe {
                     return launch(c, kind, bytes, grid, block, 0, k_xfused<T, N, V, XM_ORDER1>, a, t, cd, bt.zs);
                 case XM_LINEAR:
                     return launch(c, kind, bytes, grid, block, 0, k_xfused<T, N, V, XM_LINEAR>, a, t, cd, bt.zs);
+                case XM_ADJ: return launch(c, kind, bytes, grid, block, 0, k_xfused<T, N, V, XM_ADJ>, a, t, cd, bt.zs);
+                case XM_ADJ1:
+                    return launch(c, kind, bytes, grid, block, 0, k_xfused<T, N, V, XM_ADJ1>, a, t, cd, bt.zs);
                 default:
                     return launch(c, kind, bytes, grid, block, 0, k_xfused<T, N, V, XM_FORWARD>, a, t, cd, bt.zs);
             }
@@ -218,13 +251,14 @@ XArgs<T> make_xargs(const Dims& d, const gridspt_grid* g, int n, int nout, int64
     return a;
 }
 
-// Step 1: Gaussian noise -> masked linear field delta_1 (and its cube)
+// Step 1: Gaussian noise (drawn, or given in `noise`) -> masked linear field
+// delta_1 (and its cube)
 template <typename T, int N>
-int run_linear_field(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, void* delta1, void* delta1_k,
-                     void* work, const Tuning& tu, Batch b) {
+int run_linear_field(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, const void* noise,
+                     void* delta1, void* delta1_k, void* work, const Tuning& tu, Batch b) {
     Pipe<T, N> p(c, g, work, 1, tu, b);
     GRIDSPT_CHECK(p.twiddles());
-    GRIDSPT_CHECK(p.zfwd_single(nullptr, true, lp->seed, lp->stream));
+    GRIDSPT_CHECK(p.zfwd_single(static_cast<const T*>(noise), noise == nullptr, lp->seed, lp->stream));
     GRIDSPT_CHECK(p.yfwd(1));
     XArgs<T> a = make_xargs<T>(p.d, g, 1, 1, lp->n2max, (cpx<T>*)delta1_k, nullptr);
     a.lin = {lp->amp, lp->ns, lp->gamma, lp->growth, (double)N * N * N / (g->box * g->box * g->box)};
@@ -311,12 +345,99 @@ int run_shells(gridspt_ctx* c, const gridspt_grid* g, int nslots, const void* co
     return GRIDSPT_OK;
 }
 
+// Reverse mode of noise -> delta_1 .. delta_nmax (linear field from given
+// noise, then the D-form orders), for an objective of the delta_n only:
+// regenerate delta_m, u_m (m < nmax) from the stored spectra, then run the
+// orders backwards (the transposed order step, then the transposed products),
+// then the transposed linear field.
+template <typename T, int N>
+int run_adjoint(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, int nmax, int64_t n2max2,
+                const void* const* delta_k, const void* const* theta_k, const void* const* gdelta, void* gnoise,
+                void* work, const Tuning& tu, Batch b) {
+    Pipe<T, N> p(c, g, work, 1, tu, b);
+    const AdjLayout al = adjoint_layout(p.d, nmax);
+    T* base = reinterpret_cast<T*>(static_cast<char*>(work) + al.fields);
+    const size_t nc = (size_t)p.d.ncell();
+    auto fld = [&](int64_t i) { return base + (size_t)i * nc; };
+    // field map: D(m) 0..nmax-2, U(m, j), GD(m), GU(m, j), GV(q)
+    const int nm = nmax - 1;
+    auto D = [&](int m) { return fld(m - 1); };
+    auto U = [&](int m, int j) { return fld(nm + 3 * (m - 1) + j); };
+    auto GD = [&](int m) { return fld(4 * nm + (m - 1)); };
+    auto GU = [&](int m, int j) { return fld(5 * nm + 3 * (m - 1) + j); };
+    auto GV = [&](int q) { return fld(8 * nm + q); };
+    GRIDSPT_CHECK(p.twiddles());
+    const double kF = 2.0 * M_PI / g->box;
+    for (int m = 1; m <= nm; ++m) {
+        RegenArgs<T> r{};
+        r.cube_d = static_cast<const cpx<T>*>(delta_k[m - 1]);
+        r.cube_t = static_cast<const cpx<T>*>((m == 1 || !theta_k[m - 1]) ? delta_k[m - 1] : theta_k[m - 1]);
+        r.kF = kF;
+        GRIDSPT_CHECK(p.xregen(r));
+        T* out[4] = {D(m), U(m, 0), U(m, 1), U(m, 2)};
+        GRIDSPT_CHECK(p.to_real(4, out));
+    }
+    // forward transform of the objective gradient of order n (and g u_n)
+    auto fwd = [&](int n) -> int {
+        if (n == nmax) {
+            GRIDSPT_CHECK(p.zfwd_single(static_cast<const T*>(gdelta[n - 1]), false, 0, 0));
+            return p.yfwd(1);
+        }
+        const T* f[4] = {GD(n), GU(n, 0), GU(n, 1), GU(n, 2)};
+        GRIDSPT_CHECK(p.zfwd_four(f));
+        return p.yfwd(4);
+    };
+    for (int n = nmax; n >= 2; --n) {
+        GRIDSPT_CHECK(fwd(n));
+        XArgs<T> a = make_xargs<T>(p.d, g, n, 4, n2max2, nullptr, nullptr);
+        a.nin = n == nmax ? 1 : 4;
+        GRIDSPT_CHECK(p.xfused(XM_ADJ, a));
+        T* out[4] = {GV(0), GV(1), GV(2), GV(3)};
+        GRIDSPT_CHECK(p.to_real(4, out));
+        AdjProducts<T> ap{};
+        for (int q = 0; q < 4; ++q) ap.gv[q] = GV(q);
+        for (int i = 1; i < n; ++i) {
+            ap.d[i - 1] = D(i);
+            ap.gd_in[i - 1] = static_cast<const T*>(gdelta[i - 1]);
+            ap.gd[i - 1] = GD(i);
+            for (int j = 0; j < 3; ++j) {
+                ap.u[i - 1][j] = U(i, j);
+                ap.gu[i - 1][j] = GU(i, j);
+            }
+        }
+        ap.ncell = nc;
+        const double bytes = (double)nc * p.d.real_bytes * (4.0 + 4.0 * (n - 1) + 8.0 * (n - 1) - (n == nmax ? 3.0 * (n - 1) : 0.0));
+        const int first = n == nmax ? 1 : 0;
+        auto go = [&](auto kern) {
+            return launch(c, KD_ADJ_PRODUCTS, bytes, dim3(4096), dim3(256), 0, kern, ap, first);
+        };
+        switch (n) {
+            case 2: GRIDSPT_CHECK(go(k_adj_products<T, 2>)); break;
+            case 3: GRIDSPT_CHECK(go(k_adj_products<T, 3>)); break;
+            case 4: GRIDSPT_CHECK(go(k_adj_products<T, 4>)); break;
+            case 5: GRIDSPT_CHECK(go(k_adj_products<T, 5>)); break;
+            default: return GRIDSPT_EINVAL;
+        }
+    }
+    GRIDSPT_CHECK(fwd(1));
+    XArgs<T> a = make_xargs<T>(p.d, g, 1, 1, lp->n2max, nullptr, nullptr);
+    a.nin = nmax == 1 ? 1 : 4;
+    a.lin = {lp->amp, lp->ns, lp->gamma, lp->growth, (double)N * N * N / (g->box * g->box * g->box)};
+    GRIDSPT_CHECK(p.xfused(XM_ADJ1, a));
+    T* out[1] = {static_cast<T*>(gnoise)};
+    return p.to_real(1, out);
+}
+
 }  // namespace gridspt
 
 // explicit instantiations for one grid size, both precisions
 #define GRIDSPT_INSTANTIATE_T(T, N)                                                                                \
-    template int gridspt::run_linear_field<T, N>(gridspt_ctx*, const gridspt_grid*, const gridspt_linpk*, void*,  \
-                                                 void*, void*, const gridspt::Tuning&, gridspt::Batch);            \
+    template int gridspt::run_linear_field<T, N>(gridspt_ctx*, const gridspt_grid*, const gridspt_linpk*,         \
+                                                 const void*, void*, void*, void*, const gridspt::Tuning&,         \
+                                                 gridspt::Batch);                                                  \
+    template int gridspt::run_adjoint<T, N>(gridspt_ctx*, const gridspt_grid*, const gridspt_linpk*, int, int64_t, \
+                                            const void* const*, const void* const*, const void* const*, void*,     \
+                                            void*, const gridspt::Tuning&, gridspt::Batch);                        \
     template int gridspt::run_forward<T, N>(gridspt_ctx*, const gridspt_grid*, int64_t, const void*, void*, void*, \
                                             const gridspt::Tuning&, gridspt::Batch);                               \
     template int gridspt::run_orders<T, N>(gridspt_ctx*, const gridspt_grid*, int, int64_t, int64_t, const void*,  \

@@ -41,6 +41,11 @@ enum Kind {
     KD_SUM_ORDERS,
     KD_COPY,
     KD_BATCH_STATS,
+    KD_ZFWD_ADJ,
+    KD_XREGEN,
+    KD_XFUSED_ADJ,
+    KD_XFUSED_ADJ1,
+    KD_ADJ_PRODUCTS,
     KD_COUNT
 };
 
@@ -48,7 +53,8 @@ inline const char* const kKindNames[KD_COUNT] = {
     "twiddles",      "zfwd_field",     "zfwd_noise",   "zfwd_products", "yfwd",        "xfused_linear",
     "xfused_order1", "xfused_order",   "xfused_forward", "xshell",      "yinv",        "zinv",
     "power_partial", "power_final",    "triple_partial", "triple_final", "bisp_final", "sum_orders",
-    "copy",          "batch_stats"};
+    "copy",          "batch_stats",    "zfwd_adjoint", "xregen",        "xfused_adj",  "xfused_adj1",
+    "adj_products"};
 
 // Launch variant of each pass kind (see Rows): 0 is the default shape.
 struct Tuning {
@@ -239,9 +245,10 @@ struct Batch {
 // ---------------------------------------------------------------------------
 // pass sequences, defined in pipeline.hpp and instantiated per grid size
 // ---------------------------------------------------------------------------
+// noise: a given white-noise field (N^3 real), or null to draw it (Philox)
 template <typename T, int N>
-int run_linear_field(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, void* delta1, void* delta1_k,
-                     void* work, const Tuning& tu, Batch b);
+int run_linear_field(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, const void* noise,
+                     void* delta1, void* delta1_k, void* work, const Tuning& tu, Batch b);
 template <typename T, int N>
 int run_forward(gridspt_ctx* c, const gridspt_grid* g, int64_t n2max, const void* field, void* field_k, void* work,
                 const Tuning& tu, Batch b);
@@ -254,6 +261,26 @@ int run_orders(gridspt_ctx* c, const gridspt_grid* g, int nmax, int64_t n2max1, 
 template <typename T, int N>
 int run_shells(gridspt_ctx* c, const gridspt_grid* g, int nslots, const void* const* cubes, const int64_t* lo,
                const int64_t* hi, void* const* out, void* work, const Tuning& tu, Batch b);
+
+// reverse mode of run_linear_field (given noise) + run_orders, see adjoint_layout
+template <typename T, int N>
+int run_adjoint(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, int nmax, int64_t n2max2,
+                const void* const* delta_k, const void* const* theta_k, const void* const* gdelta, void* gnoise,
+                void* work, const Tuning& tu, Batch b);
+
+// Workspace of the reverse mode: the pipeline (no u fields) | delta_m, u_m
+// (m < nmax, regenerated) | their gradient accumulators | g V, g W.
+struct AdjLayout {
+    int64_t fields, end;  // first real field, total bytes
+    int64_t nfield;       // real fields
+};
+inline AdjLayout adjoint_layout(const Dims& d, int nmax) {
+    AdjLayout a;
+    a.fields = layout_of(d, 1).end;
+    a.nfield = 8 * (int64_t)(nmax - 1) + 4;
+    a.end = align_up(a.fields + a.nfield * d.ncell() * d.real_bytes);
+    return a;
+}
 
 // Call f(tag_t<T>, integral_constant<int, N>) for the grid's precision and size.
 template <typename F>
