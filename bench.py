@@ -240,12 +240,106 @@ def batch_bench(args) -> int:
     return 0
 
 
+def adjoint_cpu_baseline(n_sample: int = 256, box: float = 1000.0, nmax: int = 3):
+    """The FP64 oracle's reverse mode (as it stands) on a bounded sample: the
+    forward recursion plus the adjoint, n_sample^3 grid, all host threads."""
+    import numpy as np
+
+    import oracle
+    cores = oracle.set_threads(0)
+    amp = oracle.sigma8_amp(0.8, 0.96, 0.21)
+    cut = oracle.cut_n2max_strict(n_sample)
+    rng = np.random.default_rng(0)
+    w = rng.standard_normal((n_sample,) * 3)
+    gd = rng.standard_normal((nmax,) + (n_sample,) * 3)
+    t0 = time.perf_counter()
+    d1 = oracle.noise_field(w, box, amp, 0.96, 0.21, 1.0, cut)
+    oracle.orders(d1, box, nmax, cut, cut, spectra=True)
+    oracle.adjoint(w, box, amp, 0.96, 0.21, 1.0, nmax, cut, cut, gd)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample ** 3 / dt / 1e6, "unit": "Mcells/s", "cores": int(cores), "kind": "oracle",
+            "sample": "%d^3 grid, L=%g, forward orders 1..%d + reverse mode, FP64, %.1f s" % (n_sample, box, nmax, dt)}
+
+
+def adjoint_bench(args) -> int:
+    """C5: gradient of the field-level loss sum_k L^3 |delta_obs - sum_n delta_n|^2 / P_noise
+    with respect to the white noise, 256^3, L = 1000 Mpc/h, z = 1, n <= 3, FP32.
+    One step = noise -> linear field -> orders 1..3 (spectra of orders 1, 2 kept
+    as checkpoints) -> objective gradient -> reverse mode to dJ/dw."""
+    import torch
+
+    import paper_1807_04215_amd as g
+
+    n, box, nmax, pnoise = 256, 1000.0, 3, 100.0
+    cut = g.cut_n2max(n, box)
+    grid = g.Grid(n, box, g.cube_kc(cut), g.F32)
+    lp = g.LinearSpectrum(amp=g.sigma8_amp(0.8, 0.96, 0.21), ns=0.96, gamma=0.21,
+                          growth=g.growth(0.279, 0.721, 1.0), n2max=cut, seed=5)
+    ctx = g.Context()
+    # observed field: a seeded fifth-order field plus white noise of power P_noise
+    obs_lp = g.LinearSpectrum(**{**lp.__dict__, "seed": 77})
+    d1 = g.linear_field(ctx, grid, obs_lp)
+    o5 = g.orders(ctx, grid, 5, cut, cut, d1, spectra=False)
+    gen = torch.Generator(device="cuda").manual_seed(78)
+    obs = sum(o5.delta) + torch.randn((n,) * 3, generator=gen, device="cuda") * (pnoise * n ** 3 / box ** 3) ** 0.5
+    del o5, d1
+    w = torch.randn((n,) * 3, generator=gen, device="cuda")
+    scale = -2.0 * box ** 3 / pnoise / n ** 3
+
+    def step():
+        d1 = g.noise_field(ctx, grid, lp, w)
+        out = g.orders(ctx, grid, nmax, cut, cut, d1)
+        r = (obs - sum(out.delta)) * scale  # dJ/d delta_n, the same for every n
+        return g.adjoint(ctx, grid, lp, nmax, cut, out.delta_k, out.theta_k, [r] * nmax)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        gw = step()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1000.0 / args.steps
+    ctx.set_profiling(False)
+    prof = ctx.profile_read()
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    d = prof[dom]
+    achieved = d["bytes"] / (d["ms"] / 1000.0) / 1e9
+    kern_ms = sum(v["ms"] for v in prof.values())
+    if args.kernels:
+        for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"]):
+            print("%-16s launches %4d  %9.3f ms/step  %8.1f GB/s" % (
+                k, v["launches"], v["ms"] / args.steps, v["bytes"] / max(v["ms"], 1e-9) / 1e6), file=sys.stderr)
+    res = {
+        "metric": "Mcells/s of forward + reverse mode (gradient w.r.t. the white noise), 3rd order",
+        "value": round(n ** 3 / (ms_step / 1000.0) / 1e6, 3), "unit": "Mcells/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded white noise; observed field = seeded 5th-order field + white noise, P_noise=100)",
+        "config": {"workload": "c5: 256^3 grid, L=1000 Mpc/h, z=1, n=1..3, FP32, cut 2/3 k_Nyq, gradient of "
+                               "sum_k L^3 |delta_obs - sum_n delta_n|^2 / P_noise w.r.t. the white noise, "
+                               "spectra of orders < 3 as checkpoints",
+                   "grad_rms": float(gw.double().pow(2).mean().sqrt().item())},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "launch_ms": round(d["ms"] / d["launches"], 3),
+                     "algorithmic_gb_per_launch": round(d["bytes"] / d["launches"] / 1e9, 3)},
+        "kernel_ms_per_step": round(kern_ms / args.steps, 3),
+        "path_gbs": round(sum(v["bytes"] for v in prof.values()) / (kern_ms / 1000.0) / 1e9, 1),
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = adjoint_cpu_baseline()
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS) + ["c4"])
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS) + ["c4", "c5"])
     ap.add_argument("--no-tune", action="store_true", help="c4: skip the autotuner")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -280,6 +374,8 @@ def main() -> int:
         return precision_report(args)
     if args.workload == "c4":
         return batch_bench(args)
+    if args.workload == "c5":
+        return adjoint_bench(args)
     n, box, z, nmax, nbins, desc = WORKLOADS[args.workload]
     dtype = g.F64 if args.dtype == "f64" else g.F32
     cut = g.cut_n2max(n, box)
