@@ -334,12 +334,98 @@ def adjoint_bench(args) -> int:
     return 0
 
 
+def pform_bench(args) -> int:
+    """C6: the paper-literal P-form on the paper's own grid and cuts: 512^3,
+    L = 1000 Mpc/h, z = 0, k_cut = 1 h/Mpc for the linear field and 4/3 h/Mpc for
+    the higher orders (Sec. II C), n <= 5, FP32.  One step = linear field ->
+    P-form orders 1..5 (17 derived fields per order).  After the timed steps
+    the D-form runs on the same linear field and the per-order P - D
+    difference (the aliased terms the paper's cut admits) is reported."""
+    import torch
+
+    import paper_1807_04215_amd as g
+
+    n, box, nmax = 512, 1000.0, 5
+    cut1 = g.cut_n2max(n, box, 1.0)
+    cut2 = g.cut_n2max(n, box, 4.0 / 3.0)
+    grid = g.Grid(n, box, g.cube_kc(cut2), g.F32)
+    lp = g.LinearSpectrum(amp=g.sigma8_amp(0.8, 0.96, 0.21), ns=0.96, gamma=0.21, growth=1.0, n2max=cut1, seed=6)
+    ctx = g.Context()
+    d1 = g.linear_field(ctx, grid, lp)
+    out = g.alloc_orders(grid, nmax, spectra=True)
+
+    def step():
+        g.linear_field(ctx, grid, lp, out=d1)
+        g.orders_pform(ctx, grid, nmax, cut1, cut2, d1, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1000.0 / args.steps
+    ctx.set_profiling(False)
+    prof = ctx.profile_read()
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    dd = prof[dom]
+    achieved = dd["bytes"] / (dd["ms"] / 1000.0) / 1e9
+    kern_ms = sum(v["ms"] for v in prof.values())
+    if args.kernels:
+        for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"]):
+            print("%-16s launches %4d  %9.3f ms/step  %8.1f GB/s" % (
+                k, v["launches"], v["ms"] / args.steps, v["bytes"] / max(v["ms"], 1e-9) / 1e6), file=sys.stderr)
+    # P - D per order on the same linear field, and the de-aliased control (strict 2/3 cut)
+    dform = g.orders(ctx, grid, nmax, cut1, cut2, d1, spectra=False)
+    torch.cuda.synchronize()
+    pd = []
+    for i in range(nmax):
+        a, b = out.delta[i].double(), dform.delta[i].double()
+        pd.append(float((torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item()))
+        del a, b
+    del dform
+    torch.cuda.empty_cache()
+    res = {
+        "metric": "Mcells/s to 5th order, P-form (printed sources of Eq. 10)",
+        "value": round(n ** 3 / (ms_step / 1000.0) / 1e6, 3), "unit": "Mcells/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded Gaussian linear field, BBKS P0, sigma8=0.8)",
+        "config": {"workload": "c6: 512^3 grid, L=1000 Mpc/h, z=0, n=1..5, FP32, P-form, cuts 1 and 4/3 h/Mpc "
+                               "(n2max %d and %d), 17 derived fields per order" % (cut1, cut2),
+                   "p_minus_d_rel_l2_delta": ["%.3e" % e for e in pd]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "launch_ms": round(dd["ms"] / dd["launches"], 3),
+                     "algorithmic_gb_per_launch": round(dd["bytes"] / dd["launches"] / 1e9, 3)},
+        "kernel_ms_per_step": round(kern_ms / args.steps, 3),
+        "path_gbs": round(sum(v["bytes"] for v in prof.values()) / (kern_ms / 1000.0) / 1e9, 1),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        cores = oracle.set_threads(0)
+        ns_ = 256
+        c1 = oracle.cut_n2max_abs(ns_, box * ns_ / n, 1.0)
+        c2 = oracle.cut_n2max_abs(ns_, box * ns_ / n, 4.0 / 3.0)
+        t0 = time.perf_counter()
+        x = oracle.linear_field(ns_, box * ns_ / n, lp.amp, 0.96, 0.21, 1.0, c1, 6)
+        oracle.orders(x, box * ns_ / n, nmax, c1, c2, form="P", spectra=False)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": ns_ ** 3 / dt / 1e6, "unit": "Mcells/s", "cores": int(cores), "kind": "oracle",
+                               "sample": "%d^3 grid at the same cell size and cuts, linear field + P-form orders "
+                                         "1..%d, FP64, %.1f s" % (ns_, nmax, dt)}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS) + ["c4", "c5"])
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS) + ["c4", "c5", "c6"])
     ap.add_argument("--no-tune", action="store_true", help="c4: skip the autotuner")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -376,6 +462,8 @@ def main() -> int:
         return batch_bench(args)
     if args.workload == "c5":
         return adjoint_bench(args)
+    if args.workload == "c6":
+        return pform_bench(args)
     n, box, z, nmax, nbins, desc = WORKLOADS[args.workload]
     dtype = g.F64 if args.dtype == "f64" else g.F32
     cut = g.cut_n2max(n, box)

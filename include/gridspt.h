@@ -157,6 +157,24 @@ int gridspt_orders(gridspt_ctx* ctx, const gridspt_grid* g, int32_t nmax, int64_
                    const void* delta1, void* const* delta, void* const* theta, void* const* delta_k,
                    void* const* theta_k, void* work, int64_t work_bytes);
 
+/* Device scratch of gridspt_orders_pform: the transform buffers, 15 real
+ * fields per order below nmax, two real fields and two spectra. */
+int64_t gridspt_pform_workspace_bytes(const gridspt_grid* g, int32_t nmax);
+
+/* The recursion with the sources exactly as printed in Eq. 10 (the P-form):
+ * S_delta = sum_m (grad delta_m).u_{n-m} + delta_m theta_{n-m},
+ * S_theta = sum_m [d_j u_{m,k}][d_k u_{n-m,j}] + u_m.grad theta_{n-m},
+ * built pointwise from the derived fields of Eq. 15/16 of every earlier
+ * order (steps 2 and 5 of Sec. II C), then transformed and combined as in
+ * gridspt_orders.  Same arguments and layouts as gridspt_orders (for n >= 2
+ * delta_k[n-1] and theta_k[n-1] must differ).  It equals gridspt_orders
+ * mode by mode when no product aliases (both masks inside the 2/3 rule) and
+ * differs by the aliased terms otherwise (e.g. the paper's cuts of 1 and
+ * 4/3 h/Mpc on 512^3 with L = 1000 Mpc/h). */
+int gridspt_orders_pform(gridspt_ctx* ctx, const gridspt_grid* g, int32_t nmax, int64_t n2max1, int64_t n2max2,
+                         const void* delta1, void* const* delta, void* const* theta, void* const* delta_k,
+                         void* const* theta_k, void* work, int64_t work_bytes);
+
 /* Final sum of orders (the truncated series of Eq. 8):
  * out(x) = sum_{n=1..nmax} coef[n-1] delta_n(x), accumulated in FP64.
  * delta: host array of nmax device pointers; coef: host array of nmax;

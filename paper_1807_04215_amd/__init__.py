@@ -99,6 +99,8 @@ def lib():
             "gridspt_batch_destroy": ([vp], None),
             "gridspt_batch_buffer": ([vp, i32, i32, i32, i32, ctypes.POINTER(vp)], ctypes.c_int),
             "gridspt_batch_tuning": ([vp, i32, i32, vp, vp, vp], ctypes.c_int),
+            "gridspt_pform_workspace_bytes": ([gp, i32], i64),
+            "gridspt_orders_pform": ([vp, gp, i32, i64, i64, vp, vp, vp, vp, vp, vp, i64], ctypes.c_int),
             "gridspt_noise_field": ([vp, gp, ctypes.POINTER(_LinPk), vp, vp, vp, vp, i64], ctypes.c_int),
             "gridspt_adjoint_workspace_bytes": ([gp, i32], i64),
             "gridspt_adjoint": ([vp, gp, ctypes.POINTER(_LinPk), i32, i64, vp, vp, vp, vp, vp, i64], ctypes.c_int),
@@ -387,6 +389,22 @@ def orders(ctx: Context, grid: Grid, nmax: int, n2max1: int, n2max2: int, delta1
     tk = _ptr_array(out.theta_k) if out.theta_k is not None else None
     _check(lib().gridspt_orders(ctx.handle, ctypes.byref(g), nmax, n2max1, n2max2, _ptr(delta1), d, t, dk, tk,
                                 _ptr(ws), ws.numel()), "orders")
+    return out
+
+
+def orders_pform(ctx: Context, grid: Grid, nmax: int, n2max1: int, n2max2: int, delta1: torch.Tensor,
+                 out: Optional[Orders] = None, spectra: bool = True) -> Orders:
+    """The recursion with the printed (P-form) sources of Eq. 10; outputs as orders()."""
+    out = out if out is not None else alloc_orders(grid, nmax, spectra)
+    g = grid.cstruct
+    need = _check(lib().gridspt_pform_workspace_bytes(ctypes.byref(g), nmax), "pform_workspace_bytes")
+    ws = ctx.workspace(need)
+    d = _ptr_array(out.delta)
+    t = _ptr_array(out.theta)
+    dk = _ptr_array(out.delta_k) if out.delta_k is not None else None
+    tk = _ptr_array(out.theta_k) if out.theta_k is not None else None
+    _check(lib().gridspt_orders_pform(ctx.handle, ctypes.byref(g), nmax, n2max1, n2max2, _ptr(delta1), d, t, dk, tk,
+                                      _ptr(ws), ws.numel()), "orders_pform")
     return out
 
 

@@ -355,6 +355,44 @@ __global__ __launch_bounds__(256) void k_adj_products(AdjProducts<T> a, int firs
     }
 }
 
+// The printed sources of Eq. 10 for order NORD from the derived fields of the
+// earlier orders (17 per order: delta, theta, grad delta (3), grad theta (3),
+// u (3), d_i u_j (6: xx, yy, zz, xy, xz, yz)):
+//   S_delta = sum_m (grad delta_m) . u_{n-m} + delta_m theta_{n-m}
+//   S_theta = sum_m [d_j u_{m,k}][d_k u_{n-m,j}] + u_m . grad theta_{n-m}
+template <typename T>
+struct PFormProducts {
+    const T* f[4][17];  // orders 1 .. n-1: delta, theta, gd x3, gt x3, u x3, du x6
+    T* sd;
+    T* st;
+    size_t ncell;
+};
+
+template <typename T, int NORD>
+__global__ __launch_bounds__(256) void k_pform_products(PFormProducts<T> a) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell; c += stride) {
+        T v[NORD][17];
+#pragma unroll
+        for (int m = 1; m < NORD; ++m)
+#pragma unroll
+            for (int q = 0; q < 17; ++q) v[m][q] = a.f[m - 1][q][c];
+        T sdel = 0, sthe = 0;
+#pragma unroll
+        for (int m = 1; m < NORD; ++m) {
+            const T* A = v[m];
+            const T* B = v[NORD - m];
+            sdel += A[2] * B[8] + A[3] * B[9] + A[4] * B[10] + A[0] * B[1];
+            // symmetric d_i u_j: diagonal once, off-diagonal twice
+            sthe += A[11] * B[11] + A[12] * B[12] + A[13] * B[13] +
+                    (T)2 * (A[14] * B[14] + A[15] * B[15] + A[16] * B[16]);
+            sthe += A[8] * B[5] + A[9] * B[6] + A[10] * B[7];
+        }
+        a.sd[c] = sdel;
+        a.st[c] = sthe;
+    }
+}
+
 // Mean and sample standard deviation over nreal realisations of `count`
 // doubles at byte stride zs: a fixed-order two-pass sum per item.
 static __global__ void k_batch_stats(const double* x, int nreal, int count, size_t zs, double* mean, double* sdev) {

@@ -586,6 +586,43 @@ int gridspt_orders(gridspt_ctx* c, const gridspt_grid* g, int32_t nmax, int64_t 
     });
 }
 
+int64_t gridspt_pform_workspace_bytes(const gridspt_grid* g, int32_t nmax) {
+    const int rc = check_grid(g);
+    if (rc != GRIDSPT_OK) return rc;
+    if (nmax < 1 || nmax > 5) return GRIDSPT_EINVAL;
+    return pform_layout(dims_of(g), nmax).end;
+}
+
+int gridspt_orders_pform(gridspt_ctx* c, const gridspt_grid* g, int32_t nmax, int64_t n2max1, int64_t n2max2,
+                         const void* delta1, void* const* delta, void* const* theta, void* const* delta_k,
+                         void* const* theta_k, void* work, int64_t work_bytes) {
+    if (!c) return GRIDSPT_EINVAL;
+    CHECK(check_grid(g));
+    if (nmax < 1 || nmax > 5) return GRIDSPT_EINVAL;
+    CHECK(check_mask(g, n2max1));
+    if (nmax > 1) CHECK(check_mask(g, n2max2));
+    CHECK(check_ptr(delta1));
+    if (!delta || !theta) return GRIDSPT_EINVAL;
+    for (int i = 0; i < nmax; ++i) {
+        CHECK(check_ptr(delta[i]));
+        if (i > 0) CHECK(check_ptr(theta[i]));
+        else if (theta[0]) CHECK(check_ptr(theta[0]));
+        if (delta_k && delta_k[i]) CHECK(check_ptr(delta_k[i]));
+        if (theta_k && theta_k[i]) CHECK(check_ptr(theta_k[i]));
+        if (i > 0 && delta_k && theta_k && delta_k[i] && delta_k[i] == theta_k[i]) return GRIDSPT_EINVAL;
+    }
+    if (!work) return GRIDSPT_EWORKSPACE;
+    CHECK(check_ptr(work));
+    if (work_bytes < gridspt_pform_workspace_bytes(g, nmax)) return GRIDSPT_EWORKSPACE;
+    const Tuning tu{};
+    return dispatch(g, [&](auto tag, auto nc) -> int {
+        using T = typename decltype(tag)::type;
+        constexpr int N = decltype(nc)::value;
+        return run_orders_pform<T, N>(c, g, nmax, n2max1, n2max2, delta1, delta, theta, delta_k, theta_k, work, tu,
+                                      Batch{});
+    });
+}
+
 int gridspt_sum_orders(gridspt_ctx* c, const gridspt_grid* g, int32_t nmax, const void* const* delta,
                        const double* coef, double* out) {
     if (!c || !delta || !coef) return GRIDSPT_EINVAL;

@@ -181,6 +181,8 @@ __device__ __forceinline__ cpx<T> unpack_real_pair(cpx<T> c, cpx<T> m, int which
 //   packed as V_x + i V_y and V_z + i W; a block covers RPB consecutive y.
 // SRC 3: four real fields pin.d[0..3] (the reverse mode's g delta, g u),
 //   packed as d0 + i d1 and d2 + i d3; a block covers RPB consecutive y.
+// SRC 4: two real fields pin.d[0..1] (the printed sources S_delta, S_theta),
+//   packed as d0 + i d1; a block covers RPB consecutive y.
 // --------------------------------------------------------------------------
 template <typename T>
 struct ProductInputs {
@@ -218,7 +220,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __re
     using RW = Rows<T, N, V>;
     using PL = typename RW::PL;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
-    constexpr bool PACK4 = SRC == 2 || SRC == 3;       // four real fields per row
+    constexpr bool PACK4 = SRC == 2 || SRC == 3 || SRC == 4;  // field pairs packed per row
     constexpr int YB = PACK4 ? RPB : 2 * RPB;  // rows of y per block
     __shared__ cpx<T> lds[RPB * ROWE];
     // twiddles in LDS for FP32 (this pass's LDS traffic is light), else from the cache
@@ -229,9 +231,9 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __re
     const Twiddles<T, PL, LT> tws{LT ? twl : tw};
     f = zptr(f, zs);
     s1 = zptr(s1, zs);
-    if constexpr (SRC == 3) {
+    if constexpr (SRC == 3 || SRC == 4) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) pin.d[m] = zptr(pin.d[m], zs);
+        for (int m = 0; m < (SRC == 3 ? 4 : 2); ++m) pin.d[m] = zptr(pin.d[m], zs);
     }
     if constexpr (SRC == 2) {
 #pragma unroll
@@ -276,12 +278,12 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __re
             const uint32_t o = (uint32_t)(r * N + l + P * e);
             a[e] = {ldo(f0, o), ldo(f0, o + (uint32_t)(RPB * N))};
         }
-    } else if constexpr (SRC == 3) {
+    } else if constexpr (SRC == 3 || SRC == 4) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const uint32_t o = (uint32_t)(r * N + l + P * e);
             a[e] = {ldo(pin.d[0] + blockbase, o), ldo(pin.d[1] + blockbase, o)};
-            b[e] = {ldo(pin.d[2] + blockbase, o), ldo(pin.d[3] + blockbase, o)};
+            if constexpr (SRC == 3) b[e] = {ldo(pin.d[2] + blockbase, o), ldo(pin.d[3] + blockbase, o)};
         }
     } else {
         // the packed products are formed here, not after the first transform,
@@ -294,7 +296,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __re
         }
     }
 
-    constexpr int NPACK = PACK4 ? 2 : 1;
+    constexpr int NPACK = (SRC == 2 || SRC == 3) ? 2 : 1;
     static_for<NPACK>([&](auto pkc) {
         constexpr int pk = decltype(pkc)::value;
         cpx<T> v[E];
@@ -364,7 +366,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yfwd(const cpx<T>*
 // kz.  Forward x transform, the k-space step, optional cube stores, then the
 // inverse x transform of every output field, written transposed to S3.
 // --------------------------------------------------------------------------
-enum XMode { XM_ORDER = 0, XM_ORDER1 = 1, XM_LINEAR = 2, XM_FORWARD = 3, XM_ADJ = 4, XM_ADJ1 = 5 };
+enum XMode { XM_ORDER = 0, XM_ORDER1 = 1, XM_LINEAR = 2, XM_FORWARD = 3, XM_ADJ = 4, XM_ADJ1 = 5, XM_PFORM = 6 };
 
 template <typename T>
 struct XArgs {
@@ -430,7 +432,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
     // k-space step: sd holds delta_n(k), st holds theta_n(k) afterwards
     cpx<T> sd[E], st[E];
     constexpr bool ADJ = MODE == XM_ADJ || MODE == XM_ADJ1;
-    constexpr int NIN = (MODE == XM_ORDER || ADJ) ? 4 : 1;
+    constexpr int NIN = (MODE == XM_ORDER || ADJ) ? 4 : (MODE == XM_PFORM ? 2 : 1);
 #pragma unroll
     for (int e = 0; e < E; ++e) sd[e] = st[e] = {(T)0, (T)0};
     static_for<NIN>([&](auto fc) {
@@ -456,6 +458,15 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
             }
 #pragma unroll
             for (int e = 0; e < E; ++e) {
+                keep_here(sd[e]);
+                keep_here(st[e]);
+            }
+        } else if constexpr (MODE == XM_PFORM) {
+            // the printed sources of Eq. 10, transformed as they are
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                if constexpr (f == 0) sd[e] = v[e];
+                else st[e] = v[e];
                 keep_here(sd[e]);
                 keep_here(st[e]);
             }
@@ -491,10 +502,12 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
         const int kx = signed_pos(l + P * e, N);
         const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
         const bool keep = active && n2 > 0 && n2 <= a.n2max;
-        if constexpr (MODE == XM_ORDER) {
-            // S_delta = i k.V(k) N^-3, S_theta = -(k^2/2) W(k) N^-3 (divergence form of Eq. 10)
-            const cpx<T> sdel = cscale(sd[e], kF * invN3);
-            const cpx<T> sthe = cscale(st[e], (T)(-0.5) * kF * kF * (T)n2 * invN3);
+        if constexpr (MODE == XM_ORDER || MODE == XM_PFORM) {
+            // D-form: S_delta = i k.V(k) N^-3, S_theta = -(k^2/2) W(k) N^-3 (divergence form of
+            // Eq. 10); P-form: the transforms of the printed sources, times N^-3
+            const cpx<T> sdel = MODE == XM_ORDER ? cscale(sd[e], kF * invN3) : cscale(sd[e], invN3);
+            const cpx<T> sthe =
+                MODE == XM_ORDER ? cscale(st[e], (T)(-0.5) * kF * kF * (T)n2 * invN3) : cscale(st[e], invN3);
             const T cn = (T)(2.0 / ((2.0 * a.n + 3.0) * (a.n - 1.0)));
             const T m00 = cn * (T)(a.n + 0.5), m01 = cn, m10 = cn * (T)1.5, m11 = cn * (T)a.n;
             const cpx<T> dn = {m00 * sdel.x + m01 * sthe.x, m00 * sdel.y + m01 * sthe.y};
@@ -524,7 +537,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
         }
     }
     // theta_1 = delta_1 below order 2
-    if constexpr (MODE != XM_ORDER && !ADJ) {
+    if constexpr (MODE != XM_ORDER && MODE != XM_PFORM && !ADJ) {
 #pragma unroll
         for (int e = 0; e < E; ++e) st[e] = sd[e];
     }
@@ -544,8 +557,10 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
     if constexpr (MODE != XM_FORWARD) {
         // outputs.  ORDER: delta, theta, u_x, u_y, u_z;  ORDER1: delta, u_x, u_y, u_z;  LINEAR: delta;
         // ADJ: g V_x, g V_y, g V_z, g W;  ADJ1: g w
-        constexpr int NOUT_MAX = (MODE == XM_ORDER) ? 5 : ((MODE == XM_ORDER1 || MODE == XM_ADJ) ? 4 : 1);
-        constexpr int FIRST_U = (MODE == XM_ORDER) ? 2 : 1;
+        // PFORM: delta, theta
+        constexpr int NOUT_MAX =
+            (MODE == XM_ORDER) ? 5 : ((MODE == XM_ORDER1 || MODE == XM_ADJ) ? 4 : (MODE == XM_PFORM ? 2 : 1));
+        constexpr int FIRST_U = (MODE == XM_ORDER || MODE == XM_PFORM) ? 2 : 1;
         const size_t outbase = (size_t)kz * N * cd.Ky + ky0;
         static_for<NOUT_MAX>([&](auto oc) {
             constexpr int o = decltype(oc)::value;
@@ -697,6 +712,70 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xregen(RegenArgs<T
                     const T sc = n2 > 0 ? (T)((double)kj / (a.kF * (double)n2)) : (T)0;
                     const cpx<T> t = ctl[cbase + ic];
                     c = {t.y * sc, -t.x * sc};
+                }
+            }
+            v[e] = c;
+        }
+        x_inverse_store<T, N, V>(v, lds, row, tws, l, s3 + (size_t)o * a.s3_field + outbase, cd.Ky, nrows);
+    });
+}
+
+// --------------------------------------------------------------------------
+// P3 for the printed (P-form) sources: the derived real fields of one order
+// (Eq. 15, 16) from its stored spectra, five per launch (chunk 0, 1, 2):
+//   0-2  grad delta = F^-1[i k delta],      3-5  grad theta = F^-1[i k theta],
+//   6-8  u = F^-1[(-i k / k^2) theta],       9-14 d_i u_j = F^-1[(k_i k_j / k^2) theta]
+//        for (i, j) = (x,x), (y,y), (z,z), (x,y), (x,z), (y,z) (symmetric: u is a gradient)
+// written transposed to S3 fields 0..4.
+// --------------------------------------------------------------------------
+template <typename T, int N, int V, int CHUNK>
+__global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xderived(RegenArgs<T> a, const cpx<T>* __restrict__ tw,
+                                                                        CubeDims cd, size_t zs) {
+    using RW = Rows<T, N, V>;
+    using PL = typename RW::PL;
+    constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
+    __shared__ cpx<T> lds[RPB * ROWE];
+    const Twiddles<T, PL, false> tws{tw};
+    const uint32_t groups = (cd.Ky + RPB - 1) / RPB;
+    const uint32_t blk = xcd_block(blockIdx.x, cd.Kz * groups);
+    const int kz = blk / groups, ky0 = (blk % groups) * RPB;
+    const int r = threadIdx.x / P, l = threadIdx.x % P;
+    const int kyc = ky0 + r;
+    const bool active = kyc < cd.Ky;
+    const int ky = active ? (kyc <= cd.Kc ? kyc : kyc - cd.Ky) : 0;
+    const int nrows = min(RPB, cd.Ky - ky0);
+    const size_t cbase = ((size_t)kz * cd.Ky + kyc) * cd.Ky;
+    const cpx<T>* cdl = zptr(a.cube_d, zs);
+    const cpx<T>* ctl = zptr(a.cube_t, zs);
+    cpx<T>* s3 = zptr(a.s3, zs);
+    cpx<T>* row = lds + r * ROWE;
+    const size_t outbase = (size_t)kz * N * cd.Ky + ky0;
+    static_for<5>([&](auto oc) {
+        constexpr int o = decltype(oc)::value;
+        constexpr int fld = 5 * CHUNK + o;
+        cpx<T> v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = l + P * e;
+            const int ic = pos_to_compact(p, cd.Kc, N);
+            cpx<T> c = {(T)0, (T)0};
+            if (active && ic >= 0) {
+                const int kx = signed_pos(p, N);
+                auto kc = [&](int axis) { return axis == 0 ? kx : (axis == 1 ? ky : kz); };
+                const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
+                const cpx<T> src = fld < 3 ? cdl[cbase + ic] : ctl[cbase + ic];
+                if constexpr (fld < 6) {  // i k_j F
+                    const T kj = (T)(a.kF * (double)kc(fld % 3));
+                    c = {-src.y * kj, src.x * kj};
+                } else if constexpr (fld < 9) {  // (-i k_j / k^2) F
+                    const T sc = n2 > 0 ? (T)((double)kc(fld - 6) / (a.kF * (double)n2)) : (T)0;
+                    c = {src.y * sc, -src.x * sc};
+                } else {  // (k_i k_j / k^2) F
+                    constexpr int q = fld - 9;
+                    constexpr int i = q < 3 ? q : (q < 5 ? 0 : 1);
+                    constexpr int j = q < 3 ? q : (q == 3 ? 1 : 2);
+                    const T sc = n2 > 0 ? (T)((double)kc(i) * (double)kc(j) / (double)n2) : (T)0;
+                    c = cscale(src, sc);
                 }
             }
             v[e] = c;

@@ -92,6 +92,39 @@ struct Pipe {
         });
     }
 
+    // P1 of two real fields packed as one complex transform -> S1 fields 0, 1 in A
+    int zfwd_pair(const T* f0, const T* f1) {
+        return with_variant<T, N>(tu.v[KD_ZFWD_PAIR], [&](auto vc) {
+            constexpr int V = decltype(vc)::value;
+            using RW = Rows<T, N, V>;
+            ProductInputs<T> pin{};
+            pin.d[0] = f0;
+            pin.d[1] = f1;
+            const double bytes = nb() * (2.0 * d.ncell() * d.real_bytes + 2.0 * d.s1() * d.cpx_bytes);
+            return launch(c, KD_ZFWD_PAIR, bytes, dim3(N * (N / RW::RPB), 1, nz()), dim3(RW::THREADS), 0,
+                          k_zfwd<T, N, V, 4, 0>, (const T*)nullptr, pin, (uint64_t)0, (uint64_t)0, A(),
+                          (size_t)L.a_field_s1, (const cpx<T>*)tw(), (int)d.Kz, bt.zs);
+        });
+    }
+
+    // P3 of the P-form derived fields of one order, chunk 0..2 (five fields) -> S3 (A)
+    int xderived(RegenArgs<T> r, int chunk) {
+        r.s3 = A();
+        r.s3_field = (size_t)L.a_field_s3;
+        return with_variant<T, N>(tu.v[KD_XDERIVED], [&](auto vc) {
+            constexpr int V = decltype(vc)::value;
+            using RW = Rows<T, N, V>;
+            const double bytes = nb() * ((chunk == 0 ? 2.0 : 1.0) * d.cube() + 5.0 * d.s3()) * d.cpx_bytes;
+            const dim3 grid((unsigned)(d.Kz * ((d.Ky + RW::RPB - 1) / RW::RPB)), 1, nz()), block(RW::THREADS);
+            const cpx<T>* t = tw();
+            switch (chunk) {
+                case 0: return launch(c, KD_XDERIVED, bytes, grid, block, 0, k_xderived<T, N, V, 0>, r, t, cd, bt.zs);
+                case 1: return launch(c, KD_XDERIVED, bytes, grid, block, 0, k_xderived<T, N, V, 1>, r, t, cd, bt.zs);
+                default: return launch(c, KD_XDERIVED, bytes, grid, block, 0, k_xderived<T, N, V, 2>, r, t, cd, bt.zs);
+            }
+        });
+    }
+
     // P3 from stored spectra: delta_m, u_m (4 fields) -> S3 (A)
     int xregen(RegenArgs<T> r) {
         r.s3 = A();
@@ -149,11 +182,12 @@ struct Pipe {
                          : mode == XM_LINEAR ? KD_XFUSED_LINEAR
                          : mode == XM_ADJ    ? KD_XFUSED_ADJ
                          : mode == XM_ADJ1   ? KD_XFUSED_ADJ1
+                         : mode == XM_PFORM  ? KD_XFUSED_PFORM
                                              : KD_XFUSED_FORWARD;
         return with_variant<T, N>(tu.v[kind], [&](auto vc) {
             constexpr int V = decltype(vc)::value;
             using RW = Rows<T, N, V>;
-            const int nin = mode == XM_ORDER ? 4 : ((mode == XM_ADJ || mode == XM_ADJ1) ? a.nin : 1);
+            const int nin = mode == XM_ORDER ? 4 : ((mode == XM_ADJ || mode == XM_ADJ1) ? a.nin : (mode == XM_PFORM ? 2 : 1));
             const int ncube = (a.cube_d ? 1 : 0) + (a.cube_t ? 1 : 0);
             const double bytes =
                 nb() * ((double)nin * d.s2() + (double)a.nout * d.s3() + (double)ncube * d.cube()) * d.cpx_bytes;
@@ -166,6 +200,8 @@ struct Pipe {
                 case XM_LINEAR:
                     return launch(c, kind, bytes, grid, block, 0, k_xfused<T, N, V, XM_LINEAR>, a, t, cd, bt.zs);
                 case XM_ADJ: return launch(c, kind, bytes, grid, block, 0, k_xfused<T, N, V, XM_ADJ>, a, t, cd, bt.zs);
+                case XM_PFORM:
+                    return launch(c, kind, bytes, grid, block, 0, k_xfused<T, N, V, XM_PFORM>, a, t, cd, bt.zs);
                 case XM_ADJ1:
                     return launch(c, kind, bytes, grid, block, 0, k_xfused<T, N, V, XM_ADJ1>, a, t, cd, bt.zs);
                 default:
@@ -345,6 +381,96 @@ int run_shells(gridspt_ctx* c, const gridspt_grid* g, int nslots, const void* co
     return GRIDSPT_OK;
 }
 
+// Orders 1..nmax with the printed sources of Eq. 10 (the P-form): after each
+// order the 15 derived fields of Eq. 15/16 are made from its spectra; the
+// sources of order n are formed pointwise from the 17 fields of every earlier
+// order, transformed two per complex transform, and combined with the matrix
+// of Eq. 10 in the fused x pass.
+template <typename T, int N>
+int run_orders_pform(gridspt_ctx* c, const gridspt_grid* g, int nmax, int64_t n2max1, int64_t n2max2,
+                     const void* delta1, void* const* delta, void* const* theta, void* const* delta_k,
+                     void* const* theta_k, void* work, const Tuning& tu, Batch b) {
+    Pipe<T, N> p(c, g, work, 1, tu, b);
+    const PFormLayout pl = pform_layout(p.d, nmax);
+    char* wb = static_cast<char*>(work);
+    T* base = reinterpret_cast<T*>(wb + pl.fields);
+    const size_t nc = (size_t)p.d.ncell();
+    auto derived = [&](int m, int q) { return base + ((size_t)(m - 1) * 15 + q) * nc; };  // q = 0..14
+    T* sdel = base + (size_t)(nmax - 1) * 15 * nc;
+    T* sthe = sdel + nc;
+    cpx<T>* wcube_d = reinterpret_cast<cpx<T>*>(wb + pl.cubes);
+    cpx<T>* wcube_t = wcube_d + p.d.cube();
+    auto dk = [&](int i) { return (delta_k && delta_k[i]) ? (cpx<T>*)delta_k[i] : wcube_d; };
+    auto tk = [&](int i) {
+        const bool own = theta_k && theta_k[i] && !(delta_k && theta_k[i] == delta_k[i]);
+        return own ? (cpx<T>*)theta_k[i] : wcube_t;
+    };
+    const double kF = 2.0 * M_PI / g->box;
+    GRIDSPT_CHECK(p.twiddles());
+    // the derived fields of order m from its spectra
+    auto make_derived = [&](int m, const cpx<T>* cd_, const cpx<T>* ct_) -> int {
+        RegenArgs<T> r{};
+        r.cube_d = cd_;
+        r.cube_t = ct_;
+        r.kF = kF;
+        for (int ch = 0; ch < 3; ++ch) {
+            GRIDSPT_CHECK(p.xderived(r, ch));
+            T* out[5];
+            for (int i = 0; i < 5; ++i) out[i] = derived(m, 5 * ch + i);
+            GRIDSPT_CHECK(p.to_real(5, out));
+        }
+        return GRIDSPT_OK;
+    };
+    // order 1: delta_1 = theta_1 = W1 F[delta1_in]
+    GRIDSPT_CHECK(p.zfwd_single(static_cast<const T*>(delta1), false, 0, 0));
+    GRIDSPT_CHECK(p.yfwd(1));
+    {
+        cpx<T>* c1 = dk(0);
+        XArgs<T> a = make_xargs<T>(p.d, g, 1, 1, n2max1, c1, nullptr);
+        GRIDSPT_CHECK(p.xfused(XM_ORDER1, a));
+        T* out[1] = {static_cast<T*>(delta[0])};
+        GRIDSPT_CHECK(p.to_real(1, out));
+        if (theta[0] && theta[0] != delta[0])
+            GRIDSPT_CHECK(p.copy(static_cast<const T*>(delta[0]), static_cast<T*>(theta[0])));
+        if (theta_k && theta_k[0] && theta_k[0] != (void*)c1)
+            GRIDSPT_CHECK(launch(c, KD_COPY, 4.0 * p.d.cube() * p.d.real_bytes, dim3(512), dim3(256), 0, k_copy<T>,
+                                 (const T*)c1, (T*)theta_k[0], (size_t)(2 * p.d.cube()), (size_t)0));
+        if (nmax > 1) GRIDSPT_CHECK(make_derived(1, c1, c1));
+    }
+    for (int n = 2; n <= nmax; ++n) {
+        PFormProducts<T> pp{};
+        for (int m = 1; m < n; ++m) {
+            pp.f[m - 1][0] = static_cast<const T*>(delta[m - 1]);
+            pp.f[m - 1][1] = static_cast<const T*>(m == 1 ? delta[0] : theta[m - 1]);
+            for (int q = 0; q < 15; ++q) pp.f[m - 1][2 + q] = derived(m, q);
+        }
+        pp.sd = sdel;
+        pp.st = sthe;
+        pp.ncell = nc;
+        const double bytes = (double)nc * p.d.real_bytes * (17.0 * (n - 1) + 2.0);
+        auto go = [&](auto kern) {
+            return launch(c, KD_PFORM_PRODUCTS, bytes, dim3(4096), dim3(256), 0, kern, pp);
+        };
+        switch (n) {
+            case 2: GRIDSPT_CHECK(go(k_pform_products<T, 2>)); break;
+            case 3: GRIDSPT_CHECK(go(k_pform_products<T, 3>)); break;
+            case 4: GRIDSPT_CHECK(go(k_pform_products<T, 4>)); break;
+            case 5: GRIDSPT_CHECK(go(k_pform_products<T, 5>)); break;
+            default: return GRIDSPT_EINVAL;
+        }
+        GRIDSPT_CHECK(p.zfwd_pair(sdel, sthe));
+        GRIDSPT_CHECK(p.yfwd(2));
+        cpx<T>* cdn = dk(n - 1);
+        cpx<T>* ctn = tk(n - 1);
+        XArgs<T> a = make_xargs<T>(p.d, g, n, 2, n2max2, cdn, ctn);
+        GRIDSPT_CHECK(p.xfused(XM_PFORM, a));
+        T* out[2] = {static_cast<T*>(delta[n - 1]), static_cast<T*>(theta[n - 1])};
+        GRIDSPT_CHECK(p.to_real(2, out));
+        if (n < nmax) GRIDSPT_CHECK(make_derived(n, cdn, ctn));
+    }
+    return GRIDSPT_OK;
+}
+
 // Reverse mode of noise -> delta_1 .. delta_nmax (linear field from given
 // noise, then the D-form orders), for an objective of the delta_n only:
 // regenerate delta_m, u_m (m < nmax) from the stored spectra, then run the
@@ -435,6 +561,9 @@ int run_adjoint(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, 
     template int gridspt::run_linear_field<T, N>(gridspt_ctx*, const gridspt_grid*, const gridspt_linpk*,         \
                                                  const void*, void*, void*, void*, const gridspt::Tuning&,         \
                                                  gridspt::Batch);                                                  \
+    template int gridspt::run_orders_pform<T, N>(gridspt_ctx*, const gridspt_grid*, int, int64_t, int64_t,       \
+                                                 const void*, void* const*, void* const*, void* const*,            \
+                                                 void* const*, void*, const gridspt::Tuning&, gridspt::Batch);     \
     template int gridspt::run_adjoint<T, N>(gridspt_ctx*, const gridspt_grid*, const gridspt_linpk*, int, int64_t, \
                                             const void* const*, const void* const*, const void* const*, void*,     \
                                             void*, const gridspt::Tuning&, gridspt::Batch);                        \

@@ -46,6 +46,10 @@ enum Kind {
     KD_XFUSED_ADJ,
     KD_XFUSED_ADJ1,
     KD_ADJ_PRODUCTS,
+    KD_PFORM_PRODUCTS,
+    KD_ZFWD_PAIR,
+    KD_XFUSED_PFORM,
+    KD_XDERIVED,
     KD_COUNT
 };
 
@@ -54,7 +58,7 @@ inline const char* const kKindNames[KD_COUNT] = {
     "xfused_order1", "xfused_order",   "xfused_forward", "xshell",      "yinv",        "zinv",
     "power_partial", "power_final",    "triple_partial", "triple_final", "bisp_final", "sum_orders",
     "copy",          "batch_stats",    "zfwd_adjoint", "xregen",        "xfused_adj",  "xfused_adj1",
-    "adj_products"};
+    "adj_products",  "pform_products", "zfwd_pair",    "xfused_pform",  "xderived"};
 
 // Launch variant of each pass kind (see Rows): 0 is the default shape.
 struct Tuning {
@@ -267,6 +271,26 @@ template <typename T, int N>
 int run_adjoint(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, int nmax, int64_t n2max2,
                 const void* const* delta_k, const void* const* theta_k, const void* const* gdelta, void* gnoise,
                 void* work, const Tuning& tu, Batch b);
+
+// the printed (P-form) sources of Eq. 10 instead of the divergence form; same
+// arguments as run_orders, workspace pform_layout
+template <typename T, int N>
+int run_orders_pform(gridspt_ctx* c, const gridspt_grid* g, int nmax, int64_t n2max1, int64_t n2max2,
+                     const void* delta1, void* const* delta, void* const* theta, void* const* delta_k,
+                     void* const* theta_k, void* work, const Tuning& tu, Batch b);
+
+// Workspace of the P-form: the pipeline (no u fields) | 15 derived real fields
+// per order < nmax | S_delta, S_theta | the current order's two spectra.
+struct PFormLayout {
+    int64_t fields, cubes, end;
+};
+inline PFormLayout pform_layout(const Dims& d, int nmax) {
+    PFormLayout a;
+    a.fields = layout_of(d, 1).end;
+    a.cubes = align_up(a.fields + (15 * (int64_t)(nmax - 1) + 2) * d.ncell() * d.real_bytes);
+    a.end = align_up(a.cubes + 2 * d.cube() * d.cpx_bytes);
+    return a;
+}
 
 // Workspace of the reverse mode: the pipeline (no u fields) | delta_m, u_m
 // (m < nmax, regenerated) | their gradient accumulators | g V, g W.
