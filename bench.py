@@ -420,12 +420,86 @@ def pform_bench(args) -> int:
     return 0
 
 
+def stats_bench(args) -> int:
+    """C7: field statistics of the P-form fields of the paper's grid and cuts
+    (512^3, L = 1000 Mpc/h, z = 0, n <= 5): one step = Gaussian smoothing
+    (R = 10 Mpc/h) of the cumulative sums delta_SPT^(n), n = 1..5, from the stored
+    spectra, then mean, variance, skewness, kurtosis and the correlation
+    matrix of the five fields, their PDFs (100 bins on [-1.5, 3.5]) and the
+    joint PDFs of delta_SPT^(5) with each lower truncation (64 x 64)."""
+    import numpy as np
+    import torch
+
+    import paper_1807_04215_amd as g
+
+    n, box, nmax, radius = 512, 1000.0, 5, 10.0
+    cut1 = g.cut_n2max(n, box, 1.0)
+    cut2 = g.cut_n2max(n, box, 4.0 / 3.0)
+    grid = g.Grid(n, box, g.cube_kc(cut2), g.F32)
+    lp = g.LinearSpectrum(amp=g.sigma8_amp(0.8, 0.96, 0.21), ns=0.96, gamma=0.21, growth=1.0, n2max=cut1, seed=6)
+    ctx = g.Context()
+    d1 = g.linear_field(ctx, grid, lp)
+    out = g.orders_pform(ctx, grid, nmax, cut1, cut2, d1)
+    del d1
+    sm = [torch.empty((n,) * 3, device="cuda") for _ in range(nmax)]
+    coef = [1.0] * nmax
+
+    def step():
+        g.smooth(ctx, grid, out.delta_k, coef, radius, out=sm)
+        return g.field_stats(ctx, grid, [sm[-1]] + sm[:-1], nbins=100, lo=-1.5, hi=3.5, nbins2=64)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        mom, cor, cnt, jnt = step()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1000.0 / args.steps
+    ctx.set_profiling(False)
+    prof = ctx.profile_read()
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    dd = prof[dom]
+    achieved = dd["bytes"] / (dd["ms"] / 1000.0) / 1e9
+    kern_ms = sum(v["ms"] for v in prof.values())
+    if args.kernels:
+        for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"]):
+            print("%-16s launches %4d  %9.3f ms/step  %8.1f GB/s" % (
+                k, v["launches"], v["ms"] / args.steps, v["bytes"] / max(v["ms"], 1e-9) / 1e6), file=sys.stderr)
+    m = mom.cpu().numpy()
+    r = cor.cpu().numpy()
+    below = [float((sm[i] < -1.0).double().mean().item()) for i in range(nmax)]
+    res = {
+        "metric": "Mcells/s of smoothing + one-point statistics of five truncated SPT fields",
+        "value": round(n ** 3 / (ms_step / 1000.0) / 1e6, 3), "unit": "Mcells/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded Gaussian linear field, BBKS P0, sigma8=0.8)",
+        "config": {"workload": "c7: 512^3 grid, L=1000 Mpc/h, z=0, P-form orders 1..5 with cuts 1 and 4/3 h/Mpc, "
+                               "Gaussian R=10 Mpc/h, cumulative delta_SPT^(n), PDF 100 bins on [-1.5, 3.5), "
+                               "joint PDF 64 x 64 with delta_SPT^(5)",
+                   "sigma_n": ["%.4f" % np.sqrt(v) for v in np.roll(m[:, 1], -1)],
+                   "skewness_n": ["%.4f" % v for v in np.roll(m[:, 2], -1)],
+                   "r_n_5": ["%.5f" % v for v in np.roll(r[0], -1)],
+                   "fraction_below_minus_1": ["%.2e" % v for v in below]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "launch_ms": round(dd["ms"] / dd["launches"], 3),
+                     "algorithmic_gb_per_launch": round(dd["bytes"] / dd["launches"] / 1e9, 3)},
+        "kernel_ms_per_step": round(kern_ms / args.steps, 3),
+        "path_gbs": round(sum(v["bytes"] for v in prof.values()) / (kern_ms / 1000.0) / 1e9, 1),
+    }
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS) + ["c4", "c5", "c6"])
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS) + ["c4", "c5", "c6", "c7"])
     ap.add_argument("--no-tune", action="store_true", help="c4: skip the autotuner")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -464,6 +538,8 @@ def main() -> int:
         return adjoint_bench(args)
     if args.workload == "c6":
         return pform_bench(args)
+    if args.workload == "c7":
+        return stats_bench(args)
     n, box, z, nmax, nbins, desc = WORKLOADS[args.workload]
     dtype = g.F64 if args.dtype == "f64" else g.F32
     cut = g.cut_n2max(n, box)

@@ -175,6 +175,32 @@ int gridspt_orders_pform(gridspt_ctx* ctx, const gridspt_grid* g, int32_t nmax, 
                          const void* delta1, void* const* delta, void* const* theta, void* const* delta_k,
                          void* const* theta_k, void* work, int64_t work_bytes);
 
+/* Gaussian smoothing (Sec. III A-B) of cube-layout spectra into real fields:
+ * out[j](x) = F^-1[exp(-k^2 R^2 / 2) S_j(k)], S_j = sum_{i <= j} coef[i] F_i
+ * (cumulative != 0: the truncated series of Eq. 8, e.g. coef[i] = D^(i+1)) or
+ * S_j = coef[j] F_j.  fields_k, out: host arrays of nfields <= 5 device
+ * pointers; coef: host; radius R in Mpc/h (0: no smoothing).  Workspace as
+ * gridspt_workspace_bytes(g, 1). */
+int gridspt_smooth(gridspt_ctx* ctx, const gridspt_grid* g, int32_t nfields, const void* const* fields_k,
+                   const double* coef, int32_t cumulative, double radius, void* const* out, void* work,
+                   int64_t work_bytes);
+
+/* Device scratch of gridspt_field_stats. */
+int64_t gridspt_stats_workspace_bytes(int32_t nfields, int32_t nbins, int32_t nbins2);
+
+/* One-point statistics of nfields <= 8 real fields of grid g (Sec. III B):
+ *   moments  [nfields][4]: mean, variance (1/N^3), skewness, excess kurtosis;
+ *   corr     [nfields][nfields]: Pearson correlation coefficients;
+ *   counts   [nfields][nbins]: histogram, bin b = floor((x - lo) nbins / (hi - lo))
+ *            evaluated in FP64, values with b outside [0, nbins) dropped (nbins <= 1024);
+ *   joint    [nfields - 1][nbins2][nbins2]: joint histogram of field 0 (first index)
+ *            and field j + 1 on the same range with nbins2 <= 64 bins per axis.
+ * Each output pointer (device) may be NULL to skip it.  Sums are FP64 in a fixed
+ * order; counts are exact integers (as doubles). */
+int gridspt_field_stats(gridspt_ctx* ctx, const gridspt_grid* g, int32_t nfields, const void* const* fields,
+                        int32_t nbins, double lo, double hi, int32_t nbins2, double* moments, double* corr,
+                        double* counts, double* joint, void* work, int64_t work_bytes);
+
 /* Final sum of orders (the truncated series of Eq. 8):
  * out(x) = sum_{n=1..nmax} coef[n-1] delta_n(x), accumulated in FP64.
  * delta: host array of nmax device pointers; coef: host array of nmax;

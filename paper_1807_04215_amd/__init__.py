@@ -101,6 +101,9 @@ def lib():
             "gridspt_batch_tuning": ([vp, i32, i32, vp, vp, vp], ctypes.c_int),
             "gridspt_pform_workspace_bytes": ([gp, i32], i64),
             "gridspt_orders_pform": ([vp, gp, i32, i64, i64, vp, vp, vp, vp, vp, vp, i64], ctypes.c_int),
+            "gridspt_smooth": ([vp, gp, i32, vp, vp, i32, dbl, vp, vp, i64], ctypes.c_int),
+            "gridspt_stats_workspace_bytes": ([i32, i32, i32], i64),
+            "gridspt_field_stats": ([vp, gp, i32, vp, i32, dbl, dbl, i32, vp, vp, vp, vp, vp, i64], ctypes.c_int),
             "gridspt_noise_field": ([vp, gp, ctypes.POINTER(_LinPk), vp, vp, vp, vp, i64], ctypes.c_int),
             "gridspt_adjoint_workspace_bytes": ([gp, i32], i64),
             "gridspt_adjoint": ([vp, gp, ctypes.POINTER(_LinPk), i32, i64, vp, vp, vp, vp, vp, i64], ctypes.c_int),
@@ -406,6 +409,40 @@ def orders_pform(ctx: Context, grid: Grid, nmax: int, n2max1: int, n2max2: int, 
     _check(lib().gridspt_orders_pform(ctx.handle, ctypes.byref(g), nmax, n2max1, n2max2, _ptr(delta1), d, t, dk, tk,
                                       _ptr(ws), ws.numel()), "orders_pform")
     return out
+
+
+def smooth(ctx: Context, grid: Grid, fields_k: Sequence[torch.Tensor], coef: Sequence[float], radius: float,
+           cumulative: bool = True, out: Optional[Sequence[torch.Tensor]] = None):
+    """Gaussian-smoothed real fields of cube spectra: cumulative sums sum_{i<=j} coef_i F_i
+    (the truncated series) or each coef_j F_j; at most five."""
+    import numpy as np
+    out = list(out) if out is not None else [_new_real(grid) for _ in fields_k]
+    c = np.ascontiguousarray(np.asarray(coef, dtype=np.float64))
+    g = grid.cstruct
+    ws = ctx.workspace(workspace_bytes(grid, 1))
+    _check(lib().gridspt_smooth(ctx.handle, ctypes.byref(g), len(fields_k), _ptr_array(fields_k), c.ctypes.data,
+                                1 if cumulative else 0, float(radius), _ptr_array(out), _ptr(ws), ws.numel()),
+           "smooth")
+    return out
+
+
+def field_stats(ctx: Context, grid: Grid, fields: Sequence[torch.Tensor], nbins: int = 0, lo: float = -1.0,
+                hi: float = 1.0, nbins2: int = 0):
+    """(moments [nf, 4], corr [nf, nf], counts [nf, nbins] or None, joint [nf-1, nbins2, nbins2] or None)."""
+    nf = len(fields)
+    dev = dict(device="cuda", dtype=torch.float64)
+    mom = torch.empty((nf, 4), **dev)
+    cor = torch.empty((nf, nf), **dev)
+    cnt = torch.empty((nf, nbins), **dev) if nbins > 0 else None
+    jnt = torch.empty((nf - 1, nbins2, nbins2), **dev) if (nbins2 > 0 and nf > 1) else None
+    g = grid.cstruct
+    need = _check(lib().gridspt_stats_workspace_bytes(nf, nbins, nbins2 if jnt is not None else 0),
+                  "stats_workspace_bytes")
+    ws = ctx.workspace(need)
+    _check(lib().gridspt_field_stats(ctx.handle, ctypes.byref(g), nf, _ptr_array(fields), nbins, float(lo), float(hi),
+                                     nbins2, _ptr(mom), _ptr(cor), _ptr(cnt), _ptr(jnt), _ptr(ws), ws.numel()),
+           "field_stats")
+    return mom, cor, cnt, jnt
 
 
 def sum_orders(ctx: Context, grid: Grid, delta: Sequence[torch.Tensor], coef: Sequence[float],

@@ -393,6 +393,155 @@ __global__ __launch_bounds__(256) void k_pform_products(PFormProducts<T> a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// One-point statistics of real fields (Sec. III A-B): FP64 sums of x, x^2, x^3,
+// x^4 per field and x_a x_b per pair (fixed-order block trees, then the
+// fixed-order reduction of k_power_reduce), and histograms: per-block counts
+// in LDS (integer LDS atomics; the count does not depend on their order), then
+// an integer sum over blocks.  Bin b = floor((x - lo) * scale) in FP64,
+// values outside [0, nbins) dropped.
+// ---------------------------------------------------------------------------
+constexpr int kStatsMaxFields = 8;
+constexpr int kStatsQ = 4 * kStatsMaxFields + kStatsMaxFields * (kStatsMaxFields - 1) / 2;  // 60
+constexpr int kStatsThreads = 256;
+
+template <typename T>
+struct MomentArgs {
+    const T* f[kStatsMaxFields];
+    int nf;
+    size_t ncell;
+    double* partial;  // [gridDim.x][kStatsQ]
+};
+
+__host__ __device__ constexpr int pair_index(int i, int j) {  // i < j < 8
+    return i * kStatsMaxFields - i * (i + 1) / 2 + (j - i - 1);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kStatsThreads) void k_moments_partial(MomentArgs<T> a) {
+    __shared__ double red[kStatsQ * (kStatsThreads / 64)];
+    double s[kStatsMaxFields][4], x[kStatsQ - 4 * kStatsMaxFields];
+#pragma unroll
+    for (int i = 0; i < kStatsMaxFields; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[i][q] = 0.0;
+#pragma unroll
+    for (int i = 0; i < kStatsQ - 4 * kStatsMaxFields; ++i) x[i] = 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell; c += stride) {
+        double v[kStatsMaxFields];
+#pragma unroll
+        for (int i = 0; i < kStatsMaxFields; ++i) v[i] = i < a.nf ? (double)a.f[i][c] : 0.0;
+#pragma unroll
+        for (int i = 0; i < kStatsMaxFields; ++i) {
+            const double p2 = v[i] * v[i];
+            s[i][0] += v[i];
+            s[i][1] += p2;
+            s[i][2] += p2 * v[i];
+            s[i][3] += p2 * p2;
+#pragma unroll
+            for (int j = i + 1; j < kStatsMaxFields; ++j) x[pair_index(i, j)] += v[i] * v[j];
+        }
+    }
+    // per item: butterfly sum within each wavefront (fixed order), then the
+    // wavefront totals in wave order
+    constexpr int NW = kStatsThreads / 64;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    double* out = a.partial + (size_t)blockIdx.x * kStatsQ;
+#pragma unroll
+    for (int q = 0; q < kStatsQ; ++q) {
+        const double t = wave_sum(q < 4 * kStatsMaxFields ? s[q / 4][q % 4] : x[q - 4 * kStatsMaxFields]);
+        if (lane == 0) red[q * NW + wave] = t;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kStatsQ; q += blockDim.x) {
+        double t = 0.0;
+        for (int w = 0; w < NW; ++w) t += red[q * NW + w];
+        out[q] = t;
+    }
+}
+
+// moments [nf][4]: mean, variance, skewness, excess kurtosis; corr [nf][nf]: Pearson r
+static __global__ void k_moments_final(const double* sums, int nf, double ncell, double* moments, double* corr) {
+    const int t = threadIdx.x;
+    auto mean_var = [&](int i, double& m, double& v) {
+        m = sums[4 * i] / ncell;
+        v = sums[4 * i + 1] / ncell - m * m;
+    };
+    if (t < nf && moments) {
+        double m, v;
+        mean_var(t, m, v);
+        const double e3 = sums[4 * t + 2] / ncell, e2 = sums[4 * t + 1] / ncell, e4 = sums[4 * t + 3] / ncell;
+        const double c3 = e3 - 3.0 * m * e2 + 2.0 * m * m * m;
+        const double c4 = e4 - 4.0 * m * e3 + 6.0 * m * m * e2 - 3.0 * m * m * m * m;
+        moments[4 * t] = m;
+        moments[4 * t + 1] = v;
+        moments[4 * t + 2] = v > 0.0 ? c3 / (v * sqrt(v)) : 0.0;
+        moments[4 * t + 3] = v > 0.0 ? c4 / (v * v) - 3.0 : 0.0;
+    }
+    if (t < nf * nf && corr) {
+        const int i = t / nf, j = t % nf;
+        double mi, vi, mj, vj;
+        mean_var(i, mi, vi);
+        mean_var(j, mj, vj);
+        double cov;
+        if (i == j) cov = vi;
+        else {
+            const int a = i < j ? i : j, b = i < j ? j : i;
+            cov = sums[4 * kStatsMaxFields + pair_index(a, b)] / ncell - mi * mj;
+        }
+        corr[t] = (vi > 0.0 && vj > 0.0) ? cov / sqrt(vi * vj) : 0.0;
+    }
+}
+
+template <typename T>
+struct HistArgs {
+    const T* f[kStatsMaxFields];
+    int nbins;       // per axis
+    int joint;       // 0: histogram of field blockIdx.y; 1: joint of field 0 and field 1 + blockIdx.y
+    double lo, scale;
+    size_t ncell;
+    uint32_t* partial;  // [gridDim.y][gridDim.x][nb], nb = nbins or nbins^2
+};
+
+template <typename T>
+__device__ __forceinline__ int bin_of(T x, double lo, double scale, int nbins) {
+    const double fb = floor(((double)x - lo) * scale);
+    return (fb >= 0.0 && fb < (double)nbins) ? (int)fb : -1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kStatsThreads) void k_hist_partial(HistArgs<T> a) {
+    extern __shared__ uint32_t h[];
+    const int nb = a.joint ? a.nbins * a.nbins : a.nbins;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) h[i] = 0u;
+    __syncthreads();
+    const T* x = a.joint ? a.f[0] : a.f[blockIdx.y];
+    const T* y = a.joint ? a.f[1 + blockIdx.y] : nullptr;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell; c += stride) {
+        int b = bin_of(x[c], a.lo, a.scale, a.nbins);
+        if (a.joint && b >= 0) {
+            const int b2 = bin_of(y[c], a.lo, a.scale, a.nbins);
+            b = b2 >= 0 ? b * a.nbins + b2 : -1;
+        }
+        if (b >= 0) atomicAdd(&h[b], 1u);
+    }
+    __syncthreads();
+    uint32_t* out = a.partial + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * nb;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) out[i] = h[i];
+}
+
+// counts[y][bin] = sum over blocks (exact integers), as doubles
+static __global__ void k_hist_reduce(const uint32_t* partial, int nblocks, int nb, int ny, double* counts) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb * ny) return;
+    const int y = t / nb, b = t % nb;
+    uint64_t s = 0;
+    for (int i = 0; i < nblocks; ++i) s += partial[((size_t)y * nblocks + i) * nb + b];
+    counts[t] = (double)s;
+}
+
 // Mean and sample standard deviation over nreal realisations of `count`
 // doubles at byte stride zs: a fixed-order two-pass sum per item.
 static __global__ void k_batch_stats(const double* x, int nreal, int count, size_t zs, double* mean, double* sdev) {

@@ -623,6 +623,28 @@ int gridspt_orders_pform(gridspt_ctx* c, const gridspt_grid* g, int32_t nmax, in
     });
 }
 
+int gridspt_smooth(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, const void* const* fields_k,
+                   const double* coef, int32_t cumulative, double radius, void* const* out, void* work,
+                   int64_t work_bytes) {
+    if (!c || !fields_k || !coef || !out) return GRIDSPT_EINVAL;
+    CHECK(check_grid(g));
+    if (nfields < 1 || nfields > 5 || !(radius >= 0.0) || !std::isfinite(radius)) return GRIDSPT_EINVAL;
+    for (int i = 0; i < nfields; ++i) {
+        CHECK(check_ptr(fields_k[i]));
+        CHECK(check_ptr(out[i]));
+        if (!std::isfinite(coef[i])) return GRIDSPT_EINVAL;
+    }
+    if (!work) return GRIDSPT_EWORKSPACE;
+    CHECK(check_ptr(work));
+    if (work_bytes < gridspt_workspace_bytes(g, 1)) return GRIDSPT_EWORKSPACE;
+    const Tuning tu{};
+    return dispatch(g, [&](auto tag, auto nc) -> int {
+        using T = typename decltype(tag)::type;
+        constexpr int N = decltype(nc)::value;
+        return run_smooth<T, N>(c, g, nfields, fields_k, coef, cumulative, radius, out, work, tu, Batch{});
+    });
+}
+
 int gridspt_sum_orders(gridspt_ctx* c, const gridspt_grid* g, int32_t nmax, const void* const* delta,
                        const double* coef, double* out) {
     if (!c || !delta || !coef) return GRIDSPT_EINVAL;
@@ -669,6 +691,93 @@ int gridspt_power(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, const 
     CHECK(check_ptr(work));
     if (work_bytes < gridspt_power_workspace_bytes(g, npairs, nbins)) return GRIDSPT_EWORKSPACE;
     return power_enqueue(c, g, fields_k, npairs, pairs, nbins, edge_n2, pk, kmean, nmodes, work, Batch{});
+}
+
+// ---- one-point statistics ----
+
+static constexpr int kMomentBlocks = 1024, kHistBlocks = 512;
+
+static int64_t stats_ws(int nfields, int nbins, int nbins2) {
+    int64_t b = align_up((int64_t)kMomentBlocks * kStatsQ * 8) + align_up((int64_t)kStatsQ * 8);
+    if (nbins > 0) b += align_up((int64_t)nfields * kHistBlocks * nbins * 4);
+    if (nbins2 > 0 && nfields > 1) b += align_up((int64_t)(nfields - 1) * kHistBlocks * nbins2 * nbins2 * 4);
+    return b;
+}
+
+int64_t gridspt_stats_workspace_bytes(int32_t nfields, int32_t nbins, int32_t nbins2) {
+    if (nfields < 1 || nfields > kStatsMaxFields || nbins < 0 || nbins > 1024 || nbins2 < 0 || nbins2 > 64)
+        return GRIDSPT_EINVAL;
+    return stats_ws(nfields, nbins, nbins2);
+}
+
+int gridspt_field_stats(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, const void* const* fields,
+                        int32_t nbins, double lo, double hi, int32_t nbins2, double* moments, double* corr,
+                        double* counts, double* joint, void* work, int64_t work_bytes) {
+    if (!c || !fields) return GRIDSPT_EINVAL;
+    CHECK(check_grid(g));
+    if (nfields < 1 || nfields > kStatsMaxFields || nbins < 0 || nbins > 1024 || nbins2 < 0 || nbins2 > 64)
+        return GRIDSPT_EINVAL;
+    if ((counts && nbins < 1) || (joint && (nbins2 < 1 || nfields < 2))) return GRIDSPT_EINVAL;
+    if ((counts || joint) && !(std::isfinite(lo) && std::isfinite(hi) && lo < hi)) return GRIDSPT_EINVAL;
+    for (int i = 0; i < nfields; ++i) CHECK(check_ptr(fields[i]));
+    for (double* p : {moments, corr, counts, joint})
+        if (p) CHECK(check_ptr(p));
+    if (!work) return GRIDSPT_EWORKSPACE;
+    CHECK(check_ptr(work));
+    if (work_bytes < stats_ws(nfields, counts ? nbins : 0, joint ? nbins2 : 0)) return GRIDSPT_EWORKSPACE;
+    const Dims d = dims_of(g);
+    const size_t ncell = (size_t)d.ncell();
+    char* base = static_cast<char*>(work);
+    double* mpart = reinterpret_cast<double*>(base);
+    double* msum = reinterpret_cast<double*>(base + align_up((int64_t)kMomentBlocks * kStatsQ * 8));
+    char* hbase = base + align_up((int64_t)kMomentBlocks * kStatsQ * 8) + align_up((int64_t)kStatsQ * 8);
+    uint32_t* hpart = reinterpret_cast<uint32_t*>(hbase);
+    uint32_t* jpart =
+        reinterpret_cast<uint32_t*>(hbase + (counts ? align_up((int64_t)nfields * kHistBlocks * nbins * 4) : 0));
+    auto go = [&](auto tag) -> int {
+        using T = typename decltype(tag)::type;
+        if (moments || corr) {
+            MomentArgs<T> a{};
+            for (int i = 0; i < nfields; ++i) a.f[i] = static_cast<const T*>(fields[i]);
+            a.nf = nfields;
+            a.ncell = ncell;
+            a.partial = mpart;
+            CHECK(launch(c, KD_MOMENTS, (double)nfields * ncell * d.real_bytes, dim3(kMomentBlocks),
+                         dim3(kStatsThreads), 0, k_moments_partial<T>, a));
+            CHECK(launch(c, KD_MOMENTS, (double)kMomentBlocks * kStatsQ * 8, dim3(kStatsQ), dim3(kReduceThreads), 0,
+                         k_power_reduce, (const double*)mpart, kMomentBlocks, kStatsQ, msum, (size_t)0));
+            CHECK(launch(c, KD_MOMENTS, 0.0, dim3(1), dim3(64), 0, k_moments_final, (const double*)msum, nfields,
+                         (double)ncell, moments, corr));
+        }
+        HistArgs<T> h{};
+        for (int i = 0; i < nfields; ++i) h.f[i] = static_cast<const T*>(fields[i]);
+        h.lo = lo;
+        h.ncell = ncell;
+        if (counts) {
+            h.nbins = nbins;
+            h.joint = 0;
+            h.scale = (double)nbins / (hi - lo);
+            h.partial = hpart;
+            CHECK(launch(c, KD_HIST, (double)nfields * ncell * d.real_bytes, dim3(kHistBlocks, nfields),
+                         dim3(kStatsThreads), (size_t)nbins * 4, k_hist_partial<T>, h));
+            CHECK(launch(c, KD_HIST, 0.0, dim3((nfields * nbins + 255) / 256), dim3(256), 0, k_hist_reduce,
+                         (const uint32_t*)hpart, kHistBlocks, nbins, (int)nfields, counts));
+        }
+        if (joint) {
+            const int nb2 = nbins2 * nbins2;
+            h.nbins = nbins2;
+            h.joint = 1;
+            h.scale = (double)nbins2 / (hi - lo);
+            h.partial = jpart;
+            CHECK(launch(c, KD_HIST, 2.0 * (nfields - 1) * ncell * d.real_bytes, dim3(kHistBlocks, nfields - 1),
+                         dim3(kStatsThreads), (size_t)nb2 * 4, k_hist_partial<T>, h));
+            CHECK(launch(c, KD_HIST, 0.0, dim3(((nfields - 1) * nb2 + 255) / 256), dim3(256), 0, k_hist_reduce,
+                         (const uint32_t*)jpart, kHistBlocks, nb2, (int)(nfields - 1), joint));
+        }
+        return GRIDSPT_OK;
+    };
+    if (g->dtype == GRIDSPT_F64) return go(tag_t<double>{});
+    return go(tag_t<float>{});
 }
 
 int64_t gridspt_bispectrum_workspace_bytes(const gridspt_grid* g, int32_t ntri, const int32_t* tri_bins,

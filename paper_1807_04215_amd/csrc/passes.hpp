@@ -785,6 +785,73 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xderived(RegenArgs
 }
 
 // --------------------------------------------------------------------------
+// P3 for smoothed fields (Sec. III A-B): rows (kz, ky') of up to five cubes;
+// output o is the inverse x transform of exp(-k^2 R^2 / 2) S_o(k) with
+// S_o = sum_{i <= o} coef_i F_i (cumulative, the truncated series of Eq. 8)
+// or coef_o F_o, written transposed to S3 field o.
+// --------------------------------------------------------------------------
+template <typename T>
+struct SmoothArgs {
+    const cpx<T>* cube[5];
+    double coef[5];
+    int nin, cumulative;
+    double kF, radius;
+    cpx<T>* s3;
+    size_t s3_field;
+};
+
+template <typename T, int N, int V>
+__global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xsmooth(SmoothArgs<T> a, const cpx<T>* __restrict__ tw,
+                                                                       CubeDims cd, size_t zs) {
+    using RW = Rows<T, N, V>;
+    using PL = typename RW::PL;
+    constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
+    __shared__ cpx<T> lds[RPB * ROWE];
+    const Twiddles<T, PL, false> tws{tw};
+    const uint32_t groups = (cd.Ky + RPB - 1) / RPB;
+    const uint32_t blk = xcd_block(blockIdx.x, cd.Kz * groups);
+    const int kz = blk / groups, ky0 = (blk % groups) * RPB;
+    const int r = threadIdx.x / P, l = threadIdx.x % P;
+    const int kyc = ky0 + r;
+    const bool active = kyc < cd.Ky;
+    const int ky = active ? (kyc <= cd.Kc ? kyc : kyc - cd.Ky) : 0;
+    const int nrows = min(RPB, cd.Ky - ky0);
+    const size_t cbase = ((size_t)kz * cd.Ky + kyc) * cd.Ky;
+    cpx<T>* s3 = zptr(a.s3, zs);
+    cpx<T>* row = lds + r * ROWE;
+    const size_t outbase = (size_t)kz * N * cd.Ky + ky0;
+    const double g = -0.5 * a.kF * a.kF * a.radius * a.radius;
+    // the window of each kept element, once for all outputs
+    T w[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = l + P * e;
+        const int kx = signed_pos(p, N);
+        const double n2 = (double)((int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz);
+        w[e] = (active && pos_to_compact(p, cd.Kc, N) >= 0) ? (T)exp(g * n2) : (T)0;
+    }
+    static_for<5>([&](auto oc) {
+        constexpr int o = decltype(oc)::value;
+        if (o >= a.nin) return;
+        cpx<T> v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int ic = pos_to_compact(l + P * e, cd.Kc, N);
+            cpx<T> c = {(T)0, (T)0};
+            if (w[e] != (T)0) {
+#pragma unroll
+                for (int i = 0; i <= o; ++i)
+                    if (a.cumulative || i == o)
+                        c = cadd(c, cscale(zptr(a.cube[i], zs)[cbase + ic], (T)a.coef[i]));
+                c = cscale(c, w[e]);
+            }
+            v[e] = c;
+        }
+        x_inverse_store<T, N, V>(v, lds, row, tws, l, s3 + (size_t)o * a.s3_field + outbase, cd.Ky, nrows);
+    });
+}
+
+// --------------------------------------------------------------------------
 // P4: y pass, inverse.  Rows (kz, x) of S3 (Ky values, zero-extended to N);
 // block = RPB consecutive kz at one x; grid.y = field.  Writes S4 [x][y][kz].
 // --------------------------------------------------------------------------

@@ -125,6 +125,19 @@ struct Pipe {
         });
     }
 
+    // P3 of smoothed spectra -> S3 (A), one output per input
+    int xsmooth(SmoothArgs<T> sa) {
+        sa.s3 = A();
+        sa.s3_field = (size_t)L.a_field_s3;
+        return with_variant<T, N>(tu.v[KD_XSMOOTH], [&](auto vc) {
+            constexpr int V = decltype(vc)::value;
+            using RW = Rows<T, N, V>;
+            const double bytes = nb() * ((double)sa.nin * d.cube() + (double)sa.nin * d.s3()) * d.cpx_bytes;
+            return launch(c, KD_XSMOOTH, bytes, dim3((unsigned)(d.Kz * ((d.Ky + RW::RPB - 1) / RW::RPB)), 1, nz()),
+                          dim3(RW::THREADS), 0, k_xsmooth<T, N, V>, sa, (const cpx<T>*)tw(), cd, bt.zs);
+        });
+    }
+
     // P3 from stored spectra: delta_m, u_m (4 fields) -> S3 (A)
     int xregen(RegenArgs<T> r) {
         r.s3 = A();
@@ -381,6 +394,27 @@ int run_shells(gridspt_ctx* c, const gridspt_grid* g, int nslots, const void* co
     return GRIDSPT_OK;
 }
 
+// Gaussian smoothing of cube spectra, cumulative or one by one (nfields <= 5)
+template <typename T, int N>
+int run_smooth(gridspt_ctx* c, const gridspt_grid* g, int nfields, const void* const* fields_k, const double* coef,
+               int cumulative, double radius, void* const* out, void* work, const Tuning& tu, Batch b) {
+    Pipe<T, N> p(c, g, work, 1, tu, b);
+    GRIDSPT_CHECK(p.twiddles());
+    SmoothArgs<T> sa{};
+    for (int i = 0; i < nfields; ++i) {
+        sa.cube[i] = static_cast<const cpx<T>*>(fields_k[i]);
+        sa.coef[i] = coef[i];
+    }
+    sa.nin = nfields;
+    sa.cumulative = cumulative ? 1 : 0;
+    sa.kF = 2.0 * M_PI / g->box;
+    sa.radius = radius;
+    GRIDSPT_CHECK(p.xsmooth(sa));
+    T* outs[5];
+    for (int i = 0; i < nfields; ++i) outs[i] = static_cast<T*>(out[i]);
+    return p.to_real(nfields, outs);
+}
+
 // Orders 1..nmax with the printed sources of Eq. 10 (the P-form): after each
 // order the 15 derived fields of Eq. 15/16 are made from its spectra; the
 // sources of order n are formed pointwise from the 17 fields of every earlier
@@ -561,6 +595,9 @@ int run_adjoint(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, 
     template int gridspt::run_linear_field<T, N>(gridspt_ctx*, const gridspt_grid*, const gridspt_linpk*,         \
                                                  const void*, void*, void*, void*, const gridspt::Tuning&,         \
                                                  gridspt::Batch);                                                  \
+    template int gridspt::run_smooth<T, N>(gridspt_ctx*, const gridspt_grid*, int, const void* const*,            \
+                                           const double*, int, double, void* const*, void*,                      \
+                                           const gridspt::Tuning&, gridspt::Batch);                              \
     template int gridspt::run_orders_pform<T, N>(gridspt_ctx*, const gridspt_grid*, int, int64_t, int64_t,       \
                                                  const void*, void* const*, void* const*, void* const*,            \
                                                  void* const*, void*, const gridspt::Tuning&, gridspt::Batch);     \

@@ -50,6 +50,9 @@ enum Kind {
     KD_ZFWD_PAIR,
     KD_XFUSED_PFORM,
     KD_XDERIVED,
+    KD_XSMOOTH,
+    KD_MOMENTS,
+    KD_HIST,
     KD_COUNT
 };
 
@@ -58,7 +61,8 @@ inline const char* const kKindNames[KD_COUNT] = {
     "xfused_order1", "xfused_order",   "xfused_forward", "xshell",      "yinv",        "zinv",
     "power_partial", "power_final",    "triple_partial", "triple_final", "bisp_final", "sum_orders",
     "copy",          "batch_stats",    "zfwd_adjoint", "xregen",        "xfused_adj",  "xfused_adj1",
-    "adj_products",  "pform_products", "zfwd_pair",    "xfused_pform",  "xderived"};
+    "adj_products",  "pform_products", "zfwd_pair",    "xfused_pform",  "xderived",    "xsmooth",
+    "moments",       "histogram"};
 
 // Launch variant of each pass kind (see Rows): 0 is the default shape.
 struct Tuning {
@@ -271,6 +275,11 @@ template <typename T, int N>
 int run_adjoint(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, int nmax, int64_t n2max2,
                 const void* const* delta_k, const void* const* theta_k, const void* const* gdelta, void* gnoise,
                 void* work, const Tuning& tu, Batch b);
+
+// Gaussian-smoothed (cumulative) sums of up to five cube spectra into real fields
+template <typename T, int N>
+int run_smooth(gridspt_ctx* c, const gridspt_grid* g, int nfields, const void* const* fields_k, const double* coef,
+               int cumulative, double radius, void* const* out, void* work, const Tuning& tu, Batch b);
 
 // the printed (P-form) sources of Eq. 10 instead of the divergence form; same
 // arguments as run_orders, workspace pform_layout

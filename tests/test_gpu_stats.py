@@ -1,0 +1,106 @@
+"""Field statistics on the GPU (gridspt_smooth, gridspt_field_stats) against the
+oracle's plain definitions (oracle/stats.py, pinned in test_oracle_stats.py).
+
+Smoothed fields: relative L2 1e-12 (FP64), 1e-5 (FP32).  Statistics are taken
+of the GPU's own fields on both sides (the oracle reads them back), so moments
+and correlations agree to FP64 summation order and histogram counts exactly.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import stats
+import paper_1807_04215_amd as g
+from tests.layouts import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+NS, GAMMA = 0.96, 0.21
+TOL = {g.F64: 1e-12, g.F32: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available()
+    return g.Context()
+
+
+def _orders(ctx, n, box, nmax, dtype, seed):
+    cut = g.cut_n2max(n, box)
+    grid = g.Grid(n, box, g.cube_kc(cut), dtype)
+    d1 = oracle.linear_field(n, box, oracle.sigma8_amp(0.8, NS, GAMMA), NS, GAMMA, 1.0, cut, seed)
+    if dtype == g.F32:
+        d1 = d1.astype(np.float32).astype(np.float64)
+    out = g.orders(ctx, grid, nmax, cut, cut, torch.from_numpy(d1).to("cuda", grid.real_dtype))
+    ref = oracle.orders(d1, box, nmax, cut, cut)
+    return grid, out, ref
+
+
+@pytest.mark.parametrize("dtype", [g.F64, g.F32])
+@pytest.mark.parametrize("n,box,radius", [(32, 200.0, 12.0), (48, 300.0, 9.0), (32, 200.0, 0.0)])
+def test_smooth_matches_oracle(ctx, dtype, n, box, radius):
+    nmax = 5
+    grid, out, (rd, rt, rdk, rtk) = _orders(ctx, n, box, nmax, dtype, 3)
+    coef = [0.8 ** (i + 1) for i in range(nmax)]
+    for cumulative in (True, False):
+        sm = g.smooth(ctx, grid, out.delta_k, coef, radius, cumulative=cumulative)
+        ctx.sync()
+        ref = stats.smooth(list(rdk), coef, radius, box, cumulative=cumulative)
+        for j in range(nmax):
+            e = rel_l2(sm[j].cpu().numpy(), ref[j])
+            assert e < TOL[dtype], (cumulative, j, e)
+
+
+@pytest.mark.parametrize("dtype", [g.F64, g.F32])
+def test_field_stats_match_oracle(ctx, dtype):
+    n, box, nmax = 48, 300.0, 4
+    grid, out, _ = _orders(ctx, n, box, nmax, dtype, 5)
+    sm = g.smooth(ctx, grid, out.delta_k, [1.0] * nmax, 8.0)
+    fields = [sm[-1]] + sm[:-1]                 # reference first: the highest-order sum
+    mom, cor, cnt, jnt = g.field_stats(ctx, grid, fields, nbins=40, lo=-0.6, hi=0.9, nbins2=16)
+    ctx.sync()
+    host = [f.cpu().numpy().astype(np.float64) for f in fields]
+    assert np.allclose(mom.cpu().numpy(), stats.moments(host), rtol=1e-10, atol=1e-14)
+    assert np.allclose(cor.cpu().numpy(), stats.correlation(host), rtol=1e-10, atol=1e-14)
+    for i, h in enumerate(host):
+        assert np.array_equal(cnt[i].cpu().numpy(), stats.histogram(h, -0.6, 0.9, 40)), i
+    for j in range(1, len(host)):
+        assert np.array_equal(jnt[j - 1].cpu().numpy(), stats.joint_histogram(host[0], host[j], -0.6, 0.9, 16)), j
+
+
+@pytest.mark.parametrize("dtype", [g.F64, g.F32])
+def test_histogram_bin_edges_exact(ctx, dtype):
+    """Values on bin edges, on lo and hi, just inside and outside: the bin
+    decision is the same FP64 expression on both sides."""
+    n = 16
+    grid = g.Grid(n, 100.0, 5, dtype)
+    rng = np.random.default_rng(7)
+    vals = np.concatenate([np.arange(-8, 9) / 8.0, [-1.0 - 1e-7, 1.0 - 1e-7, 0.5 + 1e-9, -0.25 - 1e-9]])
+    x = rng.choice(vals, size=(n, n, n))
+    if dtype == g.F32:
+        x = x.astype(np.float32)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+    y = torch.roll(xt, 3, dims=0)
+    _, _, cnt, jnt = g.field_stats(ctx, grid, [xt, y], nbins=16, lo=-1.0, hi=1.0, nbins2=8)
+    ctx.sync()
+    xh, yh = x.astype(np.float64), y.cpu().numpy().astype(np.float64)
+    assert np.array_equal(cnt[0].cpu().numpy(), stats.histogram(xh, -1.0, 1.0, 16))
+    assert np.array_equal(cnt[1].cpu().numpy(), stats.histogram(yh, -1.0, 1.0, 16))
+    assert np.array_equal(jnt[0].cpu().numpy(), stats.joint_histogram(xh, yh, -1.0, 1.0, 8))
+
+
+def test_stats_properties_at_512(ctx):
+    """At 512^3 (ragged against the block grid-stride): counts plus the values
+    outside the range add up to N^3, r(a, a) = 1, r(a, -a) = -1."""
+    n = 512
+    grid = g.Grid(n, 1000.0, 170, g.F32)
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    a = torch.randn((n,) * 3, generator=gen, device="cuda")
+    mom, cor, cnt, _ = g.field_stats(ctx, grid, [a, -a, a], nbins=64, lo=-2.0, hi=2.0)
+    ctx.sync()
+    inside = int(((a >= -2.0) & (a < 2.0)).sum().item())
+    assert cnt[0].sum().item() == inside
+    c = cor.cpu().numpy()
+    assert abs(c[0, 2] - 1.0) < 1e-12 and abs(c[0, 1] + 1.0) < 1e-12
+    assert abs(mom[0, 1].item() - 1.0) < 1e-3
