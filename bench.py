@@ -558,8 +558,7 @@ def main() -> int:
     coef = [1.0] * nmax
 
     def step():
-        g.linear_field(ctx, grid, lp, out=out.delta[0])
-        g.orders(ctx, grid, nmax, cut, cut, out.delta[0], out=out)
+        g.orders_linear(ctx, grid, lp, nmax, cut, out=out)  # linear field + orders 1..nmax
         g.sum_orders(ctx, grid, out.delta, coef, out=total)
         if spectra:
             g.power(ctx, grid, out.delta_k, pairs, edges)

@@ -201,6 +201,15 @@ int gridspt_field_stats(gridspt_ctx* ctx, const gridspt_grid* g, int32_t nfields
                         int32_t nbins, double lo, double hi, int32_t nbins2, double* moments, double* corr,
                         double* counts, double* joint, void* work, int64_t work_bytes);
 
+/* gridspt_linear_field followed by gridspt_orders in one pass sequence: the
+ * seeded linear field of lp (W1 = lp->n2max) is formed in Fourier space and
+ * delta_1, u_1 are made from it directly (no inverse and forward transform of
+ * delta_1 in between).  Outputs as gridspt_orders (delta[0] receives delta_1);
+ * equal to the two calls up to rounding.  Workspace as gridspt_workspace_bytes. */
+int gridspt_orders_linear(gridspt_ctx* ctx, const gridspt_grid* g, const gridspt_linpk* lp, int32_t nmax,
+                          int64_t n2max2, void* const* delta, void* const* theta, void* const* delta_k,
+                          void* const* theta_k, void* work, int64_t work_bytes);
+
 /* Final sum of orders (the truncated series of Eq. 8):
  * out(x) = sum_{n=1..nmax} coef[n-1] delta_n(x), accumulated in FP64.
  * delta: host array of nmax device pointers; coef: host array of nmax;

@@ -99,6 +99,8 @@ def lib():
             "gridspt_batch_destroy": ([vp], None),
             "gridspt_batch_buffer": ([vp, i32, i32, i32, i32, ctypes.POINTER(vp)], ctypes.c_int),
             "gridspt_batch_tuning": ([vp, i32, i32, vp, vp, vp], ctypes.c_int),
+            "gridspt_orders_linear": ([vp, gp, ctypes.POINTER(_LinPk), i32, i64, vp, vp, vp, vp, vp, i64],
+                                      ctypes.c_int),
             "gridspt_pform_workspace_bytes": ([gp, i32], i64),
             "gridspt_orders_pform": ([vp, gp, i32, i64, i64, vp, vp, vp, vp, vp, vp, i64], ctypes.c_int),
             "gridspt_smooth": ([vp, gp, i32, vp, vp, i32, dbl, vp, vp, i64], ctypes.c_int),
@@ -392,6 +394,22 @@ def orders(ctx: Context, grid: Grid, nmax: int, n2max1: int, n2max2: int, delta1
     tk = _ptr_array(out.theta_k) if out.theta_k is not None else None
     _check(lib().gridspt_orders(ctx.handle, ctypes.byref(g), nmax, n2max1, n2max2, _ptr(delta1), d, t, dk, tk,
                                 _ptr(ws), ws.numel()), "orders")
+    return out
+
+
+def orders_linear(ctx: Context, grid: Grid, lp: LinearSpectrum, nmax: int, n2max2: int,
+                  out: Optional[Orders] = None, spectra: bool = True) -> Orders:
+    """Seeded linear field and orders 1..nmax in one pass sequence (delta[0] = delta_1)."""
+    out = out if out is not None else alloc_orders(grid, nmax, spectra)
+    g = grid.cstruct
+    c = _linpk(lp)
+    ws = ctx.workspace(workspace_bytes(grid, nmax))
+    d = _ptr_array(out.delta)
+    t = _ptr_array(out.theta)
+    dk = _ptr_array(out.delta_k) if out.delta_k is not None else None
+    tk = _ptr_array(out.theta_k) if out.theta_k is not None else None
+    _check(lib().gridspt_orders_linear(ctx.handle, ctypes.byref(g), ctypes.byref(c), nmax, n2max2, d, t, dk, tk,
+                                       _ptr(ws), ws.numel()), "orders_linear")
     return out
 
 

@@ -581,7 +581,35 @@ int gridspt_orders(gridspt_ctx* c, const gridspt_grid* g, int32_t nmax, int64_t 
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
         constexpr int N = decltype(nc)::value;
-        return run_orders<T, N>(c, g, nmax, n2max1, n2max2, delta1, delta, theta, delta_k, theta_k, work, tu,
+        return run_orders<T, N>(c, g, nullptr, nmax, n2max1, n2max2, delta1, delta, theta, delta_k, theta_k, work, tu,
+                                Batch{});
+    });
+}
+
+int gridspt_orders_linear(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, int32_t nmax,
+                          int64_t n2max2, void* const* delta, void* const* theta, void* const* delta_k,
+                          void* const* theta_k, void* work, int64_t work_bytes) {
+    if (!c || !lp) return GRIDSPT_EINVAL;
+    CHECK(check_grid(g));
+    if (nmax < 1 || nmax > 5) return GRIDSPT_EINVAL;
+    CHECK(check_linpk(g, lp));
+    if (nmax > 1) CHECK(check_mask(g, n2max2));
+    if (!delta || !theta) return GRIDSPT_EINVAL;
+    for (int i = 0; i < nmax; ++i) {
+        CHECK(check_ptr(delta[i]));
+        if (i > 0) CHECK(check_ptr(theta[i]));
+        else if (theta[0]) CHECK(check_ptr(theta[0]));
+        if (delta_k && delta_k[i]) CHECK(check_ptr(delta_k[i]));
+        if (theta_k && theta_k[i]) CHECK(check_ptr(theta_k[i]));
+    }
+    if (!work) return GRIDSPT_EWORKSPACE;
+    CHECK(check_ptr(work));
+    if (work_bytes < gridspt_workspace_bytes(g, nmax)) return GRIDSPT_EWORKSPACE;
+    const Tuning tu{};
+    return dispatch(g, [&](auto tag, auto nc) -> int {
+        using T = typename decltype(tag)::type;
+        constexpr int N = decltype(nc)::value;
+        return run_orders<T, N>(c, g, lp, nmax, lp->n2max, n2max2, nullptr, delta, theta, delta_k, theta_k, work, tu,
                                 Batch{});
     });
 }
@@ -938,9 +966,8 @@ int enqueue_group(gridspt_ctx* c, gridspt_batch* b, GroupPlan& p, const Tuning& 
     CHECK(dispatch(gr, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
         constexpr int N = decltype(nc)::value;
-        CHECK((run_linear_field<T, N>(c, gr, &g.lin, nullptr, delta[0], nullptr, work, tu, bt)));
-        return run_orders<T, N>(c, gr, nmax, g.lin.n2max, g.n2max2, delta[0], delta, theta, cube, nullptr, work, tu,
-                                bt);
+        return run_orders<T, N>(c, gr, &g.lin, nmax, g.lin.n2max, g.n2max2, nullptr, delta, theta, cube, nullptr, work,
+                                tu, bt);
     }));
     const unsigned one = 1;
     if (stats) {

@@ -126,6 +126,14 @@ __device__ __forceinline__ double lin_amplitude(double k, const LinParams& p) {
     return sqrt(p0 * p.vol) * p.growth;
 }
 
+// Radial table of the linear amplitude times N^-3 at every integer |n|^2:
+// tab[n2] = lin_amplitude(kF sqrt(n2)) N^-3 for 0 < n2 <= n2max, tab[0] = 0.
+static __global__ void k_amp_table(double* tab, int64_t n2max, double kF, double invN3, LinParams p) {
+    const int64_t n2 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n2 > n2max) return;
+    tab[n2] = n2 == 0 ? 0.0 : lin_amplitude(kF * sqrt((double)n2), p) * invN3;
+}
+
 // canonical registers of one row -> this row's LDS buffer in natural order
 template <typename PL, typename T>
 __device__ __forceinline__ void stage_row(const cpx<T> (&v)[PL::E], cpx<T>* row, int l) {
@@ -366,7 +374,18 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yfwd(const cpx<T>*
 // kz.  Forward x transform, the k-space step, optional cube stores, then the
 // inverse x transform of every output field, written transposed to S3.
 // --------------------------------------------------------------------------
-enum XMode { XM_ORDER = 0, XM_ORDER1 = 1, XM_LINEAR = 2, XM_FORWARD = 3, XM_ADJ = 4, XM_ADJ1 = 5, XM_PFORM = 6 };
+// LIN_ORDER1: the linear field from noise (as LINEAR) with the outputs of
+// order 1 (as ORDER1): delta_1 and u_1 without a round trip through real space
+enum XMode {
+    XM_ORDER = 0,
+    XM_ORDER1 = 1,
+    XM_LINEAR = 2,
+    XM_FORWARD = 3,
+    XM_ADJ = 4,
+    XM_ADJ1 = 5,
+    XM_PFORM = 6,
+    XM_LIN_ORDER1 = 7
+};
 
 template <typename T>
 struct XArgs {
@@ -381,6 +400,7 @@ struct XArgs {
     int64_t n2max;   // mask of this order
     double kF, invN3;
     LinParams lin;
+    const double* amp;  // LINEAR, LIN_ORDER1, ADJ1: the radial amplitude table (k_amp_table)
 };
 
 // inverse x transform of one output row and its transposed store into S3
@@ -514,9 +534,8 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
             const cpx<T> tn = {m10 * sdel.x + m11 * sthe.x, m10 * sdel.y + m11 * sthe.y};
             sd[e] = keep ? dn : cpx<T>{(T)0, (T)0};
             st[e] = keep ? tn : cpx<T>{(T)0, (T)0};
-        } else if constexpr (MODE == XM_LINEAR) {
-            T s = (T)0;
-            if (keep) s = (T)(lin_amplitude(a.kF * sqrt((double)n2), a.lin) * a.invN3);
+        } else if constexpr (MODE == XM_LINEAR || MODE == XM_LIN_ORDER1) {
+            const T s = keep ? (T)a.amp[n2] : (T)0;
             sd[e] = cscale(sd[e], s);
         } else if constexpr (MODE == XM_ADJ) {
             // (a, b) = W2 c_n M^T (G_delta, G_theta), M = [[n + 1/2, 1], [3/2, n]]
@@ -529,8 +548,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
             st[e] = keep ? bv : cpx<T>{(T)0, (T)0};
         } else if constexpr (MODE == XM_ADJ1) {
             // g w(k) = W1 A(k) (G_delta + G_theta): the transpose of the linear field
-            T s = (T)0;
-            if (keep) s = (T)(lin_amplitude(a.kF * sqrt((double)n2), a.lin) * a.invN3);
+            const T s = keep ? (T)a.amp[n2] : (T)0;
             sd[e] = cscale(cadd(sd[e], st[e]), s);
         } else {
             sd[e] = keep ? cscale(sd[e], invN3) : cpx<T>{(T)0, (T)0};
@@ -559,7 +577,9 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
         // ADJ: g V_x, g V_y, g V_z, g W;  ADJ1: g w
         // PFORM: delta, theta
         constexpr int NOUT_MAX =
-            (MODE == XM_ORDER) ? 5 : ((MODE == XM_ORDER1 || MODE == XM_ADJ) ? 4 : (MODE == XM_PFORM ? 2 : 1));
+            (MODE == XM_ORDER) ? 5
+                               : ((MODE == XM_ORDER1 || MODE == XM_LIN_ORDER1 || MODE == XM_ADJ) ? 4
+                                                                                                  : (MODE == XM_PFORM ? 2 : 1));
         constexpr int FIRST_U = (MODE == XM_ORDER || MODE == XM_PFORM) ? 2 : 1;
         const size_t outbase = (size_t)kz * N * cd.Ky + ky0;
         static_for<NOUT_MAX>([&](auto oc) {

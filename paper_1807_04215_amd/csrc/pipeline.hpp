@@ -55,6 +55,15 @@ struct Pipe {
     double nb() const { return (double)bt.nreal; }
     unsigned nz() const { return (unsigned)bt.nreal; }
 
+    // radial amplitude table of the linear field (realisation 0's workspace)
+    double* amp() const { return reinterpret_cast<double*>(ws + L.amp); }
+    int amp_table(const gridspt_grid* g, const gridspt_linpk* lp) {
+        const LinParams lin{lp->amp, lp->ns, lp->gamma, lp->growth, (double)N * N * N / (g->box * g->box * g->box)};
+        const int64_t n = lp->n2max + 1;
+        return launch(c, KD_TWIDDLE, (double)n * 8.0, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, k_amp_table,
+                      amp(), lp->n2max, 2.0 * M_PI / g->box, 1.0 / ((double)N * N * N), lin);
+    }
+
     // the shared table, computed once (realisation 0's workspace)
     int twiddles() {
         return launch(c, KD_TWIDDLE, (double)N * d.cpx_bytes, dim3((N + 255) / 256), dim3(256), 0, k_twiddles<T>,
@@ -196,6 +205,7 @@ struct Pipe {
                          : mode == XM_ADJ    ? KD_XFUSED_ADJ
                          : mode == XM_ADJ1   ? KD_XFUSED_ADJ1
                          : mode == XM_PFORM  ? KD_XFUSED_PFORM
+                         : mode == XM_LIN_ORDER1 ? KD_XFUSED_LINEAR
                                              : KD_XFUSED_FORWARD;
         return with_variant<T, N>(tu.v[kind], [&](auto vc) {
             constexpr int V = decltype(vc)::value;
@@ -215,6 +225,8 @@ struct Pipe {
                 case XM_ADJ: return launch(c, kind, bytes, grid, block, 0, k_xfused<T, N, V, XM_ADJ>, a, t, cd, bt.zs);
                 case XM_PFORM:
                     return launch(c, kind, bytes, grid, block, 0, k_xfused<T, N, V, XM_PFORM>, a, t, cd, bt.zs);
+                case XM_LIN_ORDER1:
+                    return launch(c, kind, bytes, grid, block, 0, k_xfused<T, N, V, XM_LIN_ORDER1>, a, t, cd, bt.zs);
                 case XM_ADJ1:
                     return launch(c, kind, bytes, grid, block, 0, k_xfused<T, N, V, XM_ADJ1>, a, t, cd, bt.zs);
                 default:
@@ -307,10 +319,11 @@ int run_linear_field(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk*
                      void* delta1, void* delta1_k, void* work, const Tuning& tu, Batch b) {
     Pipe<T, N> p(c, g, work, 1, tu, b);
     GRIDSPT_CHECK(p.twiddles());
+    GRIDSPT_CHECK(p.amp_table(g, lp));
     GRIDSPT_CHECK(p.zfwd_single(static_cast<const T*>(noise), noise == nullptr, lp->seed, lp->stream));
     GRIDSPT_CHECK(p.yfwd(1));
     XArgs<T> a = make_xargs<T>(p.d, g, 1, 1, lp->n2max, (cpx<T>*)delta1_k, nullptr);
-    a.lin = {lp->amp, lp->ns, lp->gamma, lp->growth, (double)N * N * N / (g->box * g->box * g->box)};
+    a.amp = p.amp();
     GRIDSPT_CHECK(p.xfused(XM_LINEAR, a));
     T* out[1] = {static_cast<T*>(delta1)};
     return p.to_real(1, out);
@@ -330,22 +343,29 @@ int run_forward(gridspt_ctx* c, const gridspt_grid* g, int64_t n2max, const void
 
 // Orders 1..nmax of the recursion (Eq. 10 in the divergence form)
 template <typename T, int N>
-int run_orders(gridspt_ctx* c, const gridspt_grid* g, int nmax, int64_t n2max1, int64_t n2max2, const void* delta1,
-               void* const* delta, void* const* theta, void* const* delta_k, void* const* theta_k, void* work,
-               const Tuning& tu, Batch b) {
+int run_orders(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, int nmax, int64_t n2max1,
+               int64_t n2max2, const void* delta1, void* const* delta, void* const* theta, void* const* delta_k,
+               void* const* theta_k, void* work, const Tuning& tu, Batch b) {
     Pipe<T, N> p(c, g, work, nmax, tu, b);
     auto dk = [&](int i) { return delta_k ? (cpx<T>*)delta_k[i] : nullptr; };
     auto tk = [&](int i) { return theta_k ? (cpx<T>*)theta_k[i] : nullptr; };
     GRIDSPT_CHECK(p.twiddles());
 
-    // order 1: delta_1 = theta_1 = W1 delta1_in; u_1 = (-ik/k^2) delta_1
-    GRIDSPT_CHECK(p.zfwd_single(static_cast<const T*>(delta1), false, 0, 0));
+    // order 1: delta_1 = theta_1 = W1 delta1_in (or the linear field of lp);
+    // u_1 = (-ik/k^2) delta_1
+    if (lp) {
+        GRIDSPT_CHECK(p.amp_table(g, lp));
+        GRIDSPT_CHECK(p.zfwd_single(nullptr, true, lp->seed, lp->stream));
+    } else {
+        GRIDSPT_CHECK(p.zfwd_single(static_cast<const T*>(delta1), false, 0, 0));
+    }
     GRIDSPT_CHECK(p.yfwd(1));
     {
         const int nout = nmax > 1 ? 4 : 1;
         cpx<T>* ct = (tk(0) && tk(0) != dk(0)) ? tk(0) : nullptr;
-        XArgs<T> a = make_xargs<T>(p.d, g, 1, nout, n2max1, dk(0), ct);
-        GRIDSPT_CHECK(p.xfused(XM_ORDER1, a));
+        XArgs<T> a = make_xargs<T>(p.d, g, 1, nout, lp ? lp->n2max : n2max1, dk(0), ct);
+        a.amp = p.amp();
+        GRIDSPT_CHECK(p.xfused(lp ? XM_LIN_ORDER1 : XM_ORDER1, a));
         T* out[4] = {static_cast<T*>(delta[0]), p.U(1, 0), p.U(1, 1), p.U(1, 2)};
         GRIDSPT_CHECK(p.to_real(nout, out));
         if (theta[0] && theta[0] != delta[0])
@@ -580,9 +600,10 @@ int run_adjoint(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, 
         }
     }
     GRIDSPT_CHECK(fwd(1));
+    GRIDSPT_CHECK(p.amp_table(g, lp));
     XArgs<T> a = make_xargs<T>(p.d, g, 1, 1, lp->n2max, nullptr, nullptr);
     a.nin = nmax == 1 ? 1 : 4;
-    a.lin = {lp->amp, lp->ns, lp->gamma, lp->growth, (double)N * N * N / (g->box * g->box * g->box)};
+    a.amp = p.amp();
     GRIDSPT_CHECK(p.xfused(XM_ADJ1, a));
     T* out[1] = {static_cast<T*>(gnoise)};
     return p.to_real(1, out);
@@ -606,7 +627,8 @@ int run_adjoint(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, 
                                             void*, const gridspt::Tuning&, gridspt::Batch);                        \
     template int gridspt::run_forward<T, N>(gridspt_ctx*, const gridspt_grid*, int64_t, const void*, void*, void*, \
                                             const gridspt::Tuning&, gridspt::Batch);                               \
-    template int gridspt::run_orders<T, N>(gridspt_ctx*, const gridspt_grid*, int, int64_t, int64_t, const void*,  \
+    template int gridspt::run_orders<T, N>(gridspt_ctx*, const gridspt_grid*, const gridspt_linpk*, int, int64_t,  \
+                                           int64_t, const void*,                                                   \
                                            void* const*, void* const*, void* const*, void* const*, void*,          \
                                            const gridspt::Tuning&, gridspt::Batch);                                \
     template int gridspt::run_shells<T, N>(gridspt_ctx*, const gridspt_grid*, int, const void* const*,             \

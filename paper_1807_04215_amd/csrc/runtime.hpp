@@ -214,17 +214,19 @@ inline Dims dims_of(const gridspt_grid* g) {
     return d;
 }
 
-// Workspace of the transform pipeline: twiddles | buffer A (S1, S3) |
-// buffer B (S2, S4) | u_m real fields.  S1/S3 and S2/S4 are never live at once.
+// Workspace of the transform pipeline: twiddles | radial amplitude table
+// ((Kc + 1)^2 doubles) | buffer A (S1, S3) | buffer B (S2, S4) | u_m real
+// fields.  S1/S3 and S2/S4 are never live at once.
 struct Layout {
-    int64_t tw, a, b, u, end;
+    int64_t tw, amp, a, b, u, end;
     int64_t a_field_s1, a_field_s3, b_field_s2, b_field_s4;  // field strides (elements)
 };
 
 inline Layout layout_of(const Dims& d, int nmax) {
     Layout L;
     L.tw = 0;
-    L.a = align_up(d.N * d.cpx_bytes);
+    L.amp = align_up(d.N * d.cpx_bytes);
+    L.a = align_up(L.amp + (d.Kc + 1) * (d.Kc + 1) * 8);
     const int64_t asz = std::max(4 * d.s1(), 5 * d.s3()) * d.cpx_bytes;
     L.b = align_up(L.a + asz);
     const int64_t bsz = std::max(4 * d.s2(), 5 * d.s4()) * d.cpx_bytes;
@@ -260,10 +262,12 @@ int run_linear_field(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk*
 template <typename T, int N>
 int run_forward(gridspt_ctx* c, const gridspt_grid* g, int64_t n2max, const void* field, void* field_k, void* work,
                 const Tuning& tu, Batch b);
+// lp: draw delta_1 from this spectrum and seed (linear field and order 1 in
+// one pass sequence; W1 = lp->n2max, delta1 unused), or null to read delta1
 template <typename T, int N>
-int run_orders(gridspt_ctx* c, const gridspt_grid* g, int nmax, int64_t n2max1, int64_t n2max2, const void* delta1,
-               void* const* delta, void* const* theta, void* const* delta_k, void* const* theta_k, void* work,
-               const Tuning& tu, Batch b);
+int run_orders(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, int nmax, int64_t n2max1,
+               int64_t n2max2, const void* delta1, void* const* delta, void* const* theta, void* const* delta_k,
+               void* const* theta_k, void* work, const Tuning& tu, Batch b);
 // bispectrum slots: shell-filtered C2R of cube fields (null: the indicator)
 // into real fields out[i]; lo/hi the n^2 range of each slot
 template <typename T, int N>

@@ -157,7 +157,8 @@ def test_workspace_sizes_follow_layout():
     b = max(4 * kz * ky * n, 5 * n * n * kz) * 8
     u = 12 * n ** 3 * 4
     got = g.lib().gridspt_workspace_bytes(ctypes.byref(G), 5)
-    assert a + b + u <= got <= a + b + u + 4 * 256 + n * 8
+    amp = (341 + 1) ** 2 * 8          # radial amplitude table
+    assert a + b + u + amp <= got <= a + b + u + amp + 5 * 256 + n * 8
     assert g.lib().gridspt_cube_elems(ctypes.byref(G)) == kz * ky * ky
 
 

@@ -220,3 +220,27 @@ def test_zeldovich_planar_on_gpu(ctx):
     rd, _, _, _ = oracle.orders(d1, box, nmax, cut, cut)
     for i in range(nmax):
         assert rel_l2(out.delta[i].cpu().numpy(), rd[i]) < 1e-12
+
+
+@pytest.mark.parametrize("dtype", [g.F64, g.F32])
+@pytest.mark.parametrize("n,box,nmax,seed", [(32, 200.0, 5, 21), (48, 300.0, 4, 22), (64, 500.0, 3, 23)])
+def test_orders_linear_matches_oracle(ctx, dtype, n, box, nmax, seed):
+    """The seeded linear field and the orders in one pass sequence (no round trip
+    of delta_1 through real space) against the oracle's linear field + orders,
+    and against the two-call GPU path."""
+    cut = g.cut_n2max(n, box)
+    grid = g.Grid(n, box, g.cube_kc(cut), dtype)
+    amp, dz = _amp(), 0.7
+    lp = g.LinearSpectrum(amp=amp, ns=NS, gamma=GAMMA, growth=dz, n2max=cut, seed=seed, stream=4)
+    out = g.orders_linear(ctx, grid, lp, nmax, cut)
+    two = g.orders(ctx, grid, nmax, cut, cut, g.linear_field(ctx, grid, lp))
+    ctx.sync()
+    ref1 = oracle.linear_field(n, box, amp, NS, GAMMA, dz, cut, seed, 4)
+    rd, rt, rdk, rtk = oracle.orders(ref1, box, nmax, cut, cut)
+    for i in range(nmax):
+        assert rel_l2(out.delta[i].cpu().numpy(), rd[i]) < TOL[dtype], i + 1
+        assert rel_l2(out.theta[i].cpu().numpy(), rt[i]) < TOL[dtype], i + 1
+        assert rel_l2(cube_from_tensor(out.delta_k[i]), half_to_cube(rdk[i], grid.kc)) < TOL[dtype], i + 1
+        e = (torch.linalg.vector_norm((out.delta[i] - two.delta[i]).double()) /
+             torch.linalg.vector_norm(two.delta[i].double())).item()
+        assert e < TOL[dtype], (i + 1, e)
