@@ -500,7 +500,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS) + ["c4", "c5", "c6", "c7"])
-    ap.add_argument("--no-tune", action="store_true", help="c4: skip the autotuner")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner of the pass variants")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-spectra", action="store_true", help="skip the spectrum stores and P(k)")
@@ -557,6 +557,8 @@ def main() -> int:
     total = torch.empty((n,) * 3, dtype=torch.float64, device="cuda")
     coef = [1.0] * nmax
 
+    tuning = g.tune_orders(ctx, grid, lp, nmax, cut, out=out) if not args.no_tune else None
+
     def step():
         g.orders_linear(ctx, grid, lp, nmax, cut, out=out)  # linear field + orders 1..nmax
         g.sum_orders(ctx, grid, out.delta, coef, out=total)
@@ -604,7 +606,8 @@ def main() -> int:
         "data": "synthetic (seeded Gaussian linear field, BBKS P0, sigma8=0.8)",
         "config": {"workload": "%s: %s, %s, cut 2/3 k_Nyq%s" % (args.workload, desc, args.dtype,
                                                                  ", 15 P_mn pairs in %d bins" % nbins if spectra else ""),
-                   "n": n, "box": box, "z": z, "nmax": nmax, "kc": grid.kc},
+                   "n": n, "box": box, "z": z, "nmax": nmax, "kc": grid.kc,
+                   "autotuned": ({k: v[0] for k, v in tuning.items()} if tuning else None)},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(dom, args), "launch_ms": round(d["ms"] / d["launches"], 3),

@@ -210,6 +210,22 @@ int gridspt_orders_linear(gridspt_ctx* ctx, const gridspt_grid* g, const gridspt
                           int64_t n2max2, void* const* delta, void* const* theta, void* const* delta_k,
                           void* const* theta_k, void* work, int64_t work_bytes);
 
+/* Autotuner of the transform passes: runs gridspt_orders_linear once per
+ * compiled launch variant of grid g (rows per block, radix split; FP32 grids
+ * of 64..1024 and 96..384 have several) with every pass in that variant,
+ * times each pass kind with HIP events, waits, and keeps the fastest variant
+ * per kind in the context for this grid size and precision.  Later calls of
+ * the context on such grids use it (results equal up to rounding).  Same
+ * arguments as gridspt_orders_linear (the outputs are overwritten).  Returns
+ * the number of variants tried. */
+int gridspt_tune_orders(gridspt_ctx* ctx, const gridspt_grid* g, const gridspt_linpk* lp, int32_t nmax,
+                        int64_t n2max2, void* const* delta, void* const* theta, void* const* delta_k,
+                        void* const* theta_k, void* work, int64_t work_bytes);
+/* The context's choice per tuned pass kind for grid g (variant 0 when not
+ * tuned), with the tuner's time; names as for gridspt_profile_read. */
+int gridspt_tuning(const gridspt_ctx* ctx, const gridspt_grid* g, int32_t max, char* names, int32_t* variant,
+                   double* ms);
+
 /* Final sum of orders (the truncated series of Eq. 8):
  * out(x) = sum_{n=1..nmax} coef[n-1] delta_n(x), accumulated in FP64.
  * delta: host array of nmax device pointers; coef: host array of nmax;

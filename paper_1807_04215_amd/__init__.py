@@ -101,6 +101,8 @@ def lib():
             "gridspt_batch_tuning": ([vp, i32, i32, vp, vp, vp], ctypes.c_int),
             "gridspt_orders_linear": ([vp, gp, ctypes.POINTER(_LinPk), i32, i64, vp, vp, vp, vp, vp, i64],
                                       ctypes.c_int),
+            "gridspt_tune_orders": ([vp, gp, ctypes.POINTER(_LinPk), i32, i64, vp, vp, vp, vp, vp, i64], ctypes.c_int),
+            "gridspt_tuning": ([vp, gp, i32, vp, vp, vp], ctypes.c_int),
             "gridspt_pform_workspace_bytes": ([gp, i32], i64),
             "gridspt_orders_pform": ([vp, gp, i32, i64, i64, vp, vp, vp, vp, vp, vp, i64], ctypes.c_int),
             "gridspt_smooth": ([vp, gp, i32, vp, vp, i32, dbl, vp, vp, i64], ctypes.c_int),
@@ -411,6 +413,29 @@ def orders_linear(ctx: Context, grid: Grid, lp: LinearSpectrum, nmax: int, n2max
     _check(lib().gridspt_orders_linear(ctx.handle, ctypes.byref(g), ctypes.byref(c), nmax, n2max2, d, t, dk, tk,
                                        _ptr(ws), ws.numel()), "orders_linear")
     return out
+
+
+def tune_orders(ctx: Context, grid: Grid, lp: LinearSpectrum, nmax: int, n2max2: int,
+                out: Optional[Orders] = None):
+    """Autotune the pass variants of this grid for the context; returns {kind: (variant, ms)}."""
+    import numpy as np
+    out = out if out is not None else alloc_orders(grid, nmax, True)
+    g = grid.cstruct
+    c = _linpk(lp)
+    ws = ctx.workspace(workspace_bytes(grid, nmax))
+    dk = _ptr_array(out.delta_k) if out.delta_k is not None else None
+    tk = _ptr_array(out.theta_k) if out.theta_k is not None else None
+    _check(lib().gridspt_tune_orders(ctx.handle, ctypes.byref(g), ctypes.byref(c), nmax, n2max2,
+                                     _ptr_array(out.delta), _ptr_array(out.theta), dk, tk, _ptr(ws), ws.numel()),
+           "tune_orders")
+    m = 16
+    names = ctypes.create_string_buffer(32 * m)
+    var = np.zeros(m, dtype=np.int32)
+    ms = np.zeros(m)
+    k = _check(lib().gridspt_tuning(ctx.handle, ctypes.byref(g), m, names, var.ctypes.data, ms.ctypes.data),
+               "tuning")
+    return {names.raw[32 * i: 32 * (i + 1)].split(b"\0", 1)[0].decode(): (int(var[i]), float(ms[i]))
+            for i in range(k)}
 
 
 def orders_pform(ctx: Context, grid: Grid, nmax: int, n2max1: int, n2max2: int, delta1: torch.Tensor,

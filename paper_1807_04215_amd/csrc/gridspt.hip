@@ -474,7 +474,7 @@ int gridspt_linear_field(gridspt_ctx* c, const gridspt_grid* g, const gridspt_li
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
     if (work_bytes < gridspt_workspace_bytes(g, 1)) return GRIDSPT_EWORKSPACE;
-    const Tuning tu{};
+    const Tuning& tu = c->tuning(g);
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
         constexpr int N = decltype(nc)::value;
@@ -493,7 +493,7 @@ int gridspt_noise_field(gridspt_ctx* c, const gridspt_grid* g, const gridspt_lin
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
     if (work_bytes < gridspt_workspace_bytes(g, 1)) return GRIDSPT_EWORKSPACE;
-    const Tuning tu{};
+    const Tuning& tu = c->tuning(g);
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
         constexpr int N = decltype(nc)::value;
@@ -531,7 +531,7 @@ int gridspt_adjoint(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* 
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
     if (work_bytes < gridspt_adjoint_workspace_bytes(g, nmax)) return GRIDSPT_EWORKSPACE;
-    const Tuning tu{};
+    const Tuning& tu = c->tuning(g);
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
         constexpr int N = decltype(nc)::value;
@@ -549,7 +549,7 @@ int gridspt_forward(gridspt_ctx* c, const gridspt_grid* g, int64_t n2max, const 
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
     if (work_bytes < gridspt_workspace_bytes(g, 1)) return GRIDSPT_EWORKSPACE;
-    const Tuning tu{};
+    const Tuning& tu = c->tuning(g);
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
         constexpr int N = decltype(nc)::value;
@@ -577,7 +577,7 @@ int gridspt_orders(gridspt_ctx* c, const gridspt_grid* g, int32_t nmax, int64_t 
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
     if (work_bytes < gridspt_workspace_bytes(g, nmax)) return GRIDSPT_EWORKSPACE;
-    const Tuning tu{};
+    const Tuning& tu = c->tuning(g);
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
         constexpr int N = decltype(nc)::value;
@@ -605,13 +605,108 @@ int gridspt_orders_linear(gridspt_ctx* c, const gridspt_grid* g, const gridspt_l
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
     if (work_bytes < gridspt_workspace_bytes(g, nmax)) return GRIDSPT_EWORKSPACE;
-    const Tuning tu{};
+    const Tuning& tu = c->tuning(g);
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
         constexpr int N = decltype(nc)::value;
         return run_orders<T, N>(c, g, lp, nmax, lp->n2max, n2max2, nullptr, delta, theta, delta_k, theta_k, work, tu,
                                 Batch{});
     });
+}
+
+// The pass kinds the autotuner times, and one timed trial of the seeded
+// orders with every kind in variant v.
+static const int kOrderKinds[] = {KD_ZFWD_NOISE, KD_ZFWD_PRODUCTS, KD_YFWD, KD_XFUSED_LINEAR, KD_XFUSED_ORDER,
+                                  KD_YINV, KD_ZINV};
+
+int gridspt_tune_orders(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, int32_t nmax, int64_t n2max2,
+                        void* const* delta, void* const* theta, void* const* delta_k, void* const* theta_k,
+                        void* work, int64_t work_bytes) {
+    if (!c || !lp) return GRIDSPT_EINVAL;
+    CHECK(check_grid(g));
+    if (nmax < 1 || nmax > 5) return GRIDSPT_EINVAL;
+    CHECK(check_linpk(g, lp));
+    if (nmax > 1) CHECK(check_mask(g, n2max2));
+    if (!delta || !theta) return GRIDSPT_EINVAL;
+    for (int i = 0; i < nmax; ++i) {
+        CHECK(check_ptr(delta[i]));
+        if (i > 0) CHECK(check_ptr(theta[i]));
+        else if (theta[0]) CHECK(check_ptr(theta[0]));
+        if (delta_k && delta_k[i]) CHECK(check_ptr(delta_k[i]));
+        if (theta_k && theta_k[i]) CHECK(check_ptr(theta_k[i]));
+    }
+    if (!work) return GRIDSPT_EWORKSPACE;
+    CHECK(check_ptr(work));
+    if (work_bytes < gridspt_workspace_bytes(g, nmax)) return GRIDSPT_EWORKSPACE;
+    int vl[8];
+    const int nv = variant_list(g->dtype, g->n, vl);
+    gridspt_ctx::Tuned best{g->n, g->dtype, Tuning{}, {}};
+    for (int k = 0; k < KD_COUNT; ++k) best.ms[k] = 1e300;
+    auto trial = [&](int v, bool keep) -> int {
+        gridspt_ctx t;
+        t.stream = c->stream;
+        t.profile = true;
+        Tuning tu;
+        for (int k = 0; k < KD_COUNT; ++k) tu.v[k] = v;
+        const int rc = dispatch(g, [&](auto tag, auto nc) -> int {
+            using T = typename decltype(tag)::type;
+            constexpr int N = decltype(nc)::value;
+            return run_orders<T, N>(&t, g, lp, nmax, lp->n2max, n2max2, nullptr, delta, theta, delta_k, theta_k, work,
+                                    tu, Batch{});
+        });
+        double ms[KD_COUNT] = {};
+        const bool synced = hipStreamSynchronize(t.stream) == hipSuccess;
+        for (auto& r : t.recs) {
+            float x = 0.f;
+            if (synced && rc == GRIDSPT_OK && hipEventElapsedTime(&x, r.start, r.stop) == hipSuccess) ms[r.kind] += x;
+            (void)hipEventDestroy(r.start);
+            (void)hipEventDestroy(r.stop);
+        }
+        for (auto e : t.pool) (void)hipEventDestroy(e);
+        if (!synced) return GRIDSPT_EHIP;
+        if (rc != GRIDSPT_OK) return rc;
+        if (keep)
+            for (int k : kOrderKinds)
+                if (ms[k] > 0.0 && ms[k] < best.ms[k]) {
+                    best.ms[k] = ms[k];
+                    best.tu.v[k] = v;
+                }
+        return GRIDSPT_OK;
+    };
+    CHECK(trial(0, false));  // warm-up
+    for (int i = 0; i < nv; ++i) CHECK(trial(vl[i], true));
+    for (int k = 0; k < KD_COUNT; ++k)
+        if (best.ms[k] >= 1e300) best.ms[k] = 0.0;
+    // the same variant for the other uses of a pass kind
+    best.tu.v[KD_ZFWD_FIELD] = best.tu.v[KD_ZFWD_NOISE];
+    best.tu.v[KD_XFUSED_ORDER1] = best.tu.v[KD_XFUSED_LINEAR];
+    for (auto& t : c->tuned)
+        if (t.n == g->n && t.dtype == g->dtype) {
+            t = best;
+            return nv;
+        }
+    c->tuned.push_back(best);
+    return nv;
+}
+
+int gridspt_tuning(const gridspt_ctx* c, const gridspt_grid* g, int32_t max, char* names, int32_t* variant,
+                   double* ms) {
+    if (!c || !g || max < 0) return GRIDSPT_EINVAL;
+    const gridspt_ctx::Tuned* t = nullptr;
+    for (const auto& x : c->tuned)
+        if (x.n == g->n && x.dtype == g->dtype) t = &x;
+    int k = 0;
+    for (int kind : kOrderKinds) {
+        if (k >= max) break;
+        if (names) {
+            std::memset(names + 32 * k, 0, 32);
+            std::strncpy(names + 32 * k, kKindNames[kind], 31);
+        }
+        if (variant) variant[k] = t ? t->tu.v[kind] : 0;
+        if (ms) ms[k] = t ? t->ms[kind] : 0.0;
+        ++k;
+    }
+    return k;
 }
 
 int64_t gridspt_pform_workspace_bytes(const gridspt_grid* g, int32_t nmax) {
@@ -642,7 +737,7 @@ int gridspt_orders_pform(gridspt_ctx* c, const gridspt_grid* g, int32_t nmax, in
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
     if (work_bytes < gridspt_pform_workspace_bytes(g, nmax)) return GRIDSPT_EWORKSPACE;
-    const Tuning tu{};
+    const Tuning& tu = c->tuning(g);
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
         constexpr int N = decltype(nc)::value;
@@ -665,7 +760,7 @@ int gridspt_smooth(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, const
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
     if (work_bytes < gridspt_workspace_bytes(g, 1)) return GRIDSPT_EWORKSPACE;
-    const Tuning tu{};
+    const Tuning& tu = c->tuning(g);
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
         constexpr int N = decltype(nc)::value;
@@ -839,7 +934,7 @@ int gridspt_bispectrum(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, c
     const int64_t pipe = layout_of(d, 1).end;
     if (work_bytes < bisp_layout(d, bp, nterms, ntri, pipe).end) return GRIDSPT_EWORKSPACE;
     return bisp_enqueue(c, g, fields_k, bp, ntri, nterms, terms, edge_n2, bk, ntriangles, work,
-                        static_cast<char*>(work) + pipe, Tuning{}, Batch{});
+                        static_cast<char*>(work) + pipe, c->tuning(g), Batch{});
 }
 
 }  // extern "C"

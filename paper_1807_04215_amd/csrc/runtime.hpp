@@ -70,10 +70,12 @@ struct Tuning {
 };
 
 // Variants compiled per (precision, size), for the autotuner: FP32 grids of
-// 64..256 (power of two) get rows-per-block halvings and the radix-4 split
+// 64..1024 (power of two) get rows-per-block halvings and the radix-4 split
 // (variants 0, 1, 4, 5), FP32 grids of 96..384 (3 * 2^a) halvings (0, 1, 2),
 // everything else only variant 0.
-constexpr bool tuned_pow2(bool f32, int n) { return f32 && (n == 64 || n == 128 || n == 256); }
+constexpr bool tuned_pow2(bool f32, int n) {
+    return f32 && (n == 64 || n == 128 || n == 256 || n == 512 || n == 1024);
+}
 constexpr bool tuned_three(bool f32, int n) { return f32 && (n == 96 || n == 192 || n == 384); }
 inline int variant_list(int dtype, int n, int* out) {
     const bool f32 = dtype == GRIDSPT_F32;
@@ -97,10 +99,22 @@ struct gridspt_ctx {
         hipEvent_t start, stop;
         double bytes;
     };
+    struct Tuned {
+        int n, dtype;
+        gridspt::Tuning tu;
+        double ms[gridspt::KD_COUNT];
+    };
     hipStream_t stream = nullptr;
     bool profile = false;
     std::vector<Record> recs;
     std::vector<hipEvent_t> pool;
+    std::vector<Tuned> tuned;  // autotuner choices per grid (size, precision)
+    const gridspt::Tuning& tuning(const gridspt_grid* g) const {
+        static const gridspt::Tuning none{};
+        for (const auto& t : tuned)
+            if (t.n == g->n && t.dtype == g->dtype) return t.tu;
+        return none;
+    }
 };
 
 namespace gridspt {

@@ -244,3 +244,24 @@ def test_orders_linear_matches_oracle(ctx, dtype, n, box, nmax, seed):
         e = (torch.linalg.vector_norm((out.delta[i] - two.delta[i]).double()) /
              torch.linalg.vector_norm(two.delta[i].double())).item()
         assert e < TOL[dtype], (i + 1, e)
+
+
+def test_tuned_context_matches_untuned():
+    """After gridspt_tune_orders the context runs each pass in the fastest
+    compiled variant; the fields equal the untuned ones to FP32 tolerance."""
+    n, box, nmax = 128, 500.0, 4
+    cut = g.cut_n2max(n, box)
+    grid = g.Grid(n, box, g.cube_kc(cut), g.F32)
+    lp = g.LinearSpectrum(amp=_amp(), ns=NS, gamma=GAMMA, n2max=cut, seed=31)
+    plain = g.Context()
+    tuned = g.Context()
+    tu = g.tune_orders(tuned, grid, lp, nmax, cut)
+    print("tuning 128^3:", tu, flush=True)
+    assert tu and all(v in (0, 1, 4, 5) for v, _ in tu.values())
+    a = g.orders_linear(plain, grid, lp, nmax, cut)
+    b = g.orders_linear(tuned, grid, lp, nmax, cut)
+    torch.cuda.synchronize()
+    for i in range(nmax):
+        e = (torch.linalg.vector_norm((a.delta[i] - b.delta[i]).double()) /
+             torch.linalg.vector_norm(a.delta[i].double())).item()
+        assert e < 2e-6, (i + 1, e)
