@@ -46,22 +46,83 @@ template <typename T>
 struct PowerArgs {
     const cpx<T>* f[kMaxFields];  // distinct fields used by this launch
     int pa[kPowerPairsPerLaunch], pb[kPowerPairsPerLaunch];  // indices into f
-    int64_t edges[kMaxBins + 1];
+    const int* bins;  // bin of every |n|^2 < n2lim (k_power_bins), -1 outside the bins
+    int64_t n2lim;
     int nf, npairs, nbins;
     double kF;
     double* partial;  // [gridDim.x][nbins][npairs + 2]
 };
 
+// Bin of every integer |n|^2 below n2lim: b with edges[b] <= n2 < edges[b + 1], else -1.
+struct BinEdges {
+    int64_t e[kMaxBins + 1];
+    int nbins;
+};
+static __global__ void k_power_bins(BinEdges be, int* bins, int64_t n2lim) {
+    const int64_t n2 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n2 >= n2lim) return;
+    int bin = -1;
+    if (n2 >= be.e[0] && n2 < be.e[be.nbins]) {
+        int lo = 0, hi = be.nbins;  // e[lo] <= n2 < e[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (n2 >= be.e[mid]) lo = mid;
+            else hi = mid;
+        }
+        bin = lo;
+    }
+    bins[n2] = bin;
+}
+
 constexpr int kPowerWaves = 4;
 
-template <typename T>
+// Lane moves of the segmented scan, as DPP modifiers (VALU, no LDS traffic):
+// row shift right by S within rows of 16 lanes, lane 15 of a row to the next
+// row (rows 1 and 3), lane 31 to the upper half (rows 2 and 3).  Lanes
+// without a source, or outside the row mask, keep `old`.
+constexpr int kDppRowShr = 0x110, kDppBcast15 = 0x142, kDppBcast31 = 0x143;
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_int(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWMASK, 0xf, false);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_dbl(double old, double v) {
+    const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)x, CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(x >> 32), CTRL, ROWMASK, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
+// One step of the segmented inclusive scan: lane i adds the value of its
+// DPP source lane when that lane holds the same bin.  Bins are monotone along
+// the 64 lanes, so equal bins at the two ends mean the whole stretch between
+// them is one run.
+template <int CTRL, int ROWMASK, int NQ>
+__device__ __forceinline__ void seg_scan_step(int bin, double (&v)[NQ], int npairs, int qp) {
+    const int ob = dpp_int<CTRL, ROWMASK>(-2, bin);
+    const bool same = ob == bin;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        if (q < npairs || q >= qp) {
+            const double o = dpp_dbl<CTRL, ROWMASK>(0.0, v[q]);
+            if (same) v[q] += o;
+        }
+    }
+}
+
+// Row-major index of the pair (i, j), i <= j, among all pairs of TRI fields.
+__host__ __device__ constexpr int tri_index(int i, int j, int tri) { return i * tri - i * (i - 1) / 2 + (j - i); }
+
+// TRI = 0: the npairs requested pairs (pa[q], pb[q]).  TRI = 1..5: every pair
+// i <= j of the TRI fields (a.npairs = TRI (TRI + 1) / 2), each field loaded
+// once per mode; the requested pairs are picked out by k_power_final.
+template <typename T, int TRI>
 __global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T> a, CubeDims cd, size_t zs) {
     constexpr int QP = kPowerPairsPerLaunch;
     extern __shared__ double acc[];  // [kPowerWaves][nbins][Q]
-    __shared__ int64_t edges[kMaxBins + 1];
     const int Q = a.npairs + 2;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    for (int i = threadIdx.x; i <= a.nbins; i += blockDim.x) edges[i] = a.edges[i];
     for (int i = threadIdx.x; i < kPowerWaves * a.nbins * Q; i += blockDim.x) acc[i] = 0.0;
     __syncthreads();
     double* my = acc + (size_t)wave * a.nbins * Q;
@@ -83,42 +144,45 @@ __global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T>
             if (kxc < c_end) {
                 const int kx = kxc <= cd.Kc ? kxc : kxc - Kx;
                 n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
-                if (n2 >= edges[0] && n2 < edges[a.nbins]) {
-                    int lo = 0, hi = a.nbins;  // edges[lo] <= n2 < edges[hi]
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (n2 >= edges[mid]) lo = mid;
-                        else hi = mid;
-                    }
-                    bin = lo;
-                }
+                if (n2 < a.n2lim) bin = a.bins[n2];
             }
             if (!__any(bin >= 0)) continue;
-            // per-mode quantities (repeated fields of different pairs hit the cache)
+            // per-mode quantities
             double v[QP + 2];
 #pragma unroll
-            for (int q = 0; q < QP; ++q) {
-                v[q] = 0.0;
-                if (q < a.npairs && bin >= 0) {
-                    const cpx<T> x = zptr(a.f[a.pa[q]], zs)[base + kxc], y = zptr(a.f[a.pb[q]], zs)[base + kxc];
-                    v[q] = w * ((double)x.x * (double)y.x + (double)x.y * (double)y.y);
+            for (int q = 0; q < QP; ++q) v[q] = 0.0;
+            if constexpr (TRI > 0) {
+                double re[TRI], im[TRI];
+#pragma unroll
+                for (int i = 0; i < TRI; ++i) {
+                    const cpx<T> x = bin >= 0 ? zptr(a.f[i], zs)[base + kxc] : cpx<T>{(T)0, (T)0};
+                    re[i] = (double)x.x;
+                    im[i] = (double)x.y;
+                }
+#pragma unroll
+                for (int i = 0; i < TRI; ++i)
+#pragma unroll
+                    for (int j = i; j < TRI; ++j) v[tri_index(i, j, TRI)] = w * (re[i] * re[j] + im[i] * im[j]);
+            } else {
+                // repeated fields of different pairs hit the cache
+#pragma unroll
+                for (int q = 0; q < QP; ++q) {
+                    if (q < a.npairs && bin >= 0) {
+                        const cpx<T> x = zptr(a.f[a.pa[q]], zs)[base + kxc], y = zptr(a.f[a.pb[q]], zs)[base + kxc];
+                        v[q] = w * ((double)x.x * (double)y.x + (double)x.y * (double)y.y);
+                    }
                 }
             }
             v[QP] = bin >= 0 ? w : 0.0;
             v[QP + 1] = bin >= 0 ? w * a.kF * sqrt((double)n2) : 0.0;
-            // segmented inclusive scan over runs of equal bin
-#pragma unroll
-            for (int s = 1; s < 64; s <<= 1) {
-                const int ob = __shfl_up(bin, s, 64);
-                const bool same = lane >= s && ob == bin;
-#pragma unroll
-                for (int q = 0; q < QP + 2; ++q) {
-                    if (q < a.npairs || q >= QP) {
-                        const double o = __shfl_up(v[q], s, 64);
-                        if (same) v[q] += o;
-                    }
-                }
-            }
+            // segmented inclusive scan over runs of equal bin: shifts 1, 2, 4, 8
+            // within rows of 16 lanes, then the row-15 and row-31 broadcasts
+            seg_scan_step<kDppRowShr + 1, 0xf>(bin, v, a.npairs, QP);
+            seg_scan_step<kDppRowShr + 2, 0xf>(bin, v, a.npairs, QP);
+            seg_scan_step<kDppRowShr + 4, 0xf>(bin, v, a.npairs, QP);
+            seg_scan_step<kDppRowShr + 8, 0xf>(bin, v, a.npairs, QP);
+            seg_scan_step<kDppBcast15, 0xa>(bin, v, a.npairs, QP);
+            seg_scan_step<kDppBcast31, 0xc>(bin, v, a.npairs, QP);
             const int nb = __shfl_down(bin, 1, 64);
             const bool last = lane == 63 || nb != bin;
             if (last && bin >= 0) {
@@ -160,20 +224,25 @@ static __global__ __launch_bounds__(kReduceThreads) void k_power_reduce(const do
     if (threadIdx.x == 0) sums[item] = red[0];
 }
 
-// P = L^3 S / sum w, kmean = sum w |k| / sum w, nmodes = sum w.
-static __global__ void k_power_final(const double* sums, int nbins, int npairs, double vol, double* pk, int pk_stride,
-                              double* kmean, double* nmodes, size_t zs) {
+// P = L^3 S / sum w, kmean = sum w |k| / sum w, nmodes = sum w; output pair p
+// is column col[p] of the sums [bin][nq] (the last two columns are sum w and
+// sum w |k|).
+struct PairCols {
+    int col[kPowerPairsPerLaunch];
+};
+static __global__ void k_power_final(const double* sums, int nbins, int nq, int npairs, PairCols pc, double vol,
+                                     double* pk, int pk_stride, double* kmean, double* nmodes, size_t zs) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     sums = zptr(sums, zs);
     pk = zptr(pk, zs);
     kmean = zptr(kmean, zs);
     nmodes = zptr(nmodes, zs);
     if (b >= nbins) return;
-    const int Q = npairs + 2;
-    const double cnt = sums[(size_t)b * Q + npairs], ks = sums[(size_t)b * Q + npairs + 1];
+    const double cnt = sums[(size_t)b * nq + nq - 2], ks = sums[(size_t)b * nq + nq - 1];
     if (nmodes) nmodes[b] = cnt;
     if (kmean) kmean[b] = cnt > 0.0 ? ks / cnt : 0.0;
-    for (int p = 0; p < npairs; ++p) pk[(size_t)p * pk_stride + b] = cnt > 0.0 ? vol * sums[(size_t)b * Q + p] / cnt : 0.0;
+    for (int p = 0; p < npairs; ++p)
+        pk[(size_t)p * pk_stride + b] = cnt > 0.0 ? vol * sums[(size_t)b * nq + pc.col[p]] / cnt : 0.0;
 }
 
 // ---------------------------------------------------------------------------

@@ -31,8 +31,9 @@ int power_blocks(const Dims& d) {
 }
 int64_t power_ws(const Dims& d, int npairs, int nbins) {
     const int q = std::min(npairs, power_chunk(nbins)) + 2;
-    // block partials, then the reduced sums
-    return align_up((int64_t)power_blocks(d) * nbins * q * 8) + align_up((int64_t)nbins * q * 8);
+    // block partials, the reduced sums, the bin of every |n|^2 inside the cube
+    return align_up((int64_t)power_blocks(d) * nbins * q * 8) + align_up((int64_t)nbins * q * 8) +
+           align_up((d.Kc + 1) * (d.Kc + 1) * 3 * 4);
 }
 
 int check_power_args(int nfields, int npairs, const int32_t* pairs, int nbins, const int64_t* edge_n2) {
@@ -57,8 +58,19 @@ int power_enqueue(gridspt_ctx* c, const gridspt_grid* g, const void* const* fiel
     auto go = [&](auto tag) -> int {
         using T = typename decltype(tag)::type;
         double* partial = static_cast<double*>(work);
-        double* sums = reinterpret_cast<double*>(static_cast<char*>(work) +
-                                                 align_up((int64_t)nblk * nbins * (std::min(npairs, chunk) + 2) * 8));
+        const int64_t part_bytes = align_up((int64_t)nblk * nbins * (std::min(npairs, chunk) + 2) * 8);
+        double* sums = reinterpret_cast<double*>(static_cast<char*>(work) + part_bytes);
+        int* bins = reinterpret_cast<int*>(static_cast<char*>(work) + part_bytes +
+                                           align_up((int64_t)nbins * (std::min(npairs, chunk) + 2) * 8));
+        // every mode of the cube has |n|^2 <= 3 Kc^2 < 3 (Kc + 1)^2
+        const int64_t n2lim = std::min<int64_t>(edge_n2[nbins], 3 * (d.Kc + 1) * (d.Kc + 1));
+        {
+            BinEdges be{};
+            for (int b = 0; b <= nbins; ++b) be.e[b] = edge_n2[b];
+            be.nbins = nbins;
+            CHECK(launch(c, KD_POWER_FINAL, (double)n2lim * 4.0, dim3((unsigned)((n2lim + 255) / 256)), dim3(256), 0,
+                         k_power_bins, be, bins, n2lim));
+        }
         for (int p0 = 0; p0 < npairs; p0 += chunk) {
             const int np = std::min(chunk, npairs - p0);
             PowerArgs<T> a{};
@@ -74,26 +86,45 @@ int power_enqueue(gridspt_ctx* c, const gridspt_grid* g, const void* const* fiel
                         a.f[nf++] = static_cast<const cpx<T>*>(fields_k[f]);
                     }
                 }
+            PairCols pc{};
             for (int q = 0; q < np; ++q) {
                 a.pa[q] = slot_of[pairs[2 * (p0 + q)]];
                 a.pb[q] = slot_of[pairs[2 * (p0 + q) + 1]];
+                pc.col[q] = q;
             }
-            for (int b = 0; b <= nbins; ++b) a.edges[b] = edge_n2[b];
+            // all pairs of up to five fields: each field loaded once per mode
+            const int tri = nf <= 5 && nf * (nf + 1) / 2 <= chunk ? nf : 0;
+            int nacc = np;  // accumulated products per mode
+            if (tri) {
+                nacc = tri * (tri + 1) / 2;
+                for (int q = 0; q < np; ++q)
+                    pc.col[q] = tri_index(std::min(a.pa[q], a.pb[q]), std::max(a.pa[q], a.pb[q]), tri);
+            }
+            a.bins = bins;
+            a.n2lim = n2lim;
             a.nf = nf;
-            a.npairs = np;
+            a.npairs = nacc;
             a.nbins = nbins;
             a.kF = 2.0 * M_PI / g->box;
             a.partial = partial;
-            const int nq = np + 2;
+            const int nq = nacc + 2;
             const size_t shm = (size_t)kPowerWaves * nbins * nq * sizeof(double);
-            CHECK(launch(c, KD_POWER, (double)nz * nf * d.cube() * d.cpx_bytes, dim3(nblk, 1, nz),
-                         dim3(64 * kPowerWaves), shm, k_power_partial<T>, a,
-                         CubeDims{(int)d.Kc, (int)d.Kz, (int)d.Ky}, bt.zs));
+            const CubeDims cdims{(int)d.Kc, (int)d.Kz, (int)d.Ky};
+            const dim3 pgrid(nblk, 1, nz), pblock(64 * kPowerWaves);
+            const double pbytes = (double)nz * nf * d.cube() * d.cpx_bytes;
+            switch (tri) {
+                case 1: CHECK(launch(c, KD_POWER, pbytes, pgrid, pblock, shm, k_power_partial<T, 1>, a, cdims, bt.zs)); break;
+                case 2: CHECK(launch(c, KD_POWER, pbytes, pgrid, pblock, shm, k_power_partial<T, 2>, a, cdims, bt.zs)); break;
+                case 3: CHECK(launch(c, KD_POWER, pbytes, pgrid, pblock, shm, k_power_partial<T, 3>, a, cdims, bt.zs)); break;
+                case 4: CHECK(launch(c, KD_POWER, pbytes, pgrid, pblock, shm, k_power_partial<T, 4>, a, cdims, bt.zs)); break;
+                case 5: CHECK(launch(c, KD_POWER, pbytes, pgrid, pblock, shm, k_power_partial<T, 5>, a, cdims, bt.zs)); break;
+                default: CHECK(launch(c, KD_POWER, pbytes, pgrid, pblock, shm, k_power_partial<T, 0>, a, cdims, bt.zs));
+            }
             CHECK(launch(c, KD_POWER_FINAL, (double)nz * nblk * nbins * nq * 8.0, dim3(nbins * nq, 1, nz),
                          dim3(kReduceThreads), 0, k_power_reduce, (const double*)partial, nblk, nq, sums, bt.zs));
             CHECK(launch(c, KD_POWER_FINAL, 0.0, dim3((nbins + 63) / 64, 1, nz), dim3(64), 0, k_power_final,
-                         (const double*)sums, nbins, np, g->box * g->box * g->box, pk + (size_t)p0 * nbins, nbins,
-                         p0 == 0 ? kmean : nullptr, p0 == 0 ? nmodes : nullptr, bt.zs));
+                         (const double*)sums, nbins, nq, np, pc, g->box * g->box * g->box, pk + (size_t)p0 * nbins,
+                         nbins, p0 == 0 ? kmean : nullptr, p0 == 0 ? nmodes : nullptr, bt.zs));
         }
         return GRIDSPT_OK;
     };
