@@ -325,11 +325,13 @@ static __global__ __launch_bounds__(kReduceThreads) void k_triple_final(const do
 struct TriMap {
     int tri[64];
 };
+// jzs: realisation stride of jsum (0 when the triangle counts are shared)
 static __global__ void k_bisp_final(const double* tsum, const double* jsum, TriMap m, int u0, int nu, int nt,
-                             double vol2, double invN3, double* bk, double* ntriangles, size_t zs) {
+                                    double vol2, double invN3, double* bk, double* ntriangles, size_t zs,
+                                    size_t jzs) {
     const int i = threadIdx.x;
     tsum = zptr(tsum, zs);
-    jsum = zptr(jsum, zs);
+    jsum = zptr(jsum, jzs);
     bk = zptr(bk, zs);
     ntriangles = zptr(ntriangles, zs);
     if (i < nu) {

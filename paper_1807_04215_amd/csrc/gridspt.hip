@@ -169,8 +169,10 @@ int check_bisp_args(int nfields, int ntri, const int32_t* tri_bins, int nterms, 
     return GRIDSPT_OK;
 }
 
-// terms and triangles are assumed validated
-BispPlan bisp_make_plan(int ntri, const int32_t* tri_bins, int nterms, const int32_t* terms, int cap) {
+// terms and triangles are assumed validated; with_terms / with_j select the
+// term sums and the triangle counts (indicator slots) the plan makes
+BispPlan bisp_make_plan(int ntri, const int32_t* tri_bins, int nterms, const int32_t* terms, int cap,
+                        bool with_terms = true, bool with_j = true) {
     std::vector<std::vector<int>> terms_of(ntri);
     for (int u = 0; u < nterms; ++u) terms_of[terms[4 * u + 3]].push_back(u);
     BispPlan bp;
@@ -183,7 +185,8 @@ BispPlan bisp_make_plan(int ntri, const int32_t* tri_bins, int nterms, const int
         for (auto& kv : index) ch.slots[kv.second] = kv.first;
         for (int t : tris) {
             const int* b = tri_bins + 3 * t;
-            ch.jitems.push_back({index[{-1, b[0]}], index[{-1, b[1]}], index[{-1, b[2]}], t});
+            if (with_j) ch.jitems.push_back({index[{-1, b[0]}], index[{-1, b[1]}], index[{-1, b[2]}], t});
+            if (with_terms)
             for (int u : terms_of[t]) {
                 const int* f = terms + 4 * u;
                 ch.titems.push_back({index[{f[0], b[0]}], index[{f[1], b[1]}], index[{f[2], b[2]}], u});
@@ -197,9 +200,12 @@ BispPlan bisp_make_plan(int ntri, const int32_t* tri_bins, int nterms, const int
     for (int t = 0; t < ntri; ++t) {
         std::set<std::pair<int, int>> need;
         const int* b = tri_bins + 3 * t;
-        for (int i = 0; i < 3; ++i) need.insert({-1, b[i]});
-        for (int u : terms_of[t])
-            for (int i = 0; i < 3; ++i) need.insert({terms[4 * u + i], b[i]});
+        if (with_j)
+            for (int i = 0; i < 3; ++i) need.insert({-1, b[i]});
+        if (with_terms)
+            for (int u : terms_of[t])
+                for (int i = 0; i < 3; ++i) need.insert({terms[4 * u + i], b[i]});
+        if (need.empty()) continue;
         int fresh = 0;
         for (auto& k : need) fresh += index.count(k) ? 0 : 1;
         if (!tris.empty() && (int)index.size() + fresh > cap) flush();
@@ -230,9 +236,12 @@ BispLayout bisp_layout(const Dims& d, const BispPlan& bp, int nterms, int ntri, 
 
 // pipe: a pipeline workspace (layout_of(d, 1) or larger); scratch: the
 // estimator's own region (bisp_layout from 0)
+// final: also form bk and ntriangles from the sums; jzs: byte stride of the
+// triangle counts between realisations (0: realisation 0's, made once)
 int bisp_enqueue(gridspt_ctx* c, const gridspt_grid* g, const void* const* fields_k, const BispPlan& bp, int ntri,
                  int nterms, const int32_t* terms, const int64_t* edge_n2, double* bk, double* ntriangles, void* pipe,
-                 void* scratch, const Tuning& tu, Batch bt) {
+                 void* scratch, const Tuning& tu, Batch bt, bool final = true, size_t jzs = SIZE_MAX) {
+    if (jzs == SIZE_MAX) jzs = bt.zs;
     const Dims d = dims_of(g);
     const BispLayout bl = bisp_layout(d, bp, nterms, ntri, 0);
     char* base = static_cast<char*>(scratch);
@@ -285,6 +294,7 @@ int bisp_enqueue(gridspt_ctx* c, const gridspt_grid* g, const void* const* field
         CHECK(triple(ch.titems, sums));
         CHECK(triple(ch.jitems, sums + nterms));
     }
+    if (!final) return GRIDSPT_OK;
     // bk = L^6 T / J per term, the term -> triangle map in the argument buffer
     const double vol2 = std::pow(g->box, 6);
     const double invN3 = 1.0 / (double)d.ncell();
@@ -294,7 +304,7 @@ int bisp_enqueue(gridspt_ctx* c, const gridspt_grid* g, const void* const* field
         const int nt = std::max(0, std::min(64, ntri - u0));
         for (int i = 0; i < nu; ++i) m.tri[i] = terms[4 * (u0 + i) + 3];
         CHECK(launch(c, KD_BISP_FINAL, 0.0, dim3(1, 1, nz), dim3(64), 0, k_bisp_final, (const double*)sums,
-                     (const double*)(sums + nterms), m, u0, nu, nt, vol2, invN3, bk, ntriangles, bt.zs));
+                     (const double*)(sums + nterms), m, u0, nu, nt, vol2, invN3, bk, ntriangles, bt.zs, jzs));
     }
     return GRIDSPT_OK;
 }
@@ -986,7 +996,7 @@ struct GroupPlan {
     std::vector<int64_t> edges;
     gridspt_batch_out out;
     Dims d;
-    BispPlan bp;
+    BispPlan bp, bpj;  // bispectrum term sums; triangle counts
     // offsets inside one realisation's arena
     int64_t o_pipe, o_delta, o_theta, o_cube, o_pws, o_pk, o_kmean, o_nmodes, o_bws, o_bk, o_ntri, zs;
     int64_t base;  // offset of realisation 0's arena in work
@@ -1051,7 +1061,13 @@ int make_group(const gridspt_batch_group& src, GroupPlan& p) {
     p.g.tri_bins = p.tri_bins.empty() ? nullptr : p.tri_bins.data();
     p.g.terms = p.terms.empty() ? nullptr : p.terms.data();
     p.d = dims_of(&p.g.grid);
-    if (src.ntri > 0) p.bp = bisp_make_plan(src.ntri, p.g.tri_bins, src.nterms, p.g.terms, kBatchSlotCap);
+    if (src.ntri > 0) {
+        // term sums in every launch of the batch; triangle counts once, at plan creation
+        p.bp = bisp_make_plan(src.ntri, p.g.tri_bins, src.nterms, p.g.terms, kBatchSlotCap, true, false);
+        p.bpj = bisp_make_plan(src.ntri, p.g.tri_bins, src.nterms, p.g.terms, kBatchSlotCap, false, true);
+        // one scratch layout for both plans: the counts must stay where the term pass reads them
+        p.bp.max_slots = p.bpj.max_slots = std::max(p.bp.max_slots, p.bpj.max_slots);
+    }
     return GRIDSPT_OK;
 }
 
@@ -1114,7 +1130,7 @@ int enqueue_group(gridspt_ctx* c, gridspt_batch* b, GroupPlan& p, const Tuning& 
         double* nt = reinterpret_cast<double*>(arena(b, p, p.o_ntri));
         if (stats) {
             CHECK(bisp_enqueue(c, gr, cube, p.bp, g.ntri, g.nterms, g.terms, g.edge_n2, bk, nt, work,
-                               arena(b, p, p.o_bws), tu, bt));
+                               arena(b, p, p.o_bws), tu, bt, true, 0));
             CHECK(launch(c, KD_BATCH_STATS, 0.0, dim3((g.nterms + 63) / 64), dim3(64), 0, k_batch_stats,
                          (const double*)bk, g.nreal, g.nterms, (size_t)p.zs, p.out.bk_mean, p.out.bk_std));
             CHECK(launch(c, KD_BATCH_STATS, 0.0, dim3((g.ntri + 63) / 64), dim3(64), 0, k_batch_stats,
@@ -1184,6 +1200,15 @@ int tune_group(gridspt_batch* b, GroupPlan& p) {
             }
     }
     return GRIDSPT_OK;
+}
+
+// The triangle counts N_123 of a group's bispectrum depend only on the grid
+// and the bins: made once, in realisation 0's sums, before any launch of the batch.
+int setup_triangles(gridspt_batch* b, GroupPlan& p) {
+    if (p.g.ntri == 0) return GRIDSPT_OK;
+    const void* none[1] = {nullptr};  // indicator slots read no spectrum
+    return bisp_enqueue(b->ctx, &p.g.grid, none, p.bpj, p.g.ntri, p.g.nterms, p.g.terms, p.g.edge_n2, nullptr,
+                        nullptr, arena(b, p, p.o_pipe), arena(b, p, p.o_bws), p.tu, Batch{1, 0}, false, 0);
 }
 
 void release(gridspt_batch* b) {
@@ -1285,6 +1310,8 @@ int gridspt_batch_create(gridspt_ctx* c, int32_t ngroups, const gridspt_batch_gr
     if (flags & GRIDSPT_BATCH_TUNE)
         for (auto& p : b->groups)
             if (rc == GRIDSPT_OK) rc = tune_group(b, p);
+    for (auto& p : b->groups)
+        if (rc == GRIDSPT_OK) rc = setup_triangles(b, p);
     if (rc == GRIDSPT_OK && !(flags & GRIDSPT_BATCH_EAGER)) rc = capture(b);
     if (rc != GRIDSPT_OK) {
         release(b);

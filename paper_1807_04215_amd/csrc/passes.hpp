@@ -635,6 +635,8 @@ struct ShellSlots {
     int64_t lo[8], hi[8];
     cpx<T>* s3;
     size_t s3_field;
+    CubeDims src;  // layout of the cubes (the launch's CubeDims may be a smaller cube
+                   // holding every shell of the launch)
 };
 
 template <typename T, int N, int V>
@@ -659,7 +661,9 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xshell(ShellSlots<
     const int ky = active ? (kyc <= cd.Kc ? kyc : kyc - cd.Ky) : 0;
     const int slot = blockIdx.y;
     const cpx<T>* cube = zptr(a.cube[slot], zs);
-    const size_t cbase = ((size_t)kz * cd.Ky + ky0) * cd.Ky;
+    // this row in the source cube: the same signed (ky, kz), source compact indices
+    const int kys = ky >= 0 ? ky : ky + a.src.Ky;
+    const size_t cbase = ((size_t)kz * a.src.Ky + kys) * a.src.Ky;
     cpx<T>* row = lds + r * ROWE;
     cpx<T> v[E];
 #pragma unroll
@@ -670,7 +674,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xshell(ShellSlots<
         const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
         const bool in = active && ic >= 0 && n2 >= a.lo[slot] && n2 < a.hi[slot];
         cpx<T> c = {(T)0, (T)0};
-        if (in) c = cube ? cube[cbase + (size_t)r * cd.Ky + ic] : cpx<T>{(T)1, (T)0};
+        if (in) c = cube ? cube[cbase + (kx >= 0 ? kx : kx + a.src.Ky)] : cpx<T>{(T)1, (T)0};
         v[e] = c;
     }
     x_inverse_store<T, N, V>(v, lds, row, tws, l,

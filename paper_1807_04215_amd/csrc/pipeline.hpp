@@ -244,8 +244,10 @@ struct Pipe {
             using RW = Rows<T, N, V>;
             int ncube = 0;
             for (int i = 0; i < nslot; ++i) ncube += s.cube[i] ? 1 : 0;
-            const double bytes = nb() * ((double)ncube * d.cube() + (double)nslot * d.s3()) * d.cpx_bytes;
-            return launch(c, KD_XSHELL, bytes, dim3((unsigned)(d.Kz * ((d.Ky + RW::RPB - 1) / RW::RPB)), nslot, nz()),
+            // cd may be smaller than the cube of s.src (shells of small radius)
+            const double rows = (double)cd.Kz * cd.Ky;
+            const double bytes = nb() * ((double)ncube * rows * cd.Ky + (double)nslot * rows * N) * d.cpx_bytes;
+            return launch(c, KD_XSHELL, bytes, dim3((unsigned)(cd.Kz * ((cd.Ky + RW::RPB - 1) / RW::RPB)), nslot, nz()),
                           dim3(RW::THREADS), 0, k_xshell<T, N, V>, s, (const cpx<T>*)tw(), cd, bt.zs);
         });
     }
@@ -255,8 +257,8 @@ struct Pipe {
         return with_variant<T, N>(tu.v[KD_YINV], [&](auto vc) {
             constexpr int V = decltype(vc)::value;
             using RW = Rows<T, N, V>;
-            const double bytes = nb() * nf * (d.s3() + d.s4()) * d.cpx_bytes;
-            return launch(c, KD_YINV, bytes, dim3((unsigned)(N * ((d.Kz + RW::RPB - 1) / RW::RPB)), nf, nz()),
+            const double bytes = nb() * nf * ((double)cd.Kz * N * cd.Ky + (double)N * N * cd.Kz) * d.cpx_bytes;
+            return launch(c, KD_YINV, bytes, dim3((unsigned)(N * ((cd.Kz + RW::RPB - 1) / RW::RPB)), nf, nz()),
                           dim3(RW::THREADS), 0, k_yinv<T, N, V>, (const cpx<T>*)A(), (size_t)L.a_field_s3, B(),
                           (size_t)L.b_field_s4, (const cpx<T>*)tw(), cd, bt.zs);
         });
@@ -270,7 +272,7 @@ struct Pipe {
             int nout = 0;
             for (int i = 0; i < njobs; ++i) nout += zj.fb[i] >= 0 ? 2 : 1;
             const double bytes =
-                nb() * nout * ((double)d.s4() * d.cpx_bytes + (double)d.ncell() * d.real_bytes);
+                nb() * nout * ((double)N * N * cd.Kz * d.cpx_bytes + (double)d.ncell() * d.real_bytes);
             return launch(c, KD_ZINV, bytes, dim3((unsigned)(N * N / RW::RPB), njobs, nz()), dim3(RW::THREADS), 0,
                           k_zinv<T, N, V>, (const cpx<T>*)B(), (size_t)L.b_field_s4, zj, (const cpx<T>*)tw(), cd,
                           bt.zs);
@@ -392,25 +394,38 @@ int run_orders(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, i
 }
 
 // Shell-filtered inverse transforms of the bispectrum estimator, five slots
-// per pass sequence
+// per pass sequence.  Slots go in order of their outer radius, and each
+// group of five is transformed on the smallest cube holding its shells
+// (Kc = floor(sqrt(largest n^2 in them))), so inner shells cost less.
 template <typename T, int N>
 int run_shells(gridspt_ctx* c, const gridspt_grid* g, int nslots, const void* const* cubes, const int64_t* lo,
                const int64_t* hi, void* const* out, void* work, const Tuning& tu, Batch b) {
     Pipe<T, N> p(c, g, work, 1, tu, b);
     GRIDSPT_CHECK(p.twiddles());
+    const CubeDims full = p.cd;
+    std::vector<int> order(nslots);
+    for (int i = 0; i < nslots; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return hi[x] < hi[y]; });
     for (int s0 = 0; s0 < nslots; s0 += 5) {
         const int nb = std::min(5, nslots - s0);
         ShellSlots<T> sh{};
+        sh.src = full;
         T* outs[5];
+        int64_t top = 1;
         for (int i = 0; i < nb; ++i) {
-            sh.cube[i] = static_cast<const cpx<T>*>(cubes[s0 + i]);
-            sh.lo[i] = lo[s0 + i];
-            sh.hi[i] = hi[s0 + i];
-            outs[i] = static_cast<T*>(out[s0 + i]);
+            const int k = order[s0 + i];
+            sh.cube[i] = static_cast<const cpx<T>*>(cubes[k]);
+            sh.lo[i] = lo[k];
+            sh.hi[i] = hi[k];
+            outs[i] = static_cast<T*>(out[k]);
+            top = std::max(top, hi[k] - 1);
         }
+        const int kc = (int)std::min<int64_t>(std::max<int64_t>(isqrt64(top), 1), full.Kc);
+        p.cd = {kc, kc + 1, 2 * kc + 1};
         GRIDSPT_CHECK(p.xshell(sh, nb));
         GRIDSPT_CHECK(p.to_real(nb, outs));
     }
+    p.cd = full;
     return GRIDSPT_OK;
 }
 
