@@ -323,7 +323,8 @@ static __global__ __launch_bounds__(kReduceThreads) void k_triple_final(const do
 // bk = L^6 T / J for terms u0 .. u0+nu-1 (both sums over x of the same grid, so
 // the N^-3 cancels); ntriangles = N^-3 J for triangles u0 .. u0+nt-1.
 struct TriMap {
-    int tri[64];
+    int tri[64];  // triangle of term u0 + i
+    int rep[64];  // the term whose sum term u0 + i takes
 };
 // jzs: realisation stride of jsum (0 when the triangle counts are shared)
 static __global__ void k_bisp_final(const double* tsum, const double* jsum, TriMap m, int u0, int nu, int nt,
@@ -336,7 +337,7 @@ static __global__ void k_bisp_final(const double* tsum, const double* jsum, TriM
     ntriangles = zptr(ntriangles, zs);
     if (i < nu) {
         const double j = jsum[m.tri[i]];
-        bk[u0 + i] = j != 0.0 ? vol2 * tsum[u0 + i] / j : 0.0;
+        bk[u0 + i] = j != 0.0 ? vol2 * tsum[m.rep[i]] / j : 0.0;
     }
     if (i < nt) ntriangles[u0 + i] = jsum[u0 + i] * invN3;
 }

@@ -146,6 +146,7 @@ struct BispChunk {
 struct BispPlan {
     std::vector<BispChunk> chunks;
     int max_slots = 0;
+    std::vector<int> rep;  // term -> the term whose sum it takes (same factors in another order)
 };
 
 constexpr int kTripleBlocks = 1024;
@@ -173,9 +174,25 @@ int check_bisp_args(int nfields, int ntri, const int32_t* tri_bins, int nterms, 
 // term sums and the triangle counts (indicator slots) the plan makes
 BispPlan bisp_make_plan(int ntri, const int32_t* tri_bins, int nterms, const int32_t* terms, int cap,
                         bool with_terms = true, bool with_j = true) {
-    std::vector<std::vector<int>> terms_of(ntri);
-    for (int u = 0; u < nterms; ++u) terms_of[terms[4 * u + 3]].push_back(u);
     BispPlan bp;
+    // a triple sum does not depend on the order of its three (field, shell)
+    // factors: terms with the same factors share one sum
+    bp.rep.resize(nterms);
+    {
+        std::map<std::array<std::pair<int, int>, 3>, int> seen;
+        for (int u = 0; u < nterms; ++u) {
+            const int* b = tri_bins + 3 * terms[4 * u + 3];
+            std::array<std::pair<int, int>, 3> key = {std::make_pair(terms[4 * u], b[0]),
+                                                      std::make_pair(terms[4 * u + 1], b[1]),
+                                                      std::make_pair(terms[4 * u + 2], b[2])};
+            std::sort(key.begin(), key.end());
+            auto it = seen.find(key);
+            bp.rep[u] = it == seen.end() ? (seen[key] = u) : it->second;
+        }
+    }
+    std::vector<std::vector<int>> terms_of(ntri);
+    for (int u = 0; u < nterms; ++u)
+        if (bp.rep[u] == u) terms_of[terms[4 * u + 3]].push_back(u);
     std::map<std::pair<int, int>, int> index;
     std::vector<int> tris;
     auto flush = [&]() {
@@ -302,7 +319,10 @@ int bisp_enqueue(gridspt_ctx* c, const gridspt_grid* g, const void* const* field
         TriMap m{};
         const int nu = std::max(0, std::min(64, nterms - u0));
         const int nt = std::max(0, std::min(64, ntri - u0));
-        for (int i = 0; i < nu; ++i) m.tri[i] = terms[4 * (u0 + i) + 3];
+        for (int i = 0; i < nu; ++i) {
+            m.tri[i] = terms[4 * (u0 + i) + 3];
+            m.rep[i] = bp.rep[u0 + i];
+        }
         CHECK(launch(c, KD_BISP_FINAL, 0.0, dim3(1, 1, nz), dim3(64), 0, k_bisp_final, (const double*)sums,
                      (const double*)(sums + nterms), m, u0, nu, nt, vol2, invN3, bk, ntriangles, bt.zs, jzs));
     }
