@@ -6,7 +6,7 @@ One step = the whole path on one synthetic realisation:
   -> FP64 sum of orders -> 15 delta-delta cross spectra P_mn(k) in 64 bins.
 Default workload: 1024^3 cells, L = 2000 Mpc/h, z = 0, FP32.
 
-Prints one JSON line (see the design doc for the fields).  `value` is cells per
+Prints one JSON line.  `value` is cells per
 second to 5th order with inputs resident in HBM; `roofline` is measured for
 the kernel that takes the most time, with HIP events on the library's stream
 over the timed steps; `cpu_baseline` times the FP64 CPU oracle on a bounded
@@ -512,8 +512,8 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (got --gpus %d); multi-GPU sharding is "
-              "described in DESIGN.md but not implemented" % args.gpus, file=sys.stderr)
+        print("bench.py: the library runs on exactly one GPU (got --gpus %d); sharding a grid over "
+              "several GPUs is not implemented" % args.gpus, file=sys.stderr)
         return 2
 
     import torch

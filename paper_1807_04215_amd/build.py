@@ -24,7 +24,7 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    # packed FP32 instructions stay off ("toolchain")
+    # packed FP32 instructions stay off: some of their forms have given wrong results
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
 ]
