@@ -137,44 +137,66 @@ __global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T>
         const double w = kz == 0 ? 1.0 : 2.0;
         const size_t base = (size_t)rowi * Kx;
         const int c_begin = half ? cd.Kc + 1 : 0, c_end = half ? Kx : cd.Kc + 1;
-        for (int c0 = c_begin; c0 < c_end; c0 += 64) {
+        // The raw loads of a chunk of 64 modes: unconditional (clamped to a valid mode of the
+        // row), so no branch waits on a load; U chunks are loaded before the first is used.
+        struct Chunk {
+            int bin;
+            int64_t n2;
+            cpx<T> x[TRI > 0 ? TRI : 2 * QP];
+        };
+        auto load = [&](int c0, Chunk& ch) {
             const int kxc = c0 + lane;
-            int bin = -1;
-            int64_t n2 = 0;
-            if (kxc < c_end) {
-                const int kx = kxc <= cd.Kc ? kxc : kxc - Kx;
-                n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
-                if (n2 < a.n2lim) bin = a.bins[n2];
-            }
-            if (!__any(bin >= 0)) continue;
-            // per-mode quantities
-            double v[QP + 2];
-#pragma unroll
-            for (int q = 0; q < QP; ++q) v[q] = 0.0;
+            const bool valid = kxc < c_end;
+            const int kx = kxc <= cd.Kc ? kxc : kxc - Kx;
+            ch.n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
+            const bool inb = valid && ch.n2 < a.n2lim;
+            const int b = a.bins[inb ? ch.n2 : 0];
+            ch.bin = inb ? b : -1;
+            const size_t at = base + (valid ? kxc : c_begin);
             if constexpr (TRI > 0) {
-                double re[TRI], im[TRI];
 #pragma unroll
-                for (int i = 0; i < TRI; ++i) {
-                    const cpx<T> x = bin >= 0 ? zptr(a.f[i], zs)[base + kxc] : cpx<T>{(T)0, (T)0};
-                    re[i] = (double)x.x;
-                    im[i] = (double)x.y;
-                }
-#pragma unroll
-                for (int i = 0; i < TRI; ++i)
-#pragma unroll
-                    for (int j = i; j < TRI; ++j) v[tri_index(i, j, TRI)] = w * (re[i] * re[j] + im[i] * im[j]);
+                for (int i = 0; i < TRI; ++i) ch.x[i] = zptr(a.f[i], zs)[at];
             } else {
                 // repeated fields of different pairs hit the cache
 #pragma unroll
                 for (int q = 0; q < QP; ++q) {
-                    if (q < a.npairs && bin >= 0) {
-                        const cpx<T> x = zptr(a.f[a.pa[q]], zs)[base + kxc], y = zptr(a.f[a.pb[q]], zs)[base + kxc];
-                        v[q] = w * ((double)x.x * (double)y.x + (double)x.y * (double)y.y);
+                    if (q < a.npairs) {  // uniform
+                        ch.x[2 * q] = zptr(a.f[a.pa[q]], zs)[at];
+                        ch.x[2 * q + 1] = zptr(a.f[a.pb[q]], zs)[at];
                     }
                 }
             }
-            v[QP] = bin >= 0 ? w : 0.0;
-            v[QP + 1] = bin >= 0 ? w * a.kF * sqrt((double)n2) : 0.0;
+        };
+        auto accumulate = [&](const Chunk& ch) {
+            const int bin = ch.bin;
+            if (!__any(bin >= 0)) return;
+            // per-mode quantities (zero off the bins)
+            double v[QP + 2];
+#pragma unroll
+            for (int q = 0; q < QP; ++q) v[q] = 0.0;
+            const double wb = bin >= 0 ? w : 0.0;
+            if constexpr (TRI > 0) {
+                double re[TRI], im[TRI];
+#pragma unroll
+                for (int i = 0; i < TRI; ++i) {
+                    re[i] = (double)ch.x[i].x;
+                    im[i] = (double)ch.x[i].y;
+                }
+#pragma unroll
+                for (int i = 0; i < TRI; ++i)
+#pragma unroll
+                    for (int j = i; j < TRI; ++j) v[tri_index(i, j, TRI)] = wb * (re[i] * re[j] + im[i] * im[j]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < QP; ++q) {
+                    if (q < a.npairs) {
+                        const cpx<T> x = ch.x[2 * q], y = ch.x[2 * q + 1];
+                        v[q] = wb * ((double)x.x * (double)y.x + (double)x.y * (double)y.y);
+                    }
+                }
+            }
+            v[QP] = wb;
+            v[QP + 1] = bin >= 0 ? w * a.kF * sqrt((double)ch.n2) : 0.0;
             // segmented inclusive scan over runs of equal bin: shifts 1, 2, 4, 8
             // within rows of 16 lanes, then the row-15 and row-31 broadcasts
             seg_scan_step<kDppRowShr + 1, 0xf>(bin, v, a.npairs, QP);
@@ -193,6 +215,14 @@ __global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T>
                 dst[a.npairs] += v[QP];
                 dst[a.npairs + 1] += v[QP + 1];
             }
+        };
+        constexpr int U = TRI > 0 ? 2 : 1;  // the pair path holds two loads per pair already
+        for (int c0 = c_begin; c0 < c_end; c0 += 64 * U) {
+            Chunk ch[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) load(c0 + 64 * u, ch[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) accumulate(ch[u]);
         }
     }
     __syncthreads();
@@ -261,29 +291,48 @@ struct TripleArgs {
 
 constexpr int kTripleThreads = 256;
 
-template <typename T>
+// NT terms (the launch's nterms).  A thread takes 16 bytes of consecutive cells
+// of every factor per step, all 3 NT loads before the first product, so the
+// loads of a step are in flight together; the factors are 16-byte aligned and
+// ncell is a multiple of the vector width (checked by the caller).
+template <typename T, int NT>
 __global__ __launch_bounds__(kTripleThreads) void k_triple_partial(TripleArgs<T> t, size_t zs) {
     __shared__ double red[kTripleThreads];
-    const T* pa[8];
-    const T* pb[8];
-    const T* pc[8];
+    constexpr int VW = 16 / (int)sizeof(T);
+    using Vec = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    const Vec* pa[NT];
+    const Vec* pb[NT];
+    const Vec* pc[NT];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        pa[u] = u < t.nterms ? zptr(t.a[u], zs) : nullptr;
-        pb[u] = u < t.nterms ? zptr(t.b[u], zs) : nullptr;
-        pc[u] = u < t.nterms ? zptr(t.c[u], zs) : nullptr;
+    for (int u = 0; u < NT; ++u) {
+        pa[u] = reinterpret_cast<const Vec*>(zptr(t.a[u], zs));
+        pb[u] = reinterpret_cast<const Vec*>(zptr(t.b[u], zs));
+        pc[u] = reinterpret_cast<const Vec*>(zptr(t.c[u], zs));
     }
     double* partial = zptr(t.partial, zs);
-    double s[8];
+    double s[NT];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s[u] = 0.0;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < t.ncell; i += stride) {
+    for (int u = 0; u < NT; ++u) s[u] = 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x, nvec = t.ncell / VW;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride) {
+        Vec va[NT], vb[NT], vc[NT];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (u < t.nterms) s[u] += (double)pa[u][i] * (double)pb[u][i] * (double)pc[u][i];
+        for (int u = 0; u < NT; ++u) {
+            va[u] = pa[u][i];
+            vb[u] = pb[u][i];
+            vc[u] = pc[u][i];
+        }
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            const T* x = reinterpret_cast<const T*>(&va[u]);
+            const T* y = reinterpret_cast<const T*>(&vb[u]);
+            const T* z = reinterpret_cast<const T*>(&vc[u]);
+#pragma unroll
+            for (int k = 0; k < VW; ++k) s[u] += (double)x[k] * (double)y[k] * (double)z[k];
+        }
     }
-    for (int u = 0; u < t.nterms; ++u) {
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
         red[threadIdx.x] = s[u];
         __syncthreads();
         for (int h = kTripleThreads / 2; h > 0; h >>= 1) {
@@ -489,7 +538,9 @@ __host__ __device__ constexpr int pair_index(int i, int j) {  // i < j < 8
     return i * kStatsMaxFields - i * (i + 1) / 2 + (j - i - 1);
 }
 
-template <typename T>
+// NF = a.nf fields, a template argument so that every load of a cell is
+// unconditional and all of them are in flight together.
+template <typename T, int NF>
 __global__ __launch_bounds__(kStatsThreads) void k_moments_partial(MomentArgs<T> a) {
     __shared__ double red[kStatsQ * (kStatsThreads / 64)];
     double s[kStatsMaxFields][4], x[kStatsQ - 4 * kStatsMaxFields];
@@ -501,18 +552,18 @@ __global__ __launch_bounds__(kStatsThreads) void k_moments_partial(MomentArgs<T>
     for (int i = 0; i < kStatsQ - 4 * kStatsMaxFields; ++i) x[i] = 0.0;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell; c += stride) {
-        double v[kStatsMaxFields];
+        double v[NF];
 #pragma unroll
-        for (int i = 0; i < kStatsMaxFields; ++i) v[i] = i < a.nf ? (double)a.f[i][c] : 0.0;
+        for (int i = 0; i < NF; ++i) v[i] = (double)a.f[i][c];
 #pragma unroll
-        for (int i = 0; i < kStatsMaxFields; ++i) {
+        for (int i = 0; i < NF; ++i) {
             const double p2 = v[i] * v[i];
             s[i][0] += v[i];
             s[i][1] += p2;
             s[i][2] += p2 * v[i];
             s[i][3] += p2 * p2;
 #pragma unroll
-            for (int j = i + 1; j < kStatsMaxFields; ++j) x[pair_index(i, j)] += v[i] * v[j];
+            for (int j = i + 1; j < NF; ++j) x[pair_index(i, j)] += v[i] * v[j];
         }
     }
     // per item: butterfly sum within each wavefront (fixed order), then the

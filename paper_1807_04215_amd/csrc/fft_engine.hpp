@@ -54,11 +54,11 @@ __device__ __forceinline__ void keep_here(cpx<T>& v) {
 
 // Compile-time loop.
 template <typename F, int... Ks>
-__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Ks...>) {
+__host__ __device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Ks...>) {
     (f(std::integral_constant<int, Ks>{}), ...);
 }
 template <int Count, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
+__host__ __device__ __forceinline__ void static_for(F&& f) {
     static_for_impl(f, std::make_integer_sequence<int, Count>{});
 }
 

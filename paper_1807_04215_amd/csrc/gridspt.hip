@@ -297,8 +297,21 @@ int bisp_enqueue(gridspt_ctx* c, const gridspt_grid* g, const void* const* field
                         t.c[i] = static_cast<const T*>(outs[items[u0 + i][2]]);
                         td.idx[i] = items[u0 + i][3];
                     }
-                    CHECK(launch(c, KD_TRIPLE, (double)nz * 3.0 * t.nterms * d.ncell() * d.real_bytes,
-                                 dim3(kTripleBlocks, 1, nz), dim3(kTripleThreads), 0, k_triple_partial<T>, t, bt.zs));
+                    // the kernel reads 16-byte vectors of cells
+                    bool aligned = bt.zs % 16 == 0 && t.ncell % (16 / sizeof(T)) == 0;
+                    for (int i = 0; i < t.nterms; ++i)
+                        for (const T* q : {t.a[i], t.b[i], t.c[i]})
+                            aligned = aligned && reinterpret_cast<uintptr_t>(q) % 16 == 0;
+                    if (!aligned) return GRIDSPT_EALIGN;
+                    int rc = GRIDSPT_OK;
+                    static_for<8>([&](auto k) {
+                        constexpr int NT = decltype(k)::value + 1;
+                        if (NT == t.nterms)
+                            rc = launch(c, KD_TRIPLE, (double)nz * 3.0 * NT * d.ncell() * d.real_bytes,
+                                        dim3(kTripleBlocks, 1, nz), dim3(kTripleThreads), 0,
+                                        k_triple_partial<T, NT>, t, bt.zs);
+                    });
+                    CHECK(rc);
                     CHECK(launch(c, KD_TRIPLE_FINAL, (double)nz * kTripleBlocks * 8.0 * 8.0, dim3(1, 1, nz),
                                  dim3(kReduceThreads), 0, k_triple_final, (const double*)partial, kTripleBlocks,
                                  t.nterms, td, dst, bt.zs));
@@ -926,8 +939,14 @@ int gridspt_field_stats(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, 
             a.nf = nfields;
             a.ncell = ncell;
             a.partial = mpart;
-            CHECK(launch(c, KD_MOMENTS, (double)nfields * ncell * d.real_bytes, dim3(kMomentBlocks),
-                         dim3(kStatsThreads), 0, k_moments_partial<T>, a));
+            int rc = GRIDSPT_OK;
+            static_for<kStatsMaxFields>([&](auto k) {
+                constexpr int NF = decltype(k)::value + 1;
+                if (NF == nfields)
+                    rc = launch(c, KD_MOMENTS, (double)nfields * ncell * d.real_bytes, dim3(kMomentBlocks),
+                                dim3(kStatsThreads), 0, k_moments_partial<T, NF>, a);
+            });
+            CHECK(rc);
             CHECK(launch(c, KD_MOMENTS, (double)kMomentBlocks * kStatsQ * 8, dim3(kStatsQ), dim3(kReduceThreads), 0,
                          k_power_reduce, (const double*)mpart, kMomentBlocks, kStatsQ, msum, (size_t)0));
             CHECK(launch(c, KD_MOMENTS, 0.0, dim3(1), dim3(64), 0, k_moments_final, (const double*)msum, nfields,

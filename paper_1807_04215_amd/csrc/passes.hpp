@@ -104,9 +104,10 @@ __device__ __forceinline__ void group_gaussians(uint64_t seed, uint64_t stream, 
         const double u1 = ((double)(w[2 * p] >> 11) + 0.5) * 0x1p-53;
         const double u2 = ((double)(w[2 * p + 1] >> 11) + 0.5) * 0x1p-53;
         const double rad = sqrt(-2.0 * log(u1));
-        const double ang = 6.28318530717958647692528676655900577 * u2;
-        g[2 * p] = rad * cos(ang);
-        g[2 * p + 1] = rad * sin(ang);
+        double sn, cs;
+        sincospi(2.0 * u2, &sn, &cs);  // the angle 2 pi u2, without a general range reduction
+        g[2 * p] = rad * cs;
+        g[2 * p + 1] = rad * sn;
     }
 }
 
@@ -192,6 +193,15 @@ __device__ __forceinline__ cpx<T> unpack_real_pair(cpx<T> c, cpx<T> m, int which
 // SRC 4: two real fields pin.d[0..1] (the printed sources S_delta, S_theta),
 //   packed as d0 + i d1; a block covers RPB consecutive y.
 // --------------------------------------------------------------------------
+// base[idx] where ok, zero elsewhere, with no branch around the load: the caller passes
+// an index that names a valid element also where ok is false, so every lane loads and
+// all loads of a row are in flight together (a branch per element would wait for each).
+template <typename T>
+__device__ __forceinline__ cpx<T> load_or_zero(const cpx<T>* base, size_t idx, bool ok) {
+    const cpx<T> t = base[idx];
+    return ok ? t : cpx<T>{(T)0, (T)0};
+}
+
 template <typename T>
 struct ProductInputs {
     const T* d[4];     // delta_1 .. delta_{n-1}
@@ -428,8 +438,9 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
     using PL = typename RW::PL;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
     __shared__ cpx<T> lds[RPB * ROWE];
-    // twiddles from the cache: this pass's LDS is busy with exchanges and staging
-    constexpr bool LT = kLdsTwiddles<T> && false;
+    // FP32 twiddles in LDS: a global-table read at every pass would leave its latency
+    // exposed at this pass's low occupancy
+    constexpr bool LT = kLdsTwiddles<T> && true;
     __shared__ cpx<T> twl[LT ? PL::TW_ALLOC : 1];
     if constexpr (LT) load_twiddles<PL, T>(twl, tw);
     __syncthreads();
@@ -455,14 +466,51 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
     constexpr int NIN = (MODE == XM_ORDER || ADJ) ? 4 : (MODE == XM_PFORM ? 2 : 1);
 #pragma unroll
     for (int e = 0; e < E; ++e) sd[e] = st[e] = {(T)0, (T)0};
+    // |n|^2 <= 3 (N/2)^2 and every mask lies below (N/2)^2: 32-bit integers are exact here
+    const T kF = (T)a.kF, invN3 = (T)a.invN3;
+    const int n2lim = (int)(a.n2max < INT32_MAX ? a.n2max : INT32_MAX);
+    // the radial amplitudes are gathered before the transform, so their latency hides behind it
+    constexpr bool AMP = MODE == XM_LINEAR || MODE == XM_LIN_ORDER1 || MODE == XM_ADJ1;
+    T ampv[AMP ? E : 1];
+    if constexpr (AMP) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int kx = signed_pos(l + P * e, N);
+            const int n2 = kx * kx + ky * ky + kz * kz;
+            const T t = (T)a.amp[n2 <= n2lim ? n2 : 0];  // unconditional: no branch around the load
+            ampv[e] = n2 <= n2lim ? t : (T)0;
+        }
+    }
+    // Input rows: unconditional loads (a row past the cube reads row 0 of the block, which
+    // exists, and is zeroed after), and field f + 1 is loaded before field f is transformed,
+    // so its latency hides behind that transform (not in the reverse mode, whose k-space
+    // accumulation leaves no registers for it).
+    const uint32_t rin = (uint32_t)((active ? r : 0) * N + l);
+    auto load_field = [&](int f, cpx<T>(&dst)[E]) {
+        const cpx<T>* in = a.s2 + (size_t)f * a.s2_field + inbase;
+#pragma unroll
+        for (int e = 0; e < E; ++e) dst[e] = load_or_zero(in, rin + (uint32_t)(P * e), active);
+    };
+    cpx<T> cur[E];
+    load_field(0, cur);
     static_for<NIN>([&](auto fc) {
         constexpr int f = decltype(fc)::value;
         if (ADJ && f >= a.nin) return;
+        constexpr bool PREFETCH = !ADJ && f + 1 < NIN;
+        cpx<T> nxt[PREFETCH ? E : 1];
+        if constexpr (PREFETCH) load_field(f + 1, nxt);
         cpx<T> v[E];
-        const cpx<T>* in = a.s2 + (size_t)f * a.s2_field + inbase;
+        if constexpr (ADJ && f > 0) {
+            load_field(f, v);
+        } else {
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = active ? ldo(in, (uint32_t)(r * N + l + P * e)) : cpx<T>{(T)0, (T)0};
+            for (int e = 0; e < E; ++e) v[e] = cur[e];
+        }
         fft_row<PL, -1, T>(v, row, tws, l);
+        if constexpr (PREFETCH) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) cur[e] = nxt[e];
+        }
         if constexpr (MODE == XM_ORDER) {
             if constexpr (f < 3) {
                 // S_delta += i k_f V_f(k)  (kF and N^-3 applied below)
@@ -499,9 +547,9 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const int kx = signed_pos(l + P * e, N);
-                    const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
+                    const int n2 = kx * kx + ky * ky + kz * kz;
                     const int kf = f == 1 ? kx : (f == 2 ? ky : kz);
-                    const T s = n2 > 0 ? (T)((double)kf / (a.kF * (double)n2)) : (T)0;
+                    const T s = n2 > 0 ? (T)kf / (kF * (T)n2) : (T)0;
                     st[e] = cadd(st[e], cpx<T>{-v[e].y * s, v[e].x * s});
                 }
             }
@@ -516,12 +564,11 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
         }
     });
 
-    const T kF = (T)a.kF, invN3 = (T)a.invN3;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int kx = signed_pos(l + P * e, N);
-        const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
-        const bool keep = active && n2 > 0 && n2 <= a.n2max;
+        const int n2 = kx * kx + ky * ky + kz * kz;
+        const bool keep = active && n2 > 0 && n2 <= n2lim;
         if constexpr (MODE == XM_ORDER || MODE == XM_PFORM) {
             // D-form: S_delta = i k.V(k) N^-3, S_theta = -(k^2/2) W(k) N^-3 (divergence form of
             // Eq. 10); P-form: the transforms of the printed sources, times N^-3
@@ -535,8 +582,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
             sd[e] = keep ? dn : cpx<T>{(T)0, (T)0};
             st[e] = keep ? tn : cpx<T>{(T)0, (T)0};
         } else if constexpr (MODE == XM_LINEAR || MODE == XM_LIN_ORDER1) {
-            const T s = keep ? (T)a.amp[n2] : (T)0;
-            sd[e] = cscale(sd[e], s);
+            sd[e] = cscale(sd[e], keep ? ampv[e] : (T)0);
         } else if constexpr (MODE == XM_ADJ) {
             // (a, b) = W2 c_n M^T (G_delta, G_theta), M = [[n + 1/2, 1], [3/2, n]]
             const T cn = (T)(2.0 / ((2.0 * a.n + 3.0) * (a.n - 1.0)));
@@ -548,8 +594,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
             st[e] = keep ? bv : cpx<T>{(T)0, (T)0};
         } else if constexpr (MODE == XM_ADJ1) {
             // g w(k) = W1 A(k) (G_delta + G_theta): the transpose of the linear field
-            const T s = keep ? (T)a.amp[n2] : (T)0;
-            sd[e] = cscale(cadd(sd[e], st[e]), s);
+            sd[e] = cscale(cadd(sd[e], st[e]), keep ? ampv[e] : (T)0);
         } else {
             sd[e] = keep ? cscale(sd[e], invN3) : cpx<T>{(T)0, (T)0};
         }
@@ -592,11 +637,11 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
                     for (int e = 0; e < E; ++e) {
                         const int kx = signed_pos(l + P * e, N);
                         if constexpr (o < 3) {
-                            const T kj = (T)(a.kF * (double)(o == 0 ? kx : (o == 1 ? ky : kz)));
+                            const T kj = kF * (T)(o == 0 ? kx : (o == 1 ? ky : kz));
                             v[e] = {sd[e].y * kj, -sd[e].x * kj};
                         } else {
-                            const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
-                            v[e] = cscale(st[e], (T)(-0.5 * a.kF * a.kF * (double)n2));
+                            const int n2 = kx * kx + ky * ky + kz * kz;
+                            v[e] = cscale(st[e], (T)(-0.5) * kF * kF * (T)n2);
                         }
                     }
                 } else if constexpr (MODE == XM_ADJ1) {
@@ -606,15 +651,21 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
 #pragma unroll
                     for (int e = 0; e < E; ++e) v[e] = (o == 0) ? sd[e] : st[e];
                 } else {
-                    // u_j(k) = (-i k_j / k^2) theta(k)
+                    // u_j(k) = (-i k_j / k^2) theta(k).  theta is no longer an output from here on,
+                    // so st becomes theta / (kF n^2) in place before the first component.
                     constexpr int comp = o - FIRST_U;
+                    if constexpr (comp == 0) {
+#pragma unroll
+                        for (int e = 0; e < E; ++e) {
+                            const int kx = signed_pos(l + P * e, N);
+                            const int n2 = kx * kx + ky * ky + kz * kz;
+                            st[e] = cscale(st[e], n2 > 0 ? (T)1 / (kF * (T)n2) : (T)0);
+                        }
+                    }
 #pragma unroll
                     for (int e = 0; e < E; ++e) {
-                        const int kx = signed_pos(l + P * e, N);
-                        const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
-                        const int kj = comp == 0 ? kx : (comp == 1 ? ky : kz);
-                        const T s = n2 > 0 ? (T)((double)kj / (a.kF * (double)n2)) : (T)0;
-                        v[e] = {st[e].y * s, -st[e].x * s};
+                        const T kj = (T)(comp == 0 ? signed_pos(l + P * e, N) : (comp == 1 ? ky : kz));
+                        v[e] = {st[e].y * kj, -st[e].x * kj};
                     }
                 }
                 x_inverse_store<T, N, V>(v, lds, row, tws, l, a.s3 + (size_t)o * a.s3_field + outbase, cd.Ky,
@@ -646,8 +697,9 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xshell(ShellSlots<
     using PL = typename RW::PL;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
     __shared__ cpx<T> lds[RPB * ROWE];
-    // twiddles from the cache: this pass's LDS is busy with exchanges and staging
-    constexpr bool LT = kLdsTwiddles<T> && false;
+    // FP32 twiddles in LDS: a global-table read at every pass would leave its latency
+    // exposed at this pass's low occupancy
+    constexpr bool LT = kLdsTwiddles<T> && true;
     __shared__ cpx<T> twl[LT ? PL::TW_ALLOC : 1];
     if constexpr (LT) load_twiddles<PL, T>(twl, tw);
     __syncthreads();
@@ -666,16 +718,23 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xshell(ShellSlots<
     const size_t cbase = ((size_t)kz * a.src.Ky + kys) * a.src.Ky;
     cpx<T>* row = lds + r * ROWE;
     cpx<T> v[E];
+    bool in[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int p = l + P * e;
-        const int ic = pos_to_compact(p, cd.Kc, N);
         const int kx = signed_pos(p, N);
-        const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
-        const bool in = active && ic >= 0 && n2 >= a.lo[slot] && n2 < a.hi[slot];
-        cpx<T> c = {(T)0, (T)0};
-        if (in) c = cube ? cube[cbase + (kx >= 0 ? kx : kx + a.src.Ky)] : cpx<T>{(T)1, (T)0};
-        v[e] = c;
+        const int64_t n2 = (int64_t)(kx * kx + ky * ky + kz * kz);
+        in[e] = active && pos_to_compact(p, cd.Kc, N) >= 0 && n2 >= a.lo[slot] && n2 < a.hi[slot];
+    }
+    if (cube) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int kx = signed_pos(l + P * e, N);
+            v[e] = load_or_zero(cube, in[e] ? cbase + (kx >= 0 ? kx : kx + a.src.Ky) : 0, in[e]);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = in[e] ? cpx<T>{(T)1, (T)0} : cpx<T>{(T)0, (T)0};
     }
     x_inverse_store<T, N, V>(v, lds, row, tws, l,
                                  zptr(a.s3, zs) + (size_t)slot * a.s3_field + (size_t)kz * N * cd.Ky + ky0, cd.Ky,
@@ -703,7 +762,11 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xregen(RegenArgs<T
     using PL = typename RW::PL;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
     __shared__ cpx<T> lds[RPB * ROWE];
-    const Twiddles<T, PL, false> tws{tw};
+    constexpr bool LT = kLdsTwiddles<T>;  // FP32 twiddles in LDS (see k_xfused)
+    __shared__ cpx<T> twl[LT ? PL::TW_ALLOC : 1];
+    if constexpr (LT) load_twiddles<PL, T>(twl, tw);
+    __syncthreads();
+    const Twiddles<T, PL, LT> tws{LT ? twl : tw};
     const uint32_t groups = (cd.Ky + RPB - 1) / RPB;
     const uint32_t blk = xcd_block(blockIdx.x, cd.Kz * groups);
     const int kz = blk / groups, ky0 = (blk % groups) * RPB;
@@ -725,20 +788,17 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xregen(RegenArgs<T
         for (int e = 0; e < E; ++e) {
             const int p = l + P * e;
             const int ic = pos_to_compact(p, cd.Kc, N);
-            cpx<T> c = {(T)0, (T)0};
-            if (active && ic >= 0) {
-                if constexpr (o == 0) {
-                    c = cdl[cbase + ic];
-                } else {
-                    const int kx = signed_pos(p, N);
-                    const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
-                    const int kj = o == 1 ? kx : (o == 2 ? ky : kz);
-                    const T sc = n2 > 0 ? (T)((double)kj / (a.kF * (double)n2)) : (T)0;
-                    const cpx<T> t = ctl[cbase + ic];
-                    c = {t.y * sc, -t.x * sc};
-                }
+            const bool ok = active && ic >= 0;
+            const cpx<T> t = load_or_zero(o == 0 ? cdl : ctl, ok ? cbase + ic : 0, ok);
+            if constexpr (o == 0) {
+                v[e] = t;
+            } else {
+                const int kx = signed_pos(p, N);
+                const int n2 = kx * kx + ky * ky + kz * kz;
+                const int kj = o == 1 ? kx : (o == 2 ? ky : kz);
+                const T sc = n2 > 0 ? (T)kj / ((T)a.kF * (T)n2) : (T)0;
+                v[e] = {t.y * sc, -t.x * sc};
             }
-            v[e] = c;
         }
         x_inverse_store<T, N, V>(v, lds, row, tws, l, s3 + (size_t)o * a.s3_field + outbase, cd.Ky, nrows);
     });
@@ -759,7 +819,11 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xderived(RegenArgs
     using PL = typename RW::PL;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
     __shared__ cpx<T> lds[RPB * ROWE];
-    const Twiddles<T, PL, false> tws{tw};
+    constexpr bool LT = kLdsTwiddles<T>;  // FP32 twiddles in LDS (see k_xfused)
+    __shared__ cpx<T> twl[LT ? PL::TW_ALLOC : 1];
+    if constexpr (LT) load_twiddles<PL, T>(twl, tw);
+    __syncthreads();
+    const Twiddles<T, PL, LT> tws{LT ? twl : tw};
     const uint32_t groups = (cd.Ky + RPB - 1) / RPB;
     const uint32_t blk = xcd_block(blockIdx.x, cd.Kz * groups);
     const int kz = blk / groups, ky0 = (blk % groups) * RPB;
@@ -782,27 +846,24 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xderived(RegenArgs
         for (int e = 0; e < E; ++e) {
             const int p = l + P * e;
             const int ic = pos_to_compact(p, cd.Kc, N);
-            cpx<T> c = {(T)0, (T)0};
-            if (active && ic >= 0) {
-                const int kx = signed_pos(p, N);
-                auto kc = [&](int axis) { return axis == 0 ? kx : (axis == 1 ? ky : kz); };
-                const int64_t n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
-                const cpx<T> src = fld < 3 ? cdl[cbase + ic] : ctl[cbase + ic];
-                if constexpr (fld < 6) {  // i k_j F
-                    const T kj = (T)(a.kF * (double)kc(fld % 3));
-                    c = {-src.y * kj, src.x * kj};
-                } else if constexpr (fld < 9) {  // (-i k_j / k^2) F
-                    const T sc = n2 > 0 ? (T)((double)kc(fld - 6) / (a.kF * (double)n2)) : (T)0;
-                    c = {src.y * sc, -src.x * sc};
-                } else {  // (k_i k_j / k^2) F
-                    constexpr int q = fld - 9;
-                    constexpr int i = q < 3 ? q : (q < 5 ? 0 : 1);
-                    constexpr int j = q < 3 ? q : (q == 3 ? 1 : 2);
-                    const T sc = n2 > 0 ? (T)((double)kc(i) * (double)kc(j) / (double)n2) : (T)0;
-                    c = cscale(src, sc);
-                }
+            const bool ok = active && ic >= 0;
+            const cpx<T> src = load_or_zero(fld < 3 ? cdl : ctl, ok ? cbase + ic : 0, ok);
+            const int kx = signed_pos(p, N);
+            auto kc = [&](int axis) { return axis == 0 ? kx : (axis == 1 ? ky : kz); };
+            const int n2 = kx * kx + ky * ky + kz * kz;
+            if constexpr (fld < 6) {  // i k_j F
+                const T kj = (T)a.kF * (T)kc(fld % 3);
+                v[e] = {-src.y * kj, src.x * kj};
+            } else if constexpr (fld < 9) {  // (-i k_j / k^2) F
+                const T sc = n2 > 0 ? (T)kc(fld - 6) / ((T)a.kF * (T)n2) : (T)0;
+                v[e] = {src.y * sc, -src.x * sc};
+            } else {  // (k_i k_j / k^2) F
+                constexpr int q = fld - 9;
+                constexpr int i = q < 3 ? q : (q < 5 ? 0 : 1);
+                constexpr int j = q < 3 ? q : (q == 3 ? 1 : 2);
+                const T sc = n2 > 0 ? (T)(kc(i) * kc(j)) / (T)n2 : (T)0;
+                v[e] = cscale(src, sc);
             }
-            v[e] = c;
         }
         x_inverse_store<T, N, V>(v, lds, row, tws, l, s3 + (size_t)o * a.s3_field + outbase, cd.Ky, nrows);
     });
@@ -831,7 +892,11 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xsmooth(SmoothArgs
     using PL = typename RW::PL;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
     __shared__ cpx<T> lds[RPB * ROWE];
-    const Twiddles<T, PL, false> tws{tw};
+    constexpr bool LT = kLdsTwiddles<T>;  // FP32 twiddles in LDS (see k_xfused)
+    __shared__ cpx<T> twl[LT ? PL::TW_ALLOC : 1];
+    if constexpr (LT) load_twiddles<PL, T>(twl, tw);
+    __syncthreads();
+    const Twiddles<T, PL, LT> tws{LT ? twl : tw};
     const uint32_t groups = (cd.Ky + RPB - 1) / RPB;
     const uint32_t blk = xcd_block(blockIdx.x, cd.Kz * groups);
     const int kz = blk / groups, ky0 = (blk % groups) * RPB;
@@ -859,18 +924,26 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xsmooth(SmoothArgs
         if (o >= a.nin) return;
         cpx<T> v[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int ic = pos_to_compact(l + P * e, cd.Kc, N);
-            cpx<T> c = {(T)0, (T)0};
-            if (w[e] != (T)0) {
+        for (int e = 0; e < E; ++e) v[e] = {(T)0, (T)0};
+        // uniform branch on the mode; the loads inside are unconditional (w = 0 off the cube)
+        auto add = [&](int i) {
+            const cpx<T>* cb = zptr(a.cube[i], zs);
+            const T ci = (T)a.coef[i];
 #pragma unroll
-                for (int i = 0; i <= o; ++i)
-                    if (a.cumulative || i == o)
-                        c = cadd(c, cscale(zptr(a.cube[i], zs)[cbase + ic], (T)a.coef[i]));
-                c = cscale(c, w[e]);
+            for (int e = 0; e < E; ++e) {
+                const int ic = pos_to_compact(l + P * e, cd.Kc, N);
+                const bool ok = active && ic >= 0;
+                v[e] = cadd(v[e], cscale(load_or_zero(cb, ok ? cbase + ic : 0, ok), ci));
             }
-            v[e] = c;
+        };
+        if (a.cumulative) {
+#pragma unroll
+            for (int i = 0; i <= o; ++i) add(i);
+        } else {
+            add(o);
         }
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = cscale(v[e], w[e]);
         x_inverse_store<T, N, V>(v, lds, row, tws, l, s3 + (size_t)o * a.s3_field + outbase, cd.Ky, nrows);
     });
 }
@@ -888,8 +961,9 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yinv(const cpx<T>*
     using PL = typename RW::PL;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
     __shared__ T lds[RPB * ROWE];  // real-valued rows (split exchange)
-    // twiddles from the cache: this pass's LDS is busy with exchanges and staging
-    constexpr bool LT = kLdsTwiddles<T> && false;
+    // FP32 twiddles in LDS: a global-table read at every pass would leave its latency
+    // exposed at this pass's low occupancy
+    constexpr bool LT = kLdsTwiddles<T> && true;
     __shared__ cpx<T> twl[LT ? PL::TW_ALLOC : 1];
     if constexpr (LT) load_twiddles<PL, T>(twl, tw);
     __syncthreads();
@@ -957,19 +1031,25 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zinv(const cpx<T>*
     const cpx<T>* B = tworows ? A : s4 + (size_t)zj.fb[job] * s4_field + q0 * cd.Kz;
     const uint32_t ra = (uint32_t)(r * cd.Kz), rb = (uint32_t)((tworows ? r + RPB : r) * cd.Kz);
     T* row = lds + r * ROWE;
+    // Every lane loads (from the stored half, its own position or the mirrored one, a valid
+    // index either way) and selects afterwards: no branch around a load, so all loads of
+    // the row are in flight together.
+    cpx<T> av[E], bv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = l + P * e;
+        const int q = p < cd.Kz ? p : (p > N - cd.Kz ? N - p : 0);
+        av[e] = ldo(A, ra + (uint32_t)q);
+        bv[e] = ldo(B, rb + (uint32_t)q);
+    }
     cpx<T> v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int p = l + P * e;
-        cpx<T> c = {(T)0, (T)0};
-        if (p < cd.Kz) {
-            const cpx<T> av = ldo(A, ra + (uint32_t)p), bv = ldo(B, rb + (uint32_t)p);
-            c = {av.x - bv.y, av.y + bv.x};
-        } else if (p > N - cd.Kz) {
-            const cpx<T> av = ldo(A, ra + (uint32_t)(N - p)), bv = ldo(B, rb + (uint32_t)(N - p));
-            c = {av.x + bv.y, bv.x - av.y};
-        }
-        v[e] = c;
+        const cpx<T> lo = {av[e].x - bv[e].y, av[e].y + bv[e].x};
+        const cpx<T> hi = {av[e].x + bv[e].y, bv[e].x - av[e].y};
+        const cpx<T> zero = {(T)0, (T)0};
+        v[e] = p < cd.Kz ? lo : (p > N - cd.Kz ? hi : zero);
     }
     fft_row_split<PL, +1, T>(v, row, tws, l);
     T* oa = zptr(zj.outa[job], zs) + q0 * N;
