@@ -366,10 +366,13 @@ __device__ __forceinline__ P* zptr(P* p, size_t zs) {
 
 // Block-index remap so that consecutive logical blocks (which write adjacent
 // pieces of the same cache lines) run on the same XCD: the hardware deals
-// blocks round-robin over 8 XCDs.
+// blocks round-robin over 8 XCDs, so XCD x runs the physical blocks x, x + 8,
+// ...; it gets the contiguous logical range starting at x q + min(x, r)
+// (q = total / 8, r = total % 8; the first r XCDs take q + 1 blocks).  A
+// bijection on [0, total) for any total = gridDim.x.
 __device__ __forceinline__ uint32_t xcd_block(uint32_t phys, uint32_t total) {
-    if (total % 8u != 0u) return phys;
-    return (phys % 8u) * (total / 8u) + phys / 8u;
+    const uint32_t x = phys % 8u, k = phys / 8u, q = total / 8u, r = total % 8u;
+    return x * q + (x < r ? x : r) + k;
 }
 
 }  // namespace gridspt
