@@ -1,20 +1,23 @@
 // The five pass kernels of one GridSPT order (Sec. II C, steps 2-6) and the
 // linear-field variants of step 1, specialised per precision T and grid size N.
 //
-// Every pass reads whole rows along the axis it transforms (contiguous in
-// HBM) and, except the last, writes its result transposed so that the next
-// pass again reads contiguous rows.  The transposition goes through LDS: a
-// block holds RPB rows, and writes RPB consecutive elements of each output row.
+// Every pass writes the rows it transforms contiguously (each lane stores its
+// points straight from registers), and every pass after the first reads its
+// rows transposed: a block holds RPB rows that are RPB consecutive elements of
+// the previous layout, loads those short runs for every position along the
+// axis and regroups them into rows through LDS.  Scattered short stores cost
+// about twice what scattered short loads cost on this memory system, so the
+// transposition sits on the load side.
 //
 // Pruning: every field after a forward transform is masked to |n|^2 <= n2max
 // with n2max < (N/2)^2, so only the cube |n_i| <= Kc (Kc = floor(sqrt(n2max)))
 // is ever non-zero.  Forward passes store only that range, inverse passes read
 // only that range.  Spectral layouts (complex, "fftfreq" order for signed
 // indices: i' <= Kc is +i', i' > Kc is i' - (2Kc+1)):
-//   S1 [kz][x][y]    Kz x N  x N      after the z pass        (Kz = Kc + 1)
-//   S2 [kz][ky][x]   Kz x Ky x N      after the y pass        (Ky = 2Kc + 1)
-//   S3 [kz][x][ky]   Kz x N  x Ky     after the fused x pass
-//   S4 [x][y][kz]    N  x N  x Kz     after the inverse y pass
+//   S1 [x][y][kz]    N  x N  x Kz     after the z pass        (Kz = Kc + 1)
+//   S2 [kz][x][ky]   Kz x N  x Ky     after the y pass        (Ky = 2Kc + 1)
+//   S3 [kz][ky][x]   Kz x Ky x N      after the fused x pass
+//   S4 [x][kz][y]    N  x Kz x N      after the inverse y pass
 //   cube [kz][ky][kx] Kz x Ky x Kx    the spectra handed to the caller
 // Real fields are [x][y][z], z contiguous.
 //
@@ -23,8 +26,8 @@
 // and in reverse C(k) = A(k) + i B(k), C(-k) = A(k)^* + i B(k)^*.
 //
 // Addressing: the rows a block touches start at a block-uniform base pointer;
-// the bulk loads add a 32-bit per-lane offset to it, so loads use the scalar
-// base + vector offset form and need no 64-bit address registers.
+// the bulk loads and stores add a 32-bit per-lane offset to it, so they use
+// the scalar base + vector offset form and need no 64-bit address registers.
 #pragma once
 #include "fft_engine.hpp"
 
@@ -142,33 +145,51 @@ __device__ __forceinline__ void stage_row(const cpx<T> (&v)[PL::E], cpx<T>* row,
     for (int e = 0; e < PL::E; ++e) row[lds_pad(l + PL::P * e)] = v[e];
 }
 
-// Transposed store of the block's rows through real-valued LDS rows (split
-// exchange): output item idx < count is (o, rr) = (idx / RPB, idx % RPB) and
-// takes position pos(o) of row rr; store(o, rr, value) writes it.  Real parts
-// travel first and wait in registers (at most N / P = E items per thread).
-template <typename T, int N, int V, typename PosF, typename StoreF, int E>
-__device__ __forceinline__ void transpose_out_split(const cpx<T> (&v)[E], const T* lds, T* row, int l, int count,
-                                                    PosF pos, StoreF store) {
+// Transposed load, gather half: item it of this thread is idx = threadIdx.x +
+// THREADS it, i.e. (q, rr) = (idx / RPB, idx % RPB): position q of block row
+// rr, read from in[q * stride + rr].  Every lane loads (items past `count`
+// read item count - 1, rows past `nrows` read row 0; both are dropped later),
+// so all loads are in flight together and can be issued before other work.
+template <typename T, int N, int V, int ITEMS>
+__device__ __forceinline__ void gather_runs(cpx<T> (&g)[ITEMS], const cpx<T>* in, uint32_t stride, int count,
+                                           int nrows) {
+    using RW = Rows<T, N, V>;
+    constexpr int RPB = RW::RPB;
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int idx = min((int)threadIdx.x + RW::THREADS * it, count * RPB - 1);
+        const int q = idx / RPB, rr = idx % RPB;
+        g[it] = ldo(in, (uint32_t)q * stride + (uint32_t)(rr < nrows ? rr : 0));
+    }
+}
+
+// Transposed load, scatter half, through real-valued LDS rows (split
+// exchange): the gathered items go to position pos(q) of LDS row rr, real
+// parts first; afterwards v[e] holds position l + P e of this wave's row, or
+// zero where has(l + P e) is false.  Starts with a block barrier (the rows may
+// still be in use) and leaves every row free for this wave's own exchanges.
+template <typename T, int N, int V, int ITEMS, typename PosF, typename HasF, int E>
+__device__ __forceinline__ void scatter_runs_split(const cpx<T> (&g)[ITEMS], T* lds, const T* row, int l, int count,
+                                                   PosF pos, HasF has, cpx<T> (&v)[E]) {
     using RW = Rows<T, N, V>;
     constexpr int RPB = RW::RPB, ROWE = RW::ROWE, P = RW::P;
     static_assert(E == RW::E, "register count of the row");
-    T re[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) row[lds_pad(l + P * e)] = v[e].x;
-    __syncthreads();
+    for (int part = 0; part < 2; ++part) {
+        __syncthreads();
 #pragma unroll
-    for (int it = 0; it < E; ++it) {
-        const int idx = threadIdx.x + RW::THREADS * it;
-        if (idx < count) re[it] = lds[(idx % RPB) * ROWE + lds_pad(pos(idx / RPB))];
-    }
-    __syncthreads();
+        for (int it = 0; it < ITEMS; ++it) {
+            const int idx = (int)threadIdx.x + RW::THREADS * it;
+            if (idx < count * RPB) lds[(idx % RPB) * ROWE + lds_pad(pos(idx / RPB))] = part ? g[it].y : g[it].x;
+        }
+        __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) row[lds_pad(l + P * e)] = v[e].y;
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < E; ++it) {
-        const int idx = threadIdx.x + RW::THREADS * it;
-        if (idx < count) store(idx / RPB, idx % RPB, cpx<T>{re[it], lds[(idx % RPB) * ROWE + lds_pad(pos(idx / RPB))]});
+        for (int e = 0; e < E; ++e) {
+            const T t = row[lds_pad(l + P * e)];
+            const T z = has(l + P * e) ? t : (T)0;
+            if (part) v[e].y = z;
+            else v[e].x = z;
+        }
     }
 }
 
@@ -324,27 +345,27 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __re
         fft_row<PL, -1, T>(v, row, tws, l);
         stage_row<PL, T>(v, row, l);
         __syncthreads();
-        // read-out: S1[kz][x][y0 + rr] for every kept kz
-        cpx<T>* out = s1 + ((size_t)x * N + y0);
+        // read-out: the kept kz of rows y0 + rr, S1 rows (x, y) of Kz values, in order
+        cpx<T>* out = s1 + ((size_t)x * N + y0) * Kz;
         for (int idx = threadIdx.x; idx < Kz * YB; idx += RW::THREADS) {
-            const int kz = idx / YB, rr = idx % YB;
+            const int rr = idx / Kz, kz = idx % Kz;
             const int team = PACK4 ? rr : rr % RPB;
             const cpx<T> c = lds[team * ROWE + lds_pad(kz)];
             const cpx<T> m = lds[team * ROWE + lds_pad(kz == 0 ? 0 : N - kz)];
-            const size_t o = (size_t)kz * N * N + rr;
             if constexpr (PACK4) {
-                out[(size_t)(2 * pk) * s1_field + o] = unpack_real_pair(c, m, 0);
-                out[(size_t)(2 * pk + 1) * s1_field + o] = unpack_real_pair(c, m, 1);
+                sto(out + (size_t)(2 * pk) * s1_field, (uint32_t)idx, unpack_real_pair(c, m, 0));
+                sto(out + (size_t)(2 * pk + 1) * s1_field, (uint32_t)idx, unpack_real_pair(c, m, 1));
             } else {
-                out[o] = unpack_real_pair(c, m, rr / RPB);
+                sto(out, (uint32_t)idx, unpack_real_pair(c, m, rr / RPB));
             }
         }
     });
 }
 
 // --------------------------------------------------------------------------
-// P2: y pass, forward.  Rows (kz, x) of S1; block = RPB consecutive x at one
-// kz; grid.y = field.  Keeps |ky| <= Kc and writes S2 [kz][ky'][x].
+// P2: y pass, forward.  Rows (x, kz) along y of S1; block = RPB consecutive
+// kz at one x (runs of RPB elements of S1); grid.y = field.  Keeps
+// |ky| <= Kc and writes S2 rows (kz, x) of Ky values.
 // --------------------------------------------------------------------------
 template <typename T, int N, int V>
 __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yfwd(const cpx<T>* __restrict__ s1, size_t s1_field,
@@ -363,26 +384,35 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yfwd(const cpx<T>*
     const Twiddles<T, PL, LT> tws{LT ? twl : tw};
     s1 = zptr(s1, zs);
     s2 = zptr(s2, zs);
-    constexpr uint32_t groups = N / RPB;
-    const uint32_t blk = xcd_block(blockIdx.x, cd.Kz * groups);
-    const int kz = blk / groups, x0 = (blk % groups) * RPB;
+    // block = RPB consecutive kz at one x: the rows (x, kz) along y
+    const uint32_t groups = (cd.Kz + RPB - 1) / RPB;
+    const uint32_t blk = xcd_block(blockIdx.x, N * groups);
+    const int x = blk / groups, kz0 = (blk % groups) * RPB;
+    const int nrows = min(RPB, cd.Kz - kz0);
     const int r = threadIdx.x / P, l = threadIdx.x % P;
-    const cpx<T>* in = s1 + (size_t)blockIdx.y * s1_field + ((size_t)kz * N + x0) * N;
     T* row = lds + r * ROWE;
+    cpx<T> g[E];
+    gather_runs<T, N, V>(g, s1 + (size_t)blockIdx.y * s1_field + (size_t)x * N * cd.Kz + kz0, (uint32_t)cd.Kz, N,
+                         nrows);
     cpx<T> v[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = ldo(in, (uint32_t)(r * N + l + P * e));
+    scatter_runs_split<T, N, V>(g, lds, row, l, N, [](int q) { return q; }, [](int) { return true; }, v);
     fft_row_split<PL, -1, T>(v, row, tws, l);
-    cpx<T>* out = s2 + (size_t)blockIdx.y * s2_field + (size_t)kz * cd.Ky * N + x0;
-    transpose_out_split<T, N, V>(
-        v, lds, row, l, cd.Ky * RPB, [&](int ky) { return compact_to_pos(ky, cd.Kc, N); },
-        [&](int ky, int rr, cpx<T> val) { sto(out, (uint32_t)(ky * N + rr), val); });
+    // S2 row (kz0 + r, x): the kept ky in compact order
+    if (r < nrows) {
+        cpx<T>* out = s2 + (size_t)blockIdx.y * s2_field + ((size_t)kz0 * N + x) * cd.Ky;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int ic = pos_to_compact(l + P * e, cd.Kc, N);
+            if (ic >= 0) sto(out, (uint32_t)(r * N * cd.Ky + ic), v[e]);
+        }
+    }
 }
 
 // --------------------------------------------------------------------------
-// P3: x pass, fused.  Rows (kz, ky') of S2; block = RPB consecutive ky' at one
-// kz.  Forward x transform, the k-space step, optional cube stores, then the
-// inverse x transform of every output field, written transposed to S3.
+// P3: x pass, fused.  Rows (kz, ky') along x of S2; block = RPB consecutive
+// ky' at one kz (runs of RPB elements of S2).  Forward x transform, the
+// k-space step, optional cube stores, then the inverse x transform of every
+// output field, stored as S3 rows (kz, ky').
 // --------------------------------------------------------------------------
 // LIN_ORDER1: the linear field from noise (as LINEAR) with the outputs of
 // order 1 (as ORDER1): delta_1 and u_1 without a round trip through real space
@@ -413,21 +443,19 @@ struct XArgs {
     const double* amp;  // LINEAR, LIN_ORDER1, ADJ1: the radial amplitude table (k_amp_table)
 };
 
-// inverse x transform of one output row and its transposed store into S3
+// inverse x transform of this wave's output row and its store as S3 row r of
+// the block (out = the block's first row; rows are N apart).  The row is
+// contiguous in S3, so every lane stores its points from registers, and the
+// transform only uses this wave's LDS row: no block barrier.
 template <typename T, int N, int V, typename TW, int E>
-__device__ __forceinline__ void x_inverse_store(cpx<T> (&v)[E], cpx<T>* lds, cpx<T>* row, TW tw, int l, cpx<T>* out,
-                                                int Ky, int nrows) {
-    using RW = Rows<T, N, V>;
-    using PL = typename RW::PL;
+__device__ __forceinline__ void x_inverse_store(cpx<T> (&v)[E], cpx<T>* row, TW tw, int l, cpx<T>* out, int r,
+                                                bool active) {
+    using PL = typename Rows<T, N, V>::PL;
     static_assert(E == PL::E, "register count of the row");
-    constexpr int RPB = RW::RPB, ROWE = RW::ROWE;
-    __syncthreads();  // the previous read-out is done with LDS
     fft_row<PL, +1, T>(v, row, tw, l);
-    stage_row<PL, T>(v, row, l);
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < N * RPB; idx += RW::THREADS) {
-        const int x = idx / RPB, rr = idx % RPB;
-        if (rr < nrows) sto(out, (uint32_t)(x * Ky + rr), lds[rr * ROWE + lds_pad(x)]);
+    if (active) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) sto(out, (uint32_t)(r * N + l + PL::P * e), v[e]);
     }
 }
 
@@ -458,7 +486,6 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
     const int ky = active ? (kyc <= cd.Kc ? kyc : kyc - cd.Ky) : 0;
     const int nrows = min(RPB, cd.Ky - ky0);
     cpx<T>* row = lds + r * ROWE;
-    const size_t inbase = ((size_t)kz * cd.Ky + ky0) * N;
 
     // k-space step: sd holds delta_n(k), st holds theta_n(k) afterwards
     cpx<T> sd[E], st[E];
@@ -481,36 +508,32 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
             ampv[e] = n2 <= n2lim ? t : (T)0;
         }
     }
-    // Input rows: unconditional loads (a row past the cube reads row 0 of the block, which
-    // exists, and is zeroed after), and field f + 1 is loaded before field f is transformed,
-    // so its latency hides behind that transform (not in the reverse mode, whose k-space
-    // accumulation leaves no registers for it).
-    const uint32_t rin = (uint32_t)((active ? r : 0) * N + l);
-    auto load_field = [&](int f, cpx<T>(&dst)[E]) {
-        const cpx<T>* in = a.s2 + (size_t)f * a.s2_field + inbase;
-#pragma unroll
-        for (int e = 0; e < E; ++e) dst[e] = load_or_zero(in, rin + (uint32_t)(P * e), active);
+    // Input rows: runs of RPB ky' for every x, regrouped through LDS (rows past the cube
+    // read row 0 of the block and are never stored).  The runs of field f + 1 are
+    // loaded before field f is transformed, so their latency hides behind it (not in
+    // the reverse mode, whose k-space accumulation leaves no registers for them).
+    auto gather_field = [&](int f, cpx<T>(&gf)[E]) {
+        gather_runs<T, N, V>(gf, a.s2 + (size_t)f * a.s2_field + (size_t)kz * N * cd.Ky + ky0, (uint32_t)cd.Ky, N,
+                             nrows);
     };
-    cpx<T> cur[E];
-    load_field(0, cur);
+    cpx<T> g[E];
+    gather_field(0, g);
     static_for<NIN>([&](auto fc) {
         constexpr int f = decltype(fc)::value;
         if (ADJ && f >= a.nin) return;
-        constexpr bool PREFETCH = !ADJ && f + 1 < NIN;
-        cpx<T> nxt[PREFETCH ? E : 1];
-        if constexpr (PREFETCH) load_field(f + 1, nxt);
+        if constexpr (ADJ && f > 0) gather_field(f, g);
+        __syncthreads();  // every wave is done with its row
+#pragma unroll
+        for (int it = 0; it < E; ++it) {
+            const int idx = (int)threadIdx.x + RW::THREADS * it;
+            lds[(idx % RPB) * ROWE + lds_pad(idx / RPB)] = g[it];
+        }
+        __syncthreads();
         cpx<T> v[E];
-        if constexpr (ADJ && f > 0) {
-            load_field(f, v);
-        } else {
 #pragma unroll
-            for (int e = 0; e < E; ++e) v[e] = cur[e];
-        }
+        for (int e = 0; e < E; ++e) v[e] = row[lds_pad(l + P * e)];
+        if constexpr (!ADJ && f + 1 < NIN) gather_field(f + 1, g);
         fft_row<PL, -1, T>(v, row, tws, l);
-        if constexpr (PREFETCH) {
-#pragma unroll
-            for (int e = 0; e < E; ++e) cur[e] = nxt[e];
-        }
         if constexpr (MODE == XM_ORDER) {
             if constexpr (f < 3) {
                 // S_delta += i k_f V_f(k)  (kF and N^-3 applied below)
@@ -626,7 +649,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
                                : ((MODE == XM_ORDER1 || MODE == XM_LIN_ORDER1 || MODE == XM_ADJ) ? 4
                                                                                                   : (MODE == XM_PFORM ? 2 : 1));
         constexpr int FIRST_U = (MODE == XM_ORDER || MODE == XM_PFORM) ? 2 : 1;
-        const size_t outbase = (size_t)kz * N * cd.Ky + ky0;
+        const size_t outbase = ((size_t)kz * cd.Ky + ky0) * N;
         static_for<NOUT_MAX>([&](auto oc) {
             constexpr int o = decltype(oc)::value;
             if (o < a.nout) {
@@ -668,8 +691,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
                         v[e] = {st[e].y * kj, -st[e].x * kj};
                     }
                 }
-                x_inverse_store<T, N, V>(v, lds, row, tws, l, a.s3 + (size_t)o * a.s3_field + outbase, cd.Ky,
-                                             nrows);
+                x_inverse_store<T, N, V>(v, row, tws, l, a.s3 + (size_t)o * a.s3_field + outbase, r, active);
             }
         });
     }
@@ -678,7 +700,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
 // --------------------------------------------------------------------------
 // P3 for shell-filtered fields (bispectrum): rows (kz, ky') of a cube, kept
 // when lo <= n^2 < hi; the field pointer may be null for the indicator 1_b.
-// Inverse x transform, written transposed to S3.  grid.y = slot.
+// Inverse x transform, stored as S3 rows.  grid.y = slot.
 // --------------------------------------------------------------------------
 template <typename T>
 struct ShellSlots {
@@ -736,15 +758,14 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xshell(ShellSlots<
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = in[e] ? cpx<T>{(T)1, (T)0} : cpx<T>{(T)0, (T)0};
     }
-    x_inverse_store<T, N, V>(v, lds, row, tws, l,
-                                 zptr(a.s3, zs) + (size_t)slot * a.s3_field + (size_t)kz * N * cd.Ky + ky0, cd.Ky,
-                                 min(RPB, cd.Ky - ky0));
+    x_inverse_store<T, N, V>(v, row, tws, l,
+                             zptr(a.s3, zs) + (size_t)slot * a.s3_field + ((size_t)kz * cd.Ky + ky0) * N, r, active);
 }
 
 // --------------------------------------------------------------------------
 // P3 from stored spectra (reverse mode): rows (kz, ky') of the cubes of
 // delta_m and theta_m; inverse x transforms of delta_m and
-// u_m = (-i k / k^2) theta_m, written transposed to S3 fields 0..3.
+// u_m = (-i k / k^2) theta_m, stored as rows of S3 fields 0..3.
 // --------------------------------------------------------------------------
 template <typename T>
 struct RegenArgs {
@@ -774,13 +795,12 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xregen(RegenArgs<T
     const int kyc = ky0 + r;
     const bool active = kyc < cd.Ky;
     const int ky = active ? (kyc <= cd.Kc ? kyc : kyc - cd.Ky) : 0;
-    const int nrows = min(RPB, cd.Ky - ky0);
     const size_t cbase = ((size_t)kz * cd.Ky + kyc) * cd.Ky;
     const cpx<T>* cdl = zptr(a.cube_d, zs);
     const cpx<T>* ctl = zptr(a.cube_t, zs);
     cpx<T>* s3 = zptr(a.s3, zs);
     cpx<T>* row = lds + r * ROWE;
-    const size_t outbase = (size_t)kz * N * cd.Ky + ky0;
+    const size_t outbase = ((size_t)kz * cd.Ky + ky0) * N;
     static_for<4>([&](auto oc) {
         constexpr int o = decltype(oc)::value;
         cpx<T> v[E];
@@ -800,7 +820,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xregen(RegenArgs<T
                 v[e] = {t.y * sc, -t.x * sc};
             }
         }
-        x_inverse_store<T, N, V>(v, lds, row, tws, l, s3 + (size_t)o * a.s3_field + outbase, cd.Ky, nrows);
+        x_inverse_store<T, N, V>(v, row, tws, l, s3 + (size_t)o * a.s3_field + outbase, r, active);
     });
 }
 
@@ -810,7 +830,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xregen(RegenArgs<T
 //   0-2  grad delta = F^-1[i k delta],      3-5  grad theta = F^-1[i k theta],
 //   6-8  u = F^-1[(-i k / k^2) theta],       9-14 d_i u_j = F^-1[(k_i k_j / k^2) theta]
 //        for (i, j) = (x,x), (y,y), (z,z), (x,y), (x,z), (y,z) (symmetric: u is a gradient)
-// written transposed to S3 fields 0..4.
+// stored as rows of S3 fields 0..4.
 // --------------------------------------------------------------------------
 template <typename T, int N, int V, int CHUNK>
 __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xderived(RegenArgs<T> a, const cpx<T>* __restrict__ tw,
@@ -831,13 +851,12 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xderived(RegenArgs
     const int kyc = ky0 + r;
     const bool active = kyc < cd.Ky;
     const int ky = active ? (kyc <= cd.Kc ? kyc : kyc - cd.Ky) : 0;
-    const int nrows = min(RPB, cd.Ky - ky0);
     const size_t cbase = ((size_t)kz * cd.Ky + kyc) * cd.Ky;
     const cpx<T>* cdl = zptr(a.cube_d, zs);
     const cpx<T>* ctl = zptr(a.cube_t, zs);
     cpx<T>* s3 = zptr(a.s3, zs);
     cpx<T>* row = lds + r * ROWE;
-    const size_t outbase = (size_t)kz * N * cd.Ky + ky0;
+    const size_t outbase = ((size_t)kz * cd.Ky + ky0) * N;
     static_for<5>([&](auto oc) {
         constexpr int o = decltype(oc)::value;
         constexpr int fld = 5 * CHUNK + o;
@@ -865,7 +884,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xderived(RegenArgs
                 v[e] = cscale(src, sc);
             }
         }
-        x_inverse_store<T, N, V>(v, lds, row, tws, l, s3 + (size_t)o * a.s3_field + outbase, cd.Ky, nrows);
+        x_inverse_store<T, N, V>(v, row, tws, l, s3 + (size_t)o * a.s3_field + outbase, r, active);
     });
 }
 
@@ -873,7 +892,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xderived(RegenArgs
 // P3 for smoothed fields (Sec. III A-B): rows (kz, ky') of up to five cubes;
 // output o is the inverse x transform of exp(-k^2 R^2 / 2) S_o(k) with
 // S_o = sum_{i <= o} coef_i F_i (cumulative, the truncated series of Eq. 8)
-// or coef_o F_o, written transposed to S3 field o.
+// or coef_o F_o, stored as rows of S3 field o.
 // --------------------------------------------------------------------------
 template <typename T>
 struct SmoothArgs {
@@ -904,11 +923,10 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xsmooth(SmoothArgs
     const int kyc = ky0 + r;
     const bool active = kyc < cd.Ky;
     const int ky = active ? (kyc <= cd.Kc ? kyc : kyc - cd.Ky) : 0;
-    const int nrows = min(RPB, cd.Ky - ky0);
     const size_t cbase = ((size_t)kz * cd.Ky + kyc) * cd.Ky;
     cpx<T>* s3 = zptr(a.s3, zs);
     cpx<T>* row = lds + r * ROWE;
-    const size_t outbase = (size_t)kz * N * cd.Ky + ky0;
+    const size_t outbase = ((size_t)kz * cd.Ky + ky0) * N;
     const double g = -0.5 * a.kF * a.kF * a.radius * a.radius;
     // the window of each kept element, once for all outputs
     T w[E];
@@ -944,13 +962,14 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xsmooth(SmoothArgs
         }
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = cscale(v[e], w[e]);
-        x_inverse_store<T, N, V>(v, lds, row, tws, l, s3 + (size_t)o * a.s3_field + outbase, cd.Ky, nrows);
+        x_inverse_store<T, N, V>(v, row, tws, l, s3 + (size_t)o * a.s3_field + outbase, r, active);
     });
 }
 
 // --------------------------------------------------------------------------
-// P4: y pass, inverse.  Rows (kz, x) of S3 (Ky values, zero-extended to N);
-// block = RPB consecutive kz at one x; grid.y = field.  Writes S4 [x][y][kz].
+// P4: y pass, inverse.  Rows (kz, x) along ky' of S3 (Ky values, zero-extended
+// to N); block = RPB consecutive x at one kz (runs of RPB elements of S3);
+// grid.y = field.  Writes S4 rows (x, kz) of N values.
 // --------------------------------------------------------------------------
 template <typename T, int N, int V>
 __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yinv(const cpx<T>* __restrict__ s3, size_t s3_field,
@@ -970,33 +989,31 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yinv(const cpx<T>*
     const Twiddles<T, PL, LT> tws{LT ? twl : tw};
     s3 = zptr(s3, zs);
     s4 = zptr(s4, zs);
-    const uint32_t groups = (cd.Kz + RPB - 1) / RPB;
-    const uint32_t blk = xcd_block(blockIdx.x, N * groups);
-    const int x = blk / groups, kz0 = (blk % groups) * RPB;
+    constexpr uint32_t groups = N / RPB;
+    const uint32_t blk = xcd_block(blockIdx.x, cd.Kz * groups);
+    const int kz = blk / groups, x0 = (blk % groups) * RPB;
     const int r = threadIdx.x / P, l = threadIdx.x % P;
-    const bool active = kz0 + r < cd.Kz;
-    const cpx<T>* in = s3 + (size_t)blockIdx.y * s3_field + ((size_t)kz0 * N + x) * cd.Ky;
-    const uint32_t rowoff = (uint32_t)(r * N * cd.Ky);
     T* row = lds + r * ROWE;
+    cpx<T> g[E];
+    gather_runs<T, N, V>(g, s3 + (size_t)blockIdx.y * s3_field + (size_t)kz * cd.Ky * N + x0, (uint32_t)N, cd.Ky,
+                         RPB);
     cpx<T> v[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int ic = pos_to_compact(l + P * e, cd.Kc, N);
-        v[e] = (active && ic >= 0) ? ldo(in, rowoff + (uint32_t)ic) : cpx<T>{(T)0, (T)0};
-    }
+    scatter_runs_split<T, N, V>(
+        g, lds, row, l, cd.Ky, [&](int q) { return compact_to_pos(q, cd.Kc, N); },
+        [&](int p) { return pos_to_compact(p, cd.Kc, N) >= 0; }, v);
     fft_row_split<PL, +1, T>(v, row, tws, l);
-    cpx<T>* out = s4 + (size_t)blockIdx.y * s4_field + (size_t)x * N * cd.Kz + kz0;
-    const int nrows = min(RPB, cd.Kz - kz0);
-    transpose_out_split<T, N, V>(v, lds, row, l, N * RPB, [](int y) { return y; }, [&](int y, int rr, cpx<T> val) {
-        if (rr < nrows) sto(out, (uint32_t)(y * cd.Kz + rr), val);
-    });
+    // S4 row (x0 + r, kz)
+    cpx<T>* out = s4 + (size_t)blockIdx.y * s4_field + ((size_t)x0 * cd.Kz + kz) * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) sto(out, (uint32_t)(r * cd.Kz * N + l + P * e), v[e]);
 }
 
 // --------------------------------------------------------------------------
-// P5: z pass, inverse to real.  Rows (x, y) of S4 (Kz values).  Job j pairs
-// either two fields of the same row (fb[j] >= 0; block = RPB rows) or one
-// field of two rows q and q + RPB (fb[j] < 0; block = 2 RPB rows, and the
-// second half of the grid idles).  grid.y = job.
+// P5: z pass, inverse to real.  Rows (x, y) along kz of S4 (Kz values); a
+// block holds runs of consecutive y at one x.  Job j pairs either two fields
+// of the same row (fb[j] >= 0; block = RPB rows) or one field of two rows y
+// and y + RPB (fb[j] < 0; block = 2 RPB rows, and the second half of the grid
+// idles).  grid.y = job.
 // --------------------------------------------------------------------------
 template <typename T>
 struct ZJobs {
@@ -1012,7 +1029,11 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zinv(const cpx<T>*
     using RW = Rows<T, N, V>;
     using PL = typename RW::PL;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
-    __shared__ T lds[RPB * ROWE];  // real-valued exchange rows (split exchange)
+    // real-valued exchange rows (split exchange); before the transform the same
+    // LDS holds the staged runs as complex rows of SROW >= Kz elements
+    __shared__ __align__(16) T lds[RPB * ROWE];
+    constexpr int SROW = ROWE / 2;
+    static_assert(SROW >= N / 2, "a staged row holds every kept kz");
     // twiddles in LDS for FP32 (this pass's LDS traffic is light), else from the cache
     constexpr bool LT = kLdsTwiddles<T> && true;
     __shared__ cpx<T> twl[LT ? PL::TW_ALLOC : 1];
@@ -1026,31 +1047,44 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zinv(const cpx<T>*
     const uint32_t blk = xcd_block(blockIdx.x, nblk);
     if (tworows && blk >= nblk / 2) return;  // whole block leaves; no block barrier follows
     const int r = threadIdx.x / P, l = threadIdx.x % P;
-    const size_t q0 = (size_t)blk * (tworows ? 2 * RPB : RPB);  // first row of the block
-    const cpx<T>* A = s4 + (size_t)zj.fa[job] * s4_field + q0 * cd.Kz;
-    const cpx<T>* B = tworows ? A : s4 + (size_t)zj.fb[job] * s4_field + q0 * cd.Kz;
-    const uint32_t ra = (uint32_t)(r * cd.Kz), rb = (uint32_t)((tworows ? r + RPB : r) * cd.Kz);
+    const size_t q0 = (size_t)blk * (tworows ? 2 * RPB : RPB);  // first row (x N + y) of the block
+    const int x = (int)(q0 / N), y0 = (int)(q0 % N);
+    const cpx<T>* A = s4 + (size_t)zj.fa[job] * s4_field + (size_t)x * cd.Kz * N + y0;
+    const cpx<T>* B = tworows ? A + RPB : s4 + (size_t)zj.fb[job] * s4_field + (size_t)x * cd.Kz * N + y0;
     T* row = lds + r * ROWE;
-    // Every lane loads (from the stored half, its own position or the mirrored one, a valid
-    // index either way) and selects afterwards: no branch around a load, so all loads of
-    // the row are in flight together.
-    cpx<T> av[E], bv[E];
+    // runs of RPB y for every kz (Kz <= N / 2, so E / 2 items per thread), all loads first
+    constexpr int IT = E / 2;
+    cpx<T> ga[IT], gb[IT];
+    gather_runs<T, N, V>(ga, A, (uint32_t)N, cd.Kz, RPB);
+    gather_runs<T, N, V>(gb, B, (uint32_t)N, cd.Kz, RPB);
+    cpx<T>* stage = reinterpret_cast<cpx<T>*>(lds);
+    auto scatter = [&](const cpx<T>(&gg)[IT]) {
+        __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int p = l + P * e;
-        const int q = p < cd.Kz ? p : (p > N - cd.Kz ? N - p : 0);
-        av[e] = ldo(A, ra + (uint32_t)q);
-        bv[e] = ldo(B, rb + (uint32_t)q);
-    }
+        for (int it = 0; it < IT; ++it) {
+            const int idx = (int)threadIdx.x + RW::THREADS * it;
+            if (idx < cd.Kz * RPB) stage[(idx % RPB) * SROW + idx / RPB] = gg[it];
+        }
+        __syncthreads();
+    };
+    // position p of the Hermitian row takes kz = p (p < Kz) or the mirror N - p
+    auto src = [&](int p) { return p < cd.Kz ? p : (p > N - cd.Kz ? N - p : 0); };
+    scatter(ga);
+    cpx<T> av[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) av[e] = stage[r * SROW + src(l + P * e)];
+    scatter(gb);
     cpx<T> v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int p = l + P * e;
-        const cpx<T> lo = {av[e].x - bv[e].y, av[e].y + bv[e].x};
-        const cpx<T> hi = {av[e].x + bv[e].y, bv[e].x - av[e].y};
+        const cpx<T> bv = stage[r * SROW + src(p)];
+        const cpx<T> lo = {av[e].x - bv.y, av[e].y + bv.x};
+        const cpx<T> hi = {av[e].x + bv.y, bv.x - av[e].y};
         const cpx<T> zero = {(T)0, (T)0};
         v[e] = p < cd.Kz ? lo : (p > N - cd.Kz ? hi : zero);
     }
+    __syncthreads();  // every wave has read the staged runs before the exchanges reuse the LDS
     fft_row_split<PL, +1, T>(v, row, tws, l);
     T* oa = zptr(zj.outa[job], zs) + q0 * N;
     T* ob = zptr(tworows ? zj.outa[job] : zj.outb[job], zs) + q0 * N;

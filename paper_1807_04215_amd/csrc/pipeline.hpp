@@ -187,7 +187,8 @@ struct Pipe {
             constexpr int V = decltype(vc)::value;
             using RW = Rows<T, N, V>;
             const double bytes = nb() * nf * (d.s1() + d.s2()) * d.cpx_bytes;
-            return launch(c, KD_YFWD, bytes, dim3((unsigned)(d.Kz * (N / RW::RPB)), nf, nz()), dim3(RW::THREADS), 0,
+            return launch(c, KD_YFWD, bytes, dim3((unsigned)(N * ((d.Kz + RW::RPB - 1) / RW::RPB)), nf, nz()),
+                          dim3(RW::THREADS), 0,
                           k_yfwd<T, N, V>, (const cpx<T>*)A(), (size_t)L.a_field_s1, B(), (size_t)L.b_field_s2,
                           (const cpx<T>*)tw(), cd, bt.zs);
         });
@@ -258,7 +259,7 @@ struct Pipe {
             constexpr int V = decltype(vc)::value;
             using RW = Rows<T, N, V>;
             const double bytes = nb() * nf * ((double)cd.Kz * N * cd.Ky + (double)N * N * cd.Kz) * d.cpx_bytes;
-            return launch(c, KD_YINV, bytes, dim3((unsigned)(N * ((cd.Kz + RW::RPB - 1) / RW::RPB)), nf, nz()),
+            return launch(c, KD_YINV, bytes, dim3((unsigned)(cd.Kz * (N / RW::RPB)), nf, nz()),
                           dim3(RW::THREADS), 0, k_yinv<T, N, V>, (const cpx<T>*)A(), (size_t)L.a_field_s3, B(),
                           (size_t)L.b_field_s4, (const cpx<T>*)tw(), cd, bt.zs);
         });
