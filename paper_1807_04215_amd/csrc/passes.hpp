@@ -14,12 +14,16 @@
 // is ever non-zero.  Forward passes store only that range, inverse passes read
 // only that range.  Spectral layouts (complex, "fftfreq" order for signed
 // indices: i' <= Kc is +i', i' > Kc is i' - (2Kc+1)):
-//   S1 [x][y][kz]    N  x N  x Kz     after the z pass        (Kz = Kc + 1)
+//   S1 [x][kz/TZ][y][kz%TZ]           after the z pass        (Kz = Kc + 1)
+//                    N  x Kz x N, in tiles of TZ kz (the last tile narrower)
 //   S2 [kz][x][ky]   Kz x N  x Ky     after the y pass        (Ky = 2Kc + 1)
 //   S3 [kz][ky][x]   Kz x Ky x N      after the fused x pass
 //   S4 [x][kz][y]    N  x Kz x N      after the inverse y pass
 //   cube [kz][ky][kx] Kz x Ky x Kx    the spectra handed to the caller
-// Real fields are [x][y][z], z contiguous.
+// Real fields are [x][y][z], z contiguous.  S1 is tiled because the z pass
+// (rows (x, y)) and the y pass (rows (x, kz)) both hold one x per block: a z
+// pass block stores a whole block of y for every tile, and a y pass block
+// reads one whole tile.
 //
 // Real data along z is transformed two rows (or two fields) per complex FFT:
 // c = a + i b gives A(k) = (C(k) + C(-k)^*) / 2 and B(k) = (C(k) - C(-k)^*) / 2i,
@@ -56,6 +60,10 @@ struct Rows {
     static constexpr int ROWE = lds_row_elems(N);
     static_assert(THREADS <= 1024, "block too large");
 };
+
+// Width of the kz tiles of S1: the rows of a y pass block in variant 0.
+template <typename T, int N>
+constexpr int kTileZ = Rows<T, N, 0>::RPB;
 
 // element at a 32-bit element offset from a block-uniform base
 template <typename T>
@@ -345,18 +353,22 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __re
         fft_row<PL, -1, T>(v, row, tws, l);
         stage_row<PL, T>(v, row, l);
         __syncthreads();
-        // read-out: the kept kz of rows y0 + rr, S1 rows (x, y) of Kz values, in order
-        cpx<T>* out = s1 + ((size_t)x * N + y0) * Kz;
+        // read-out: the kept kz of rows y0 + rr in S1 tile order, tile by tile (tb = first
+        // kz of the tile, w its width); consecutive items are consecutive addresses
+        constexpr int TZ = kTileZ<T, N>;
+        cpx<T>* out = s1 + (size_t)x * N * Kz;
         for (int idx = threadIdx.x; idx < Kz * YB; idx += RW::THREADS) {
-            const int rr = idx / Kz, kz = idx % Kz;
+            const int tb = idx / (YB * TZ) * TZ, w = min(TZ, Kz - tb);
+            const int j = idx - tb * YB, rr = j / w, kz = tb + j % w;
+            const uint32_t o = (uint32_t)(tb * N + (y0 + rr) * w + (kz - tb));
             const int team = PACK4 ? rr : rr % RPB;
             const cpx<T> c = lds[team * ROWE + lds_pad(kz)];
             const cpx<T> m = lds[team * ROWE + lds_pad(kz == 0 ? 0 : N - kz)];
             if constexpr (PACK4) {
-                sto(out + (size_t)(2 * pk) * s1_field, (uint32_t)idx, unpack_real_pair(c, m, 0));
-                sto(out + (size_t)(2 * pk + 1) * s1_field, (uint32_t)idx, unpack_real_pair(c, m, 1));
+                sto(out + (size_t)(2 * pk) * s1_field, o, unpack_real_pair(c, m, 0));
+                sto(out + (size_t)(2 * pk + 1) * s1_field, o, unpack_real_pair(c, m, 1));
             } else {
-                sto(out, (uint32_t)idx, unpack_real_pair(c, m, rr / RPB));
+                sto(out, o, unpack_real_pair(c, m, rr / RPB));
             }
         }
     });
@@ -391,9 +403,12 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yfwd(const cpx<T>*
     const int nrows = min(RPB, cd.Kz - kz0);
     const int r = threadIdx.x / P, l = threadIdx.x % P;
     T* row = lds + r * ROWE;
+    // the S1 tile holding kz0 .. kz0 + nrows - 1 (RPB divides the tile width TZ)
+    constexpr int TZ = kTileZ<T, N>;
+    const int tb = kz0 / TZ * TZ, w = min(TZ, cd.Kz - tb);
     cpx<T> g[E];
-    gather_runs<T, N, V>(g, s1 + (size_t)blockIdx.y * s1_field + (size_t)x * N * cd.Kz + kz0, (uint32_t)cd.Kz, N,
-                         nrows);
+    gather_runs<T, N, V>(g, s1 + (size_t)blockIdx.y * s1_field + (size_t)x * N * cd.Kz + (size_t)tb * N + (kz0 - tb),
+                         (uint32_t)w, N, nrows);
     cpx<T> v[E];
     scatter_runs_split<T, N, V>(g, lds, row, l, N, [](int q) { return q; }, [](int) { return true; }, v);
     fft_row_split<PL, -1, T>(v, row, tws, l);
