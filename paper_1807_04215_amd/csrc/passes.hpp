@@ -90,9 +90,11 @@ __device__ __forceinline__ int pos_to_compact(int p, int Kc, int n) {
 // Philox4x64-10 (Salmon et al., SC'11) and Box-Muller: unit Gaussians of the
 // four cells 4q .. 4q+3.  counter = (q, stream, 0, 0), key = (seed, 0); word
 // pairs (w0, w1), (w2, w3) give 53-bit uniforms in (0, 1); cell 4q + r takes
-// pair r / 2 and the cosine (r even) or sine (r odd) branch.
+// pair r / 2 and the cosine (r even) or sine (r odd) branch.  The transform
+// runs in the precision T of the field (an FP32 field needs no FP64 logarithm).
 // --------------------------------------------------------------------------
-__device__ __forceinline__ void group_gaussians(uint64_t seed, uint64_t stream, uint64_t q, double (&g)[4]) {
+template <typename T>
+__device__ __forceinline__ void group_gaussians(uint64_t seed, uint64_t stream, uint64_t q, T (&g)[4]) {
     uint64_t c0 = q, c1 = stream, c2 = 0, c3 = 0;
     uint64_t k0 = seed, k1 = 0;
 #pragma unroll
@@ -112,11 +114,13 @@ __device__ __forceinline__ void group_gaussians(uint64_t seed, uint64_t stream, 
     const uint64_t w[4] = {c0, c1, c2, c3};
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
-        const double u1 = ((double)(w[2 * p] >> 11) + 0.5) * 0x1p-53;
-        const double u2 = ((double)(w[2 * p + 1] >> 11) + 0.5) * 0x1p-53;
-        const double rad = sqrt(-2.0 * log(u1));
-        double sn, cs;
-        sincospi(2.0 * u2, &sn, &cs);  // the angle 2 pi u2, without a general range reduction
+        // the 53-bit uniforms are formed in FP64 (exact), then rounded once to T
+        const T u1 = (T)(((double)(w[2 * p] >> 11) + 0.5) * 0x1p-53);
+        const T u2 = (T)(((double)(w[2 * p + 1] >> 11) + 0.5) * 0x1p-53);
+        const T rad = sqrt((T)-2 * log(u1));
+        T sn, cs;  // the angle 2 pi u2, without a general range reduction
+        if constexpr (sizeof(T) == 4) sincospif((T)2 * u2, &sn, &cs);
+        else sincospi((T)2 * u2, &sn, &cs);
         g[2 * p] = rad * cs;
         g[2 * p + 1] = rad * sn;
     }
@@ -307,8 +311,8 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __re
 #pragma unroll
         for (int i = 0; i < E / 2; ++i) {
             const int grp = threadIdx.x + RW::THREADS * i;  // < 2 RPB N / 4
-            double gs[4];
-            group_gaussians(seed, stream, (blockbase >> 2) + grp, gs);
+            T gs[4];
+            group_gaussians<T>(seed, stream, (blockbase >> 2) + grp, gs);
             const int rr = (4 * grp) / N, pos = (4 * grp) % N;
             const int team = rr % RPB, part = rr / RPB;
 #pragma unroll
