@@ -1036,9 +1036,9 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yinv(const cpx<T>*
 // --------------------------------------------------------------------------
 template <typename T>
 struct ZJobs {
-    int fa[3], fb[3];  // S4 field indices (fb < 0: one field over two rows)
-    T* outa[3];
-    T* outb[3];
+    int fa[8], fb[8];  // S4 field indices (fb < 0: one field over two rows)
+    T* outa[8];
+    T* outb[8];
 };
 
 template <typename T, int N, int V>
@@ -1053,6 +1053,14 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zinv(const cpx<T>*
     __shared__ __align__(16) T lds[RPB * ROWE];
     constexpr int SROW = ROWE / 2;
     static_assert(SROW >= N / 2, "a staged row holds every kept kz");
+    // A block covers RPB rows (two fields) or 2 RPB rows (one field); the grid has
+    // N^2 / (2 RPB) blocks when every job is of the second kind, else N^2 / RPB, and
+    // blocks past the rows of their job leave before any barrier.
+    const int job = blockIdx.y;
+    const bool tworows = zj.fb[job] < 0;
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const size_t q0 = (size_t)blk * (tworows ? 2 * RPB : RPB);  // first row (x N + y) of the block
+    if (q0 >= (size_t)N * N) return;  // whole block leaves
     // twiddles in LDS for FP32 (this pass's LDS traffic is light), else from the cache
     constexpr bool LT = kLdsTwiddles<T> && true;
     __shared__ cpx<T> twl[LT ? PL::TW_ALLOC : 1];
@@ -1060,13 +1068,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zinv(const cpx<T>*
     __syncthreads();
     const Twiddles<T, PL, LT> tws{LT ? twl : tw};
     s4 = zptr(s4, zs);
-    const int job = blockIdx.y;
-    const bool tworows = zj.fb[job] < 0;
-    const uint32_t nblk = (uint32_t)((size_t)N * N / RPB);
-    const uint32_t blk = xcd_block(blockIdx.x, nblk);
-    if (tworows && blk >= nblk / 2) return;  // whole block leaves; no block barrier follows
     const int r = threadIdx.x / P, l = threadIdx.x % P;
-    const size_t q0 = (size_t)blk * (tworows ? 2 * RPB : RPB);  // first row (x N + y) of the block
     const int x = (int)(q0 / N), y0 = (int)(q0 % N);
     const cpx<T>* A = s4 + (size_t)zj.fa[job] * s4_field + (size_t)x * cd.Kz * N + y0;
     const cpx<T>* B = tworows ? A + RPB : s4 + (size_t)zj.fb[job] * s4_field + (size_t)x * cd.Kz * N + y0;
