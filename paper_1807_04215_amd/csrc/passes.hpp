@@ -241,15 +241,26 @@ struct ProductInputs {
     const T* u[4][3];  // u_1 .. u_{n-1}
 };
 
+// The 4 (NORD - 1) raw inputs of one cell: delta_m, u_m for m = 1 .. NORD - 1.
 template <typename T, int NORD>
-__device__ __forceinline__ void load_products(const ProductInputs<T>& pin, size_t blockbase, uint32_t off,
-                                              cpx<T>& a, cpx<T>& b) {
+__device__ __forceinline__ void load_raw(const ProductInputs<T>& pin, size_t blockbase, uint32_t off,
+                                         T (&raw)[4 * (NORD - 1)]) {
+#pragma unroll
+    for (int m = 1; m < NORD; ++m) {
+        raw[4 * (m - 1)] = ldo(pin.d[m - 1] + blockbase, off);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) raw[4 * (m - 1) + 1 + j] = ldo(pin.u[m - 1][j] + blockbase, off);
+    }
+}
+
+template <typename T, int NORD>
+__device__ __forceinline__ void combine_products(const T (&raw)[4 * (NORD - 1)], cpx<T>& a, cpx<T>& b) {
     T d[NORD], u[NORD][3];
 #pragma unroll
     for (int m = 1; m < NORD; ++m) {
-        d[m] = ldo(pin.d[m - 1] + blockbase, off);
+        d[m] = raw[4 * (m - 1)];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) u[m][j] = ldo(pin.u[m - 1][j] + blockbase, off);
+        for (int j = 0; j < 3; ++j) u[m][j] = raw[4 * (m - 1) + 1 + j];
     }
     T vx = 0, vy = 0, vz = 0, w = 0;
 #pragma unroll
@@ -337,11 +348,21 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __re
             if constexpr (SRC == 3) b[e] = {ldo(pin.d[2] + blockbase, o), ldo(pin.d[3] + blockbase, o)};
         }
     } else {
-        // the packed products are formed here, not after the first transform,
-        // so the raw inputs are dead before the FFTs start
+        // The packed products are formed here, not after the first transform, so the raw
+        // inputs are dead before the FFTs start.  The raw loads run DEPTH elements ahead of
+        // the products (about 48 values in flight per lane), so a wave waits for memory
+        // once per DEPTH elements rather than once per element.
+        constexpr int NR = 4 * (NORD - 1);
+        constexpr int DEPTH = (48 / NR) < 2 ? 2 : ((48 / NR) > 4 ? 4 : (48 / NR));
+        T raw[DEPTH][NR];
+#pragma unroll
+        for (int e = 0; e < DEPTH - 1; ++e) load_raw<T, NORD>(pin, blockbase, (uint32_t)(r * N + l + P * e), raw[e]);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            load_products<T, NORD>(pin, blockbase, (uint32_t)(r * N + l + P * e), a[e], b[e]);
+            if (e + DEPTH - 1 < E)
+                load_raw<T, NORD>(pin, blockbase, (uint32_t)(r * N + l + P * (e + DEPTH - 1)),
+                                  raw[(e + DEPTH - 1) % DEPTH]);
+            combine_products<T, NORD>(raw[e % DEPTH], a[e], b[e]);
             keep_here(a[e]);
             keep_here(b[e]);
         }
