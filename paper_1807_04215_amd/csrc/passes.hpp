@@ -401,14 +401,18 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __re
 
 // --------------------------------------------------------------------------
 // P2: y pass, forward.  Rows (x, kz) along y of S1; block = RPB consecutive
-// kz at one x (runs of RPB elements of S1); grid.y = field.  Keeps
-// |ky| <= Kc and writes S2 rows (kz, x) of Ky values.
+// kz at one x (one S1 tile); grid.y = j takes input field j in_step to output
+// field j out_step.  Keeps |ky| <= Kc and writes S2 rows (kz, x) of Ky values.
+// COMB (the products of an order, one launch with grid.y = 1; the steps are
+// unused): output field 1 is D = i (ky V_y + kz V_z) from inputs V_y, V_z (fields 1, 2).
+// i k.V is linear, so its y and z terms are summed here and the x pass needs one
+// field fewer; V_x and W go through a plain launch.
 // --------------------------------------------------------------------------
-template <typename T, int N, int V>
+template <typename T, int N, int V, bool COMB = false>
 __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yfwd(const cpx<T>* __restrict__ s1, size_t s1_field,
                                                                     cpx<T>* __restrict__ s2, size_t s2_field,
                                                                     const cpx<T>* __restrict__ tw, CubeDims cd,
-                                                                    size_t zs) {
+                                                                    size_t zs, int in_step, int out_step) {
     using RW = Rows<T, N, V>;
     using PL = typename RW::PL;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
@@ -431,15 +435,33 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yfwd(const cpx<T>*
     // the S1 tile holding kz0 .. kz0 + nrows - 1 (RPB divides the tile width TZ)
     constexpr int TZ = kTileZ<T, N>;
     const int tb = kz0 / TZ * TZ, w = min(TZ, cd.Kz - tb);
-    cpx<T> g[E];
-    gather_runs<T, N, V>(g, s1 + (size_t)blockIdx.y * s1_field + (size_t)x * N * cd.Kz + (size_t)tb * N + (kz0 - tb),
-                         (uint32_t)w, N, nrows);
+    auto transform = [&](int f, cpx<T>(&v)[E]) {
+        cpx<T> g[E];
+        gather_runs<T, N, V>(g, s1 + (size_t)f * s1_field + (size_t)x * N * cd.Kz + (size_t)tb * N + (kz0 - tb),
+                             (uint32_t)w, N, nrows);
+        scatter_runs_split<T, N, V>(g, lds, row, l, N, [](int q) { return q; }, [](int) { return true; }, v);
+        fft_row_split<PL, -1, T>(v, row, tws, l);
+    };
     cpx<T> v[E];
-    scatter_runs_split<T, N, V>(g, lds, row, l, N, [](int q) { return q; }, [](int) { return true; }, v);
-    fft_row_split<PL, -1, T>(v, row, tws, l);
+    const int fout = COMB ? 1 : (int)blockIdx.y * out_step;
+    if constexpr (!COMB) {
+        transform((int)blockIdx.y * in_step, v);
+    } else {
+        // D = i ky V_y + i kz V_z (inputs 1 and 2), the y and z terms of i k.V (integer
+        // ky, kz; the x pass adds i kx V_x and applies kF)
+        cpx<T> vz[E];
+        transform(1, v);
+        transform(2, vz);
+        const T kz = (T)(kz0 + r);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const T ky = (T)signed_pos(l + P * e, N);
+            v[e] = cmul_i(cpx<T>{ky * v[e].x + kz * vz[e].x, ky * v[e].y + kz * vz[e].y});
+        }
+    }
     // S2 row (kz0 + r, x): the kept ky in compact order
     if (r < nrows) {
-        cpx<T>* out = s2 + (size_t)blockIdx.y * s2_field + ((size_t)kz0 * N + x) * cd.Ky;
+        cpx<T>* out = s2 + (size_t)fout * s2_field + ((size_t)kz0 * N + x) * cd.Ky;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int ic = pos_to_compact(l + P * e, cd.Kc, N);
@@ -530,7 +552,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
     // k-space step: sd holds delta_n(k), st holds theta_n(k) afterwards
     cpx<T> sd[E], st[E];
     constexpr bool ADJ = MODE == XM_ADJ || MODE == XM_ADJ1;
-    constexpr int NIN = (MODE == XM_ORDER || ADJ) ? 4 : (MODE == XM_PFORM ? 2 : 1);
+    constexpr int NIN = MODE == XM_ORDER ? 3 : (ADJ ? 4 : (MODE == XM_PFORM ? 2 : 1));
 #pragma unroll
     for (int e = 0; e < E; ++e) sd[e] = st[e] = {(T)0, (T)0};
     // |n|^2 <= 3 (N/2)^2 and every mask lies below (N/2)^2: 32-bit integers are exact here
@@ -575,14 +597,14 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
         if constexpr (!ADJ && f + 1 < NIN) gather_field(f + 1, g);
         fft_row<PL, -1, T>(v, row, tws, l);
         if constexpr (MODE == XM_ORDER) {
-            if constexpr (f < 3) {
-                // S_delta += i k_f V_f(k)  (kF and N^-3 applied below)
+            // inputs V_x, D = i (ky V_y + kz V_z) (formed by the y pass), W
+            if constexpr (f == 0) {
+                // S_delta = i kx V_x + D  (kF and N^-3 applied below)
 #pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const int kx = signed_pos(l + P * e, N);
-                    const T kf = (T)(f == 0 ? kx : (f == 1 ? ky : kz));
-                    sd[e] = cadd(sd[e], cscale(cmul_i(v[e]), kf));
-                }
+                for (int e = 0; e < E; ++e) sd[e] = cscale(cmul_i(v[e]), (T)signed_pos(l + P * e, N));
+            } else if constexpr (f == 1) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) sd[e] = cadd(sd[e], v[e]);
             } else {
 #pragma unroll
                 for (int e = 0; e < E; ++e) st[e] = v[e];

@@ -190,7 +190,24 @@ struct Pipe {
             return launch(c, KD_YFWD, bytes, dim3((unsigned)(N * ((d.Kz + RW::RPB - 1) / RW::RPB)), nf, nz()),
                           dim3(RW::THREADS), 0,
                           k_yfwd<T, N, V>, (const cpx<T>*)A(), (size_t)L.a_field_s1, B(), (size_t)L.b_field_s2,
-                          (const cpx<T>*)tw(), cd, bt.zs);
+                          (const cpx<T>*)tw(), cd, bt.zs, 1, 1);
+        });
+    }
+
+    // P2 for the products of an order: S1 fields V_x, V_y, V_z, W (A) -> S2 fields
+    // V_x, i (ky V_y + kz V_z), W (B); V_x and W in one plain launch (inputs 0, 3
+    // to outputs 0, 2), the combined field in its own
+    int yfwd_products() {
+        return with_variant<T, N>(tu.v[KD_YFWD], [&](auto vc) {
+            constexpr int V = decltype(vc)::value;
+            using RW = Rows<T, N, V>;
+            const dim3 grid((unsigned)(N * ((d.Kz + RW::RPB - 1) / RW::RPB)), 2, nz()), block(RW::THREADS);
+            GRIDSPT_CHECK(launch(c, KD_YFWD, nb() * 2.0 * (d.s1() + d.s2()) * d.cpx_bytes, grid, block, 0,
+                                 k_yfwd<T, N, V>, (const cpx<T>*)A(), (size_t)L.a_field_s1, B(),
+                                 (size_t)L.b_field_s2, (const cpx<T>*)tw(), cd, bt.zs, 3, 2));
+            return launch(c, KD_YFWD, nb() * (2.0 * d.s1() + d.s2()) * d.cpx_bytes, dim3(grid.x, 1, nz()), block, 0,
+                          k_yfwd<T, N, V, true>, (const cpx<T>*)A(), (size_t)L.a_field_s1, B(), (size_t)L.b_field_s2,
+                          (const cpx<T>*)tw(), cd, bt.zs, 0, 0);
         });
     }
 
@@ -211,7 +228,7 @@ struct Pipe {
         return with_variant<T, N>(tu.v[kind], [&](auto vc) {
             constexpr int V = decltype(vc)::value;
             using RW = Rows<T, N, V>;
-            const int nin = mode == XM_ORDER ? 4 : ((mode == XM_ADJ || mode == XM_ADJ1) ? a.nin : (mode == XM_PFORM ? 2 : 1));
+            const int nin = mode == XM_ORDER ? 3 : ((mode == XM_ADJ || mode == XM_ADJ1) ? a.nin : (mode == XM_PFORM ? 2 : 1));
             const int ncube = (a.cube_d ? 1 : 0) + (a.cube_t ? 1 : 0);
             const double bytes =
                 nb() * ((double)nin * d.s2() + (double)a.nout * d.s3() + (double)ncube * d.cube()) * d.cpx_bytes;
@@ -387,7 +404,7 @@ int run_orders(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, i
             for (int j = 0; j < 3; ++j) pin.u[m - 1][j] = p.U(m, j);
         }
         GRIDSPT_CHECK(p.zfwd_products(n, pin));
-        GRIDSPT_CHECK(p.yfwd(4));
+        GRIDSPT_CHECK(p.yfwd_products());
         const int nout = n < nmax ? 5 : 2;
         XArgs<T> a = make_xargs<T>(p.d, g, n, nout, n2max2, dk(n - 1), tk(n - 1));
         GRIDSPT_CHECK(p.xfused(XM_ORDER, a));
