@@ -216,7 +216,7 @@ __global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T>
                 dst[a.npairs + 1] += v[QP + 1];
             }
         };
-        constexpr int U = TRI > 0 ? 2 : 1;  // the pair path holds two loads per pair already
+        constexpr int U = TRI > 0 ? 3 : 1;  // the pair path holds two loads per pair already
         for (int c0 = c_begin; c0 < c_end; c0 += 64 * U) {
             Chunk ch[U];
 #pragma unroll
