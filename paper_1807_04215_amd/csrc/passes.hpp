@@ -1071,17 +1071,16 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yinv(const cpx<T>*
 }
 
 // --------------------------------------------------------------------------
-// P5: z pass, inverse to real.  Rows (x, y) along kz of S4 (Kz values); a
-// block holds runs of consecutive y at one x.  Job j pairs either two fields
-// of the same row (fb[j] >= 0; block = RPB rows) or one field of two rows y
-// and y + RPB (fb[j] < 0; block = 2 RPB rows, and the second half of the grid
-// idles).  grid.y = job.
+// P5: z pass, inverse to real.  Rows (x, y) along kz of S4 (Kz values).  Job
+// j (grid.y) is S4 field f[j] into the real field out[j]; a block holds 2 RPB
+// consecutive y at one x, and each complex transform carries rows y and
+// y + RPB as its real and imaginary parts, so the block loads runs of 2 RPB
+// consecutive y (whole cache lines).  grid.x = N^2 / (2 RPB).
 // --------------------------------------------------------------------------
 template <typename T>
 struct ZJobs {
-    int fa[8], fb[8];  // S4 field indices (fb < 0: one field over two rows)
-    T* outa[8];
-    T* outb[8];
+    int f[8];  // S4 field indices
+    T* out[8];
 };
 
 template <typename T, int N, int V>
@@ -1096,14 +1095,9 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zinv(const cpx<T>*
     __shared__ __align__(16) T lds[RPB * ROWE];
     constexpr int SROW = ROWE / 2;
     static_assert(SROW >= N / 2, "a staged row holds every kept kz");
-    // A block covers RPB rows (two fields) or 2 RPB rows (one field); the grid has
-    // N^2 / (2 RPB) blocks when every job is of the second kind, else N^2 / RPB, and
-    // blocks past the rows of their job leave before any barrier.
     const int job = blockIdx.y;
-    const bool tworows = zj.fb[job] < 0;
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const size_t q0 = (size_t)blk * (tworows ? 2 * RPB : RPB);  // first row (x N + y) of the block
-    if (q0 >= (size_t)N * N) return;  // whole block leaves
+    const size_t q0 = (size_t)blk * 2 * RPB;  // first row (x N + y) of the block
     // twiddles in LDS for FP32 (this pass's LDS traffic is light), else from the cache
     constexpr bool LT = kLdsTwiddles<T> && true;
     __shared__ cpx<T> twl[LT ? PL::TW_ALLOC : 1];
@@ -1113,10 +1107,10 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zinv(const cpx<T>*
     s4 = zptr(s4, zs);
     const int r = threadIdx.x / P, l = threadIdx.x % P;
     const int x = (int)(q0 / N), y0 = (int)(q0 % N);
-    const cpx<T>* A = s4 + (size_t)zj.fa[job] * s4_field + (size_t)x * cd.Kz * N + y0;
-    const cpx<T>* B = tworows ? A + RPB : s4 + (size_t)zj.fb[job] * s4_field + (size_t)x * cd.Kz * N + y0;
+    const cpx<T>* A = s4 + (size_t)zj.f[job] * s4_field + (size_t)x * cd.Kz * N + y0;  // rows y0 + r
+    const cpx<T>* B = A + RPB;                                                          // rows y0 + RPB + r
     T* row = lds + r * ROWE;
-    // runs of RPB y for every kz (Kz <= N / 2, so E / 2 items per thread), all loads first
+    // runs of RPB y for every kz, twice (Kz <= N / 2, so E / 2 items per thread), all loads first
     constexpr int IT = E / 2;
     cpx<T> ga[IT], gb[IT];
     gather_runs<T, N, V>(ga, A, (uint32_t)N, cd.Kz, RPB);
@@ -1150,13 +1144,11 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zinv(const cpx<T>*
     }
     __syncthreads();  // every wave has read the staged runs before the exchanges reuse the LDS
     fft_row_split<PL, +1, T>(v, row, tws, l);
-    T* oa = zptr(zj.outa[job], zs) + q0 * N;
-    T* ob = zptr(tworows ? zj.outa[job] : zj.outb[job], zs) + q0 * N;
-    const uint32_t wa = (uint32_t)(r * N), wb = (uint32_t)((tworows ? r + RPB : r) * N);
+    T* out = zptr(zj.out[job], zs) + q0 * N;
 #pragma unroll
-    for (int e = 0; e < E; ++e) sto(oa, wa + (uint32_t)(l + P * e), v[e].x);
+    for (int e = 0; e < E; ++e) sto(out, (uint32_t)(r * N + l + P * e), v[e].x);
 #pragma unroll
-    for (int e = 0; e < E; ++e) sto(ob, wb + (uint32_t)(l + P * e), v[e].y);
+    for (int e = 0; e < E; ++e) sto(out, (uint32_t)((r + RPB) * N + l + P * e), v[e].y);
 }
 
 }  // namespace gridspt

@@ -287,32 +287,23 @@ struct Pipe {
         return with_variant<T, N>(tu.v[KD_ZINV], [&](auto vc) {
             constexpr int V = decltype(vc)::value;
             using RW = Rows<T, N, V>;
-            int nout = 0, npair = 0;
-            for (int i = 0; i < njobs; ++i) {
-                nout += zj.fb[i] >= 0 ? 2 : 1;
-                npair += zj.fb[i] >= 0 ? 1 : 0;
-            }
             const double bytes =
-                nb() * nout * ((double)N * N * cd.Kz * d.cpx_bytes + (double)d.ncell() * d.real_bytes);
-            const unsigned gx = (unsigned)(N * N / RW::RPB / (npair ? 1 : 2));
-            return launch(c, KD_ZINV, bytes, dim3(gx, njobs, nz()), dim3(RW::THREADS), 0,
-                          k_zinv<T, N, V>, (const cpx<T>*)B(), (size_t)L.b_field_s4, zj, (const cpx<T>*)tw(), cd,
-                          bt.zs);
+                nb() * njobs * ((double)N * N * cd.Kz * d.cpx_bytes + (double)d.ncell() * d.real_bytes);
+            return launch(c, KD_ZINV, bytes, dim3((unsigned)(N * N / (2 * RW::RPB)), njobs, nz()),
+                          dim3(RW::THREADS), 0, k_zinv<T, N, V>, (const cpx<T>*)B(), (size_t)L.b_field_s4, zj,
+                          (const cpx<T>*)tw(), cd, bt.zs);
         });
     }
 
-    // P4 + P5 for nf <= 8 fields of S3 into real outputs out[0..nf-1]: each
-    // field two rows at a time, so a block reads runs of 2 RPB consecutive y
-    // (whole cache lines) rather than two fields' runs of RPB
+    // P4 + P5 for nf <= 8 fields of S3 into real outputs out[0..nf-1], one z
+    // inverse job per field
     int to_real(int nf, T* const* out) {
         if (nf < 1 || nf > 8) return GRIDSPT_EINVAL;
         GRIDSPT_CHECK(yinv(nf));
         ZJobs<T> zj{};
         for (int i = 0; i < nf; ++i) {
-            zj.fa[i] = i;
-            zj.fb[i] = -1;
-            zj.outa[i] = out[i];
-            zj.outb[i] = nullptr;
+            zj.f[i] = i;
+            zj.out[i] = out[i];
         }
         return zinv(zj, nf);
     }
