@@ -38,8 +38,6 @@ __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
 }
 template <typename T>
 __device__ __forceinline__ cpx<T> cscale(cpx<T> a, T s) { return {a.x * s, a.y * s}; }
-template <typename T>
-__device__ __forceinline__ cpx<T> cconj(cpx<T> a) { return {a.x, -a.y}; }
 // multiply by +i
 template <typename T>
 __device__ __forceinline__ cpx<T> cmul_i(cpx<T> a) { return {-a.y, a.x}; }
