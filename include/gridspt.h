@@ -221,6 +221,14 @@ int gridspt_orders_linear(gridspt_ctx* ctx, const gridspt_grid* g, const gridspt
 int gridspt_tune_orders(gridspt_ctx* ctx, const gridspt_grid* g, const gridspt_linpk* lp, int32_t nmax,
                         int64_t n2max2, void* const* delta, void* const* theta, void* const* delta_k,
                         void* const* theta_k, void* work, int64_t work_bytes);
+/* Pins launch variant `variant` for every pass kind of grids of g's size and
+ * precision in this context, replacing any autotuner choice.  The variant
+ * changes only block shapes and radix splits, never results beyond rounding.
+ * Variant 0 is always compiled; FP32 N = 64 .. 1024 (powers of two) also have
+ * 1, 4, 5 and FP32 N = 96, 192, 384 have 1, 2.  Returns GRIDSPT_EINVAL for a
+ * variant not compiled for the grid. */
+int gridspt_set_tuning(gridspt_ctx* ctx, const gridspt_grid* g, int32_t variant);
+
 /* The context's choice per tuned pass kind for grid g (variant 0 when not
  * tuned), with the tuner's time; names as for gridspt_profile_read. */
 int gridspt_tuning(const gridspt_ctx* ctx, const gridspt_grid* g, int32_t max, char* names, int32_t* variant,

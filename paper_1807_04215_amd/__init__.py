@@ -103,6 +103,7 @@ def lib():
                                       ctypes.c_int),
             "gridspt_tune_orders": ([vp, gp, ctypes.POINTER(_LinPk), i32, i64, vp, vp, vp, vp, vp, i64], ctypes.c_int),
             "gridspt_tuning": ([vp, gp, i32, vp, vp, vp], ctypes.c_int),
+            "gridspt_set_tuning": ([vp, gp, i32], ctypes.c_int),
             "gridspt_pform_workspace_bytes": ([gp, i32], i64),
             "gridspt_orders_pform": ([vp, gp, i32, i64, i64, vp, vp, vp, vp, vp, vp, i64], ctypes.c_int),
             "gridspt_smooth": ([vp, gp, i32, vp, vp, i32, dbl, vp, vp, i64], ctypes.c_int),
@@ -413,6 +414,12 @@ def orders_linear(ctx: Context, grid: Grid, lp: LinearSpectrum, nmax: int, n2max
     _check(lib().gridspt_orders_linear(ctx.handle, ctypes.byref(g), ctypes.byref(c), nmax, n2max2, d, t, dk, tk,
                                        _ptr(ws), ws.numel()), "orders_linear")
     return out
+
+
+def set_tuning(ctx: Context, grid: Grid, variant: int) -> None:
+    """Pin launch variant `variant` for every pass of this grid's size and precision."""
+    g = grid.cstruct
+    _check(lib().gridspt_set_tuning(ctx.handle, ctypes.byref(g), int(variant)), "set_tuning")
 
 
 def tune_orders(ctx: Context, grid: Grid, lp: LinearSpectrum, nmax: int, n2max2: int,

@@ -763,6 +763,28 @@ int gridspt_tune_orders(gridspt_ctx* c, const gridspt_grid* g, const gridspt_lin
     return nv;
 }
 
+int gridspt_set_tuning(gridspt_ctx* c, const gridspt_grid* g, int32_t variant) {
+    if (!c) return GRIDSPT_EINVAL;
+    CHECK(check_grid(g));
+    int vl[8];
+    const int nv = variant_list(g->dtype, g->n, vl);
+    bool ok = false;
+    for (int i = 0; i < nv; ++i) ok = ok || vl[i] == variant;
+    if (!ok) return GRIDSPT_EINVAL;
+    gridspt_ctx::Tuned t{g->n, g->dtype, Tuning{}, {}};
+    for (int k = 0; k < KD_COUNT; ++k) {
+        t.tu.v[k] = variant;
+        t.ms[k] = 0.0;
+    }
+    for (auto& x : c->tuned)
+        if (x.n == g->n && x.dtype == g->dtype) {
+            x = t;
+            return GRIDSPT_OK;
+        }
+    c->tuned.push_back(t);
+    return GRIDSPT_OK;
+}
+
 int gridspt_tuning(const gridspt_ctx* c, const gridspt_grid* g, int32_t max, char* names, int32_t* variant,
                    double* ms) {
     if (!c || !g || max < 0) return GRIDSPT_EINVAL;

@@ -150,6 +150,35 @@ def test_validation_before_any_gpu_work():
         lib.gridspt_destroy(h)
 
 
+def test_set_tuning_accepts_only_compiled_variants():
+    """gridspt_set_tuning pins a compiled launch variant (host-side bookkeeping, no GPU work)."""
+    lib = g.lib()
+    h = ctypes.c_void_p()
+    assert lib.gridspt_create(ctypes.byref(h), None) == 0
+    try:
+        f32_64 = _grid(n=64, kc=21, dtype=g.F32)
+        f64_64 = _grid(n=64, kc=21, dtype=g.F64)
+        f32_96 = _grid(n=96, kc=31, dtype=g.F32)
+        f32_48 = _grid(n=48, kc=15, dtype=g.F32)
+        assert lib.gridspt_set_tuning(None, ctypes.byref(f32_64), 0) == -1
+        for v, want in ((0, 0), (1, 0), (4, 0), (5, 0), (2, -1), (3, -1), (8, -1)):
+            assert lib.gridspt_set_tuning(h, ctypes.byref(f32_64), v) == want, v
+        assert lib.gridspt_set_tuning(h, ctypes.byref(f64_64), 1) == -1
+        assert lib.gridspt_set_tuning(h, ctypes.byref(f32_96), 2) == 0
+        assert lib.gridspt_set_tuning(h, ctypes.byref(f32_96), 4) == -1
+        assert lib.gridspt_set_tuning(h, ctypes.byref(f32_48), 1) == -1
+        assert lib.gridspt_set_tuning(h, ctypes.byref(_grid(n=63)), 0) == -1
+        # the pinned variant is what the context reports for every tuned pass kind
+        assert lib.gridspt_set_tuning(h, ctypes.byref(f32_64), 5) == 0
+        var = (ctypes.c_int32 * 16)()
+        k = lib.gridspt_tuning(h, ctypes.byref(f32_64), 16, None, var, None)
+        assert k > 0 and all(var[i] == 5 for i in range(k))
+        k = lib.gridspt_tuning(h, ctypes.byref(f32_96), 16, None, var, None)
+        assert k > 0 and all(var[i] == 2 for i in range(k))
+    finally:
+        lib.gridspt_destroy(h)
+
+
 def test_workspace_sizes_follow_layout():
     G = _grid(n=1024, kc=341, dtype=0, box=2000.0)
     n, kz, ky = 1024, 342, 683
