@@ -634,7 +634,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
                     const int kx = signed_pos(l + P * e, N);
                     const int n2 = kx * kx + ky * ky + kz * kz;
                     const int kf = f == 1 ? kx : (f == 2 ? ky : kz);
-                    const T s = n2 > 0 ? (T)kf / (kF * (T)n2) : (T)0;
+                    const T s = n2 > 0 ? (T)((double)kf / (a.kF * (double)n2)) : (T)0;
                     st[e] = cadd(st[e], cpx<T>{-v[e].y * s, v[e].x * s});
                 }
             }
@@ -722,11 +722,11 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
                     for (int e = 0; e < E; ++e) {
                         const int kx = signed_pos(l + P * e, N);
                         if constexpr (o < 3) {
-                            const T kj = kF * (T)(o == 0 ? kx : (o == 1 ? ky : kz));
+                            const T kj = (T)(a.kF * (double)(o == 0 ? kx : (o == 1 ? ky : kz)));
                             v[e] = {sd[e].y * kj, -sd[e].x * kj};
                         } else {
                             const int n2 = kx * kx + ky * ky + kz * kz;
-                            v[e] = cscale(st[e], (T)(-0.5) * kF * kF * (T)n2);
+                            v[e] = cscale(st[e], (T)(-0.5 * a.kF * a.kF * (double)n2));
                         }
                     }
                 } else if constexpr (MODE == XM_ADJ1) {
@@ -736,21 +736,16 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
 #pragma unroll
                     for (int e = 0; e < E; ++e) v[e] = (o == 0) ? sd[e] : st[e];
                 } else {
-                    // u_j(k) = (-i k_j / k^2) theta(k).  theta is no longer an output from here on,
-                    // so st becomes theta / (kF n^2) in place before the first component.
+                    // u_j(k) = (-i k_j / k^2) theta(k); the factor k_j / (kF n^2) is formed in FP64
+                    // and rounded once (u feeds every later order's products)
                     constexpr int comp = o - FIRST_U;
-                    if constexpr (comp == 0) {
-#pragma unroll
-                        for (int e = 0; e < E; ++e) {
-                            const int kx = signed_pos(l + P * e, N);
-                            const int n2 = kx * kx + ky * ky + kz * kz;
-                            st[e] = cscale(st[e], n2 > 0 ? (T)1 / (kF * (T)n2) : (T)0);
-                        }
-                    }
 #pragma unroll
                     for (int e = 0; e < E; ++e) {
-                        const T kj = (T)(comp == 0 ? signed_pos(l + P * e, N) : (comp == 1 ? ky : kz));
-                        v[e] = {st[e].y * kj, -st[e].x * kj};
+                        const int kx = signed_pos(l + P * e, N);
+                        const int n2 = kx * kx + ky * ky + kz * kz;
+                        const int kj = comp == 0 ? kx : (comp == 1 ? ky : kz);
+                        const T s = n2 > 0 ? (T)((double)kj / (a.kF * (double)n2)) : (T)0;
+                        v[e] = {st[e].y * s, -st[e].x * s};
                     }
                 }
                 x_inverse_store<T, N, V>(v, row, tws, l, a.s3 + (size_t)o * a.s3_field + outbase, r, active);
@@ -878,7 +873,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xregen(RegenArgs<T
                 const int kx = signed_pos(p, N);
                 const int n2 = kx * kx + ky * ky + kz * kz;
                 const int kj = o == 1 ? kx : (o == 2 ? ky : kz);
-                const T sc = n2 > 0 ? (T)kj / ((T)a.kF * (T)n2) : (T)0;
+                const T sc = n2 > 0 ? (T)((double)kj / (a.kF * (double)n2)) : (T)0;
                 v[e] = {t.y * sc, -t.x * sc};
             }
         }
@@ -933,16 +928,16 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xderived(RegenArgs
             auto kc = [&](int axis) { return axis == 0 ? kx : (axis == 1 ? ky : kz); };
             const int n2 = kx * kx + ky * ky + kz * kz;
             if constexpr (fld < 6) {  // i k_j F
-                const T kj = (T)a.kF * (T)kc(fld % 3);
+                const T kj = (T)(a.kF * (double)kc(fld % 3));
                 v[e] = {-src.y * kj, src.x * kj};
             } else if constexpr (fld < 9) {  // (-i k_j / k^2) F
-                const T sc = n2 > 0 ? (T)kc(fld - 6) / ((T)a.kF * (T)n2) : (T)0;
+                const T sc = n2 > 0 ? (T)((double)kc(fld - 6) / (a.kF * (double)n2)) : (T)0;
                 v[e] = {src.y * sc, -src.x * sc};
             } else {  // (k_i k_j / k^2) F
                 constexpr int q = fld - 9;
                 constexpr int i = q < 3 ? q : (q < 5 ? 0 : 1);
                 constexpr int j = q < 3 ? q : (q == 3 ? 1 : 2);
-                const T sc = n2 > 0 ? (T)(kc(i) * kc(j)) / (T)n2 : (T)0;
+                const T sc = n2 > 0 ? (T)((double)kc(i) * (double)kc(j) / (double)n2) : (T)0;
                 v[e] = cscale(src, sc);
             }
         }
