@@ -621,7 +621,7 @@ template <typename T>
 struct HistArgs {
     const T* f[kStatsMaxFields];
     int nbins;       // per axis
-    int joint;       // 0: histogram of field blockIdx.y; 1: joint of field 0 and field 1 + blockIdx.y
+    int joint;       // set by the caller for k_hist_partial<T, true>: joint of field 0 and field 1 + blockIdx.y
     double lo, scale;
     size_t ncell;
     uint32_t* partial;  // [gridDim.y][gridDim.x][nb], nb = nbins or nbins^2
@@ -633,26 +633,67 @@ __device__ __forceinline__ int bin_of(T x, double lo, double scale, int nbins) {
     return (fb >= 0.0 && fb < (double)nbins) ? (int)fb : -1;
 }
 
-template <typename T>
+// Each wavefront counts into its own LDS histogram (fewer lanes collide on one
+// bin's atomic), the block adds its wavefronts' counts at the end; counts are
+// integers, so the order does not matter.  A thread takes 16 bytes of
+// consecutive cells per step (the tail, if any, one cell at a time).
+template <typename T, bool JOINT>
 __global__ __launch_bounds__(kStatsThreads) void k_hist_partial(HistArgs<T> a) {
-    extern __shared__ uint32_t h[];
-    const int nb = a.joint ? a.nbins * a.nbins : a.nbins;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) h[i] = 0u;
+    extern __shared__ uint32_t h[];  // [waves][nb]
+    constexpr int NW = kStatsThreads / 64;
+    const int nb = JOINT ? a.nbins * a.nbins : a.nbins;
+    for (int i = threadIdx.x; i < NW * nb; i += blockDim.x) h[i] = 0u;
     __syncthreads();
-    const T* x = a.joint ? a.f[0] : a.f[blockIdx.y];
-    const T* y = a.joint ? a.f[1 + blockIdx.y] : nullptr;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell; c += stride) {
-        int b = bin_of(x[c], a.lo, a.scale, a.nbins);
-        if (a.joint && b >= 0) {
-            const int b2 = bin_of(y[c], a.lo, a.scale, a.nbins);
+    uint32_t* hw = h + (threadIdx.x / 64) * nb;
+    const T* x = JOINT ? a.f[0] : a.f[blockIdx.y];
+    const T* y = JOINT ? a.f[1 + blockIdx.y] : nullptr;
+    auto count = [&](T xv, T yv) {
+        int b = bin_of(xv, a.lo, a.scale, a.nbins);
+        if (JOINT && b >= 0) {
+            const int b2 = bin_of(yv, a.lo, a.scale, a.nbins);
             b = b2 >= 0 ? b * a.nbins + b2 : -1;
         }
-        if (b >= 0) atomicAdd(&h[b], 1u);
+        if (b >= 0) atomicAdd(&hw[b], 1u);
+    };
+    // U vectors per thread per step, all loaded before the first is counted
+    constexpr int VW = 16 / (int)sizeof(T), U = 4;
+    using Vec = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    const size_t stride = (size_t)gridDim.x * blockDim.x, nv = a.ncell / VW, nstep = nv / (U * stride);
+    const Vec* xv = reinterpret_cast<const Vec*>(x);
+    const Vec* yv = reinterpret_cast<const Vec*>(y);
+    const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (size_t s = 0; s < nstep; ++s) {
+        Vec vx[U], vy[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            vx[u] = xv[(s * U + u) * stride + t0];
+            vy[u] = JOINT ? yv[(s * U + u) * stride + t0] : vx[u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const T* px = reinterpret_cast<const T*>(&vx[u]);
+            const T* py = reinterpret_cast<const T*>(&vy[u]);
+#pragma unroll
+            for (int k = 0; k < VW; ++k) count(px[k], py[k]);
+        }
     }
+    // the remaining vectors one at a time, then the cells past the last whole vector
+    for (size_t c = nstep * U * stride + t0; c < nv; c += stride) {
+        const Vec vx = xv[c], vy = JOINT ? yv[c] : vx;
+        const T* px = reinterpret_cast<const T*>(&vx);
+        const T* py = reinterpret_cast<const T*>(&vy);
+#pragma unroll
+        for (int k = 0; k < VW; ++k) count(px[k], py[k]);
+    }
+    for (size_t c = nv * VW + t0; c < a.ncell; c += stride) count(x[c], JOINT ? y[c] : x[c]);
     __syncthreads();
     uint32_t* out = a.partial + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * nb;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) out[i] = h[i];
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        uint32_t t = 0u;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t += h[w * nb + i];
+        out[i] = t;
+    }
 }
 
 // counts[y][bin] = sum over blocks (exact integers), as doubles

@@ -984,7 +984,7 @@ int gridspt_field_stats(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, 
             h.scale = (double)nbins / (hi - lo);
             h.partial = hpart;
             CHECK(launch(c, KD_HIST, (double)nfields * ncell * d.real_bytes, dim3(kHistBlocks, nfields),
-                         dim3(kStatsThreads), (size_t)nbins * 4, k_hist_partial<T>, h));
+                         dim3(kStatsThreads), (size_t)nbins * 4 * (kStatsThreads / 64), k_hist_partial<T, false>, h));
             CHECK(launch(c, KD_HIST, 0.0, dim3((nfields * nbins + 255) / 256), dim3(256), 0, k_hist_reduce,
                          (const uint32_t*)hpart, kHistBlocks, nbins, (int)nfields, counts));
         }
@@ -995,7 +995,7 @@ int gridspt_field_stats(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, 
             h.scale = (double)nbins2 / (hi - lo);
             h.partial = jpart;
             CHECK(launch(c, KD_HIST, 2.0 * (nfields - 1) * ncell * d.real_bytes, dim3(kHistBlocks, nfields - 1),
-                         dim3(kStatsThreads), (size_t)nb2 * 4, k_hist_partial<T>, h));
+                         dim3(kStatsThreads), (size_t)nb2 * 4 * (kStatsThreads / 64), k_hist_partial<T, true>, h));
             CHECK(launch(c, KD_HIST, 0.0, dim3(((nfields - 1) * nb2 + 255) / 256), dim3(256), 0, k_hist_reduce,
                          (const uint32_t*)jpart, kHistBlocks, nb2, (int)(nfields - 1), joint));
         }
