@@ -696,14 +696,34 @@ __global__ __launch_bounds__(kStatsThreads) void k_hist_partial(HistArgs<T> a) {
     }
 }
 
-// counts[y][bin] = sum over blocks (exact integers), as doubles
-static __global__ void k_hist_reduce(const uint32_t* partial, int nblocks, int nb, int ny, double* counts) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nb * ny) return;
-    const int y = t / nb, b = t % nb;
+// counts[y][bin] = sum over blocks (exact integers), as doubles.  Block
+// (kHistRedBins, kHistRedSlices): lane x owns one bin of this block's run of
+// kHistRedBins bins (coalesced reads along the partial rows), row w sums the
+// partial blocks w, w + kHistRedSlices, ...; the slices meet in LDS.
+constexpr int kHistRedBins = 64, kHistRedSlices = 16;
+static __global__ __launch_bounds__(kHistRedBins* kHistRedSlices) void k_hist_reduce(const uint32_t* partial,
+                                                                                     int nblocks, int nb,
+                                                                                     double* counts) {
+    __shared__ uint64_t part[kHistRedSlices][kHistRedBins];
+    const int b = blockIdx.x * kHistRedBins + threadIdx.x, y = blockIdx.y, w = threadIdx.y;
+    const int bc = b < nb ? b : nb - 1;
+    const uint32_t* p = partial + (size_t)y * nblocks * nb + bc;
     uint64_t s = 0;
-    for (int i = 0; i < nblocks; ++i) s += partial[((size_t)y * nblocks + i) * nb + b];
-    counts[t] = (double)s;
+    int i = w;
+    for (; i + 3 * kHistRedSlices < nblocks; i += 4 * kHistRedSlices) {
+        const uint32_t v0 = p[(size_t)i * nb], v1 = p[(size_t)(i + kHistRedSlices) * nb];
+        const uint32_t v2 = p[(size_t)(i + 2 * kHistRedSlices) * nb], v3 = p[(size_t)(i + 3 * kHistRedSlices) * nb];
+        s += (uint64_t)v0 + v1 + v2 + v3;
+    }
+    for (; i < nblocks; i += kHistRedSlices) s += p[(size_t)i * nb];
+    part[w][threadIdx.x] = s;
+    __syncthreads();
+    if (w == 0 && b < nb) {
+        uint64_t t = 0;
+#pragma unroll
+        for (int j = 0; j < kHistRedSlices; ++j) t += part[j][threadIdx.x];
+        counts[(size_t)y * nb + b] = (double)t;
+    }
 }
 
 // Mean and sample standard deviation over nreal realisations of `count`

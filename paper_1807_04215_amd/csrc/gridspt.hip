@@ -985,8 +985,9 @@ int gridspt_field_stats(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, 
             h.partial = hpart;
             CHECK(launch(c, KD_HIST, (double)nfields * ncell * d.real_bytes, dim3(kHistBlocks, nfields),
                          dim3(kStatsThreads), (size_t)nbins * 4 * (kStatsThreads / 64), k_hist_partial<T, false>, h));
-            CHECK(launch(c, KD_HIST, 0.0, dim3((nfields * nbins + 255) / 256), dim3(256), 0, k_hist_reduce,
-                         (const uint32_t*)hpart, kHistBlocks, nbins, (int)nfields, counts));
+            CHECK(launch(c, KD_HIST, 0.0, dim3((nbins + kHistRedBins - 1) / kHistRedBins, nfields),
+                         dim3(kHistRedBins, kHistRedSlices), 0, k_hist_reduce, (const uint32_t*)hpart, kHistBlocks,
+                         nbins, counts));
         }
         if (joint) {
             const int nb2 = nbins2 * nbins2;
@@ -996,8 +997,9 @@ int gridspt_field_stats(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, 
             h.partial = jpart;
             CHECK(launch(c, KD_HIST, 2.0 * (nfields - 1) * ncell * d.real_bytes, dim3(kHistBlocks, nfields - 1),
                          dim3(kStatsThreads), (size_t)nb2 * 4 * (kStatsThreads / 64), k_hist_partial<T, true>, h));
-            CHECK(launch(c, KD_HIST, 0.0, dim3(((nfields - 1) * nb2 + 255) / 256), dim3(256), 0, k_hist_reduce,
-                         (const uint32_t*)jpart, kHistBlocks, nb2, (int)(nfields - 1), joint));
+            CHECK(launch(c, KD_HIST, 0.0, dim3((nb2 + kHistRedBins - 1) / kHistRedBins, nfields - 1),
+                         dim3(kHistRedBins, kHistRedSlices), 0, k_hist_reduce, (const uint32_t*)jpart, kHistBlocks,
+                         nb2, joint));
         }
         return GRIDSPT_OK;
     };

@@ -274,6 +274,51 @@ __device__ __forceinline__ void combine_products(const T (&raw)[4 * (NORD - 1)],
     b = {vz, w};
 }
 
+// Forward z transforms of a block's packed rows and the read-out of their kept
+// kz into S1 tiles.  NPACK transforms per row (a, then b).  PACK4: every row
+// packs two fields, the block covers RPB rows of y, and transform pk goes to
+// S1 fields 2 pk and 2 pk + 1; otherwise team r packs rows y0 + r and
+// y0 + RPB + r of one field (2 RPB rows of y).
+template <typename T, int N, int V, int NPACK, bool PACK4, typename TWS>
+__device__ __forceinline__ void zfwd_readout(const cpx<T> (&a)[Rows<T, N, V>::E], const cpx<T> (&b)[Rows<T, N, V>::E],
+                                             cpx<T>* lds, TWS tws, cpx<T>* s1, size_t s1_field, int x, int y0,
+                                             int Kz) {
+    using RW = Rows<T, N, V>;
+    using PL = typename RW::PL;
+    constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
+    constexpr int YB = PACK4 ? RPB : 2 * RPB;
+    const int r = threadIdx.x / P, l = threadIdx.x % P;
+    cpx<T>* row = lds + r * ROWE;
+    static_for<NPACK>([&](auto pkc) {
+        constexpr int pk = decltype(pkc)::value;
+        cpx<T> v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = pk == 0 ? a[e] : b[e];
+        if constexpr (pk > 0) __syncthreads();  // previous read-out has finished with LDS
+        fft_row<PL, -1, T>(v, row, tws, l);
+        stage_row<PL, T>(v, row, l);
+        __syncthreads();
+        // read-out: the kept kz of rows y0 + rr in S1 tile order, tile by tile (tb = first
+        // kz of the tile, w its width); consecutive items are consecutive addresses
+        constexpr int TZ = kTileZ<T, N>;
+        cpx<T>* out = s1 + (size_t)x * N * Kz;
+        for (int idx = threadIdx.x; idx < Kz * YB; idx += RW::THREADS) {
+            const int tb = idx / (YB * TZ) * TZ, w = min(TZ, Kz - tb);
+            const int j = idx - tb * YB, rr = j / w, kz = tb + j % w;
+            const uint32_t o = (uint32_t)(tb * N + (y0 + rr) * w + (kz - tb));
+            const int team = PACK4 ? rr : rr % RPB;
+            const cpx<T> c = lds[team * ROWE + lds_pad(kz)];
+            const cpx<T> m = lds[team * ROWE + lds_pad(kz == 0 ? 0 : N - kz)];
+            if constexpr (PACK4) {
+                sto(out + (size_t)(2 * pk) * s1_field, o, unpack_real_pair(c, m, 0));
+                sto(out + (size_t)(2 * pk + 1) * s1_field, o, unpack_real_pair(c, m, 1));
+            } else {
+                sto(out, o, unpack_real_pair(c, m, rr / RPB));
+            }
+        }
+    });
+}
+
 template <typename T, int N, int V, int SRC, int NORD>
 __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __restrict__ f, ProductInputs<T> pin,
                                                                     uint64_t seed, uint64_t stream,
@@ -369,34 +414,151 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __re
     }
 
     constexpr int NPACK = (SRC == 2 || SRC == 3) ? 2 : 1;
-    static_for<NPACK>([&](auto pkc) {
-        constexpr int pk = decltype(pkc)::value;
-        cpx<T> v[E];
+    zfwd_readout<T, N, V, NPACK, PACK4>(a, b, lds, tws, s1, s1_field, x, y0, Kz);
+}
+
+// --------------------------------------------------------------------------
+// P5 of order NORD - 1 chained into P1 of order NORD.  The products of order
+// NORD read delta_m, u_m of the lower orders as real rows; the latest order's
+// four (delta, u_x, u_y, u_z) come straight from their S4 spectra here: the z
+// inverse of delta + i u_x and of u_y + i u_z (the two-fields-per-transform
+// packing of the header), the real rows stored where an output is set (a
+// field that no later pass reads is not stored), then used in the products
+// without a round trip through HBM.  A block covers RPB consecutive y at one
+// x, as for SRC 2 of k_zfwd; the rest of the pass is that of SRC 2.
+// --------------------------------------------------------------------------
+template <typename T>
+struct ChainArgs {
+    const cpx<T>* s4;
+    size_t s4_field;
+    int f[4];   // S4 fields of delta, u_x, u_y, u_z of order NORD - 1
+    T* out[4];  // their real rows, or null
+    T* dup;     // a second copy of delta, or null
+};
+
+template <typename T, int N, int V, int NORD>
+__global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zchain(ProductInputs<T> pin, ChainArgs<T> ch,
+                                                                      cpx<T>* __restrict__ s1, size_t s1_field,
+                                                                      const cpx<T>* __restrict__ tw, int Kz,
+                                                                      size_t zs) {
+    static_assert(NORD >= 2 && NORD <= 5, "orders 2 .. 5");
+    using RW = Rows<T, N, V>;
+    using PL = typename RW::PL;
+    constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
+    __shared__ cpx<T> lds[RPB * ROWE];
+    constexpr bool LT = kLdsTwiddles<T> && true;
+    __shared__ cpx<T> twl[LT ? PL::TW_ALLOC : 1];
+    if constexpr (LT) load_twiddles<PL, T>(twl, tw);
+    __syncthreads();
+    const Twiddles<T, PL, LT> tws{LT ? twl : tw};
+    s1 = zptr(s1, zs);
+    ch.s4 = zptr(ch.s4, zs);
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = pk == 0 ? a[e] : b[e];
-        if constexpr (pk > 0) __syncthreads();  // previous read-out has finished with LDS
-        fft_row<PL, -1, T>(v, row, tws, l);
-        stage_row<PL, T>(v, row, l);
-        __syncthreads();
-        // read-out: the kept kz of rows y0 + rr in S1 tile order, tile by tile (tb = first
-        // kz of the tile, w its width); consecutive items are consecutive addresses
-        constexpr int TZ = kTileZ<T, N>;
-        cpx<T>* out = s1 + (size_t)x * N * Kz;
-        for (int idx = threadIdx.x; idx < Kz * YB; idx += RW::THREADS) {
-            const int tb = idx / (YB * TZ) * TZ, w = min(TZ, Kz - tb);
-            const int j = idx - tb * YB, rr = j / w, kz = tb + j % w;
-            const uint32_t o = (uint32_t)(tb * N + (y0 + rr) * w + (kz - tb));
-            const int team = PACK4 ? rr : rr % RPB;
-            const cpx<T> c = lds[team * ROWE + lds_pad(kz)];
-            const cpx<T> m = lds[team * ROWE + lds_pad(kz == 0 ? 0 : N - kz)];
-            if constexpr (PACK4) {
-                sto(out + (size_t)(2 * pk) * s1_field, o, unpack_real_pair(c, m, 0));
-                sto(out + (size_t)(2 * pk + 1) * s1_field, o, unpack_real_pair(c, m, 1));
-            } else {
-                sto(out, o, unpack_real_pair(c, m, rr / RPB));
+    for (int i = 0; i < 4; ++i)
+        if (ch.out[i]) ch.out[i] = zptr(ch.out[i], zs);
+    if (ch.dup) ch.dup = zptr(ch.dup, zs);
+#pragma unroll
+    for (int m = 0; m < NORD - 2; ++m) {
+        pin.d[m] = zptr(pin.d[m], zs);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) pin.u[m][j] = zptr(pin.u[m][j], zs);
+    }
+    constexpr uint32_t groups = N / RPB;
+    const uint32_t blk = xcd_block(blockIdx.x, N * groups);
+    const int x = blk / groups, y0 = (blk % groups) * RPB;
+    const int r = threadIdx.x / P, l = threadIdx.x % P;
+    const size_t blockbase = ((size_t)x * N + y0) * N;  // first cell of the block
+
+    // z inverse of the latest order: pair q packs fields f[2q] + i f[2q+1].  The
+    // staged runs of the two fields sit side by side in LDS (rows of SROW >= Kz
+    // complex elements); position p of the Hermitian row takes kz = p or N - p.
+    constexpr int IT = E / 2, SROW = ROWE / 2;
+    static_assert(SROW >= N / 2, "a staged row holds every kept kz");
+    cpx<T>* stage = lds;
+    T* xrow = reinterpret_cast<T*>(lds) + r * ROWE;
+    auto src = [&](int p) { return p < Kz ? p : (p > N - Kz ? N - p : 0); };
+    const cpx<T>* s4x = ch.s4 + (size_t)x * Kz * N + y0;
+    cpx<T> cur[2][E];
+    static_for<2>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        cpx<T> ga[IT], gb[IT];
+        gather_runs<T, N, V>(ga, s4x + (size_t)ch.f[2 * q] * ch.s4_field, (uint32_t)N, Kz, RPB);
+        gather_runs<T, N, V>(gb, s4x + (size_t)ch.f[2 * q + 1] * ch.s4_field, (uint32_t)N, Kz, RPB);
+        __syncthreads();  // the previous transform's exchanges are done with the LDS
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int idx = (int)threadIdx.x + RW::THREADS * it;
+            if (idx < Kz * RPB) {
+                stage[(idx % RPB) * SROW + idx / RPB] = ga[it];
+                stage[(RPB + idx % RPB) * SROW + idx / RPB] = gb[it];
             }
         }
+        __syncthreads();
+        cpx<T> v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = l + P * e;
+            const cpx<T> av = stage[r * SROW + src(p)], bv = stage[(RPB + r) * SROW + src(p)];
+            const cpx<T> lo = {av.x - bv.y, av.y + bv.x};
+            const cpx<T> hi = {av.x + bv.y, bv.x - av.y};
+            const cpx<T> zero = {(T)0, (T)0};
+            v[e] = p < Kz ? lo : (p > N - Kz ? hi : zero);
+        }
+        __syncthreads();  // every wave has read the staged runs before the exchanges reuse the LDS
+        fft_row_split<PL, +1, T>(v, xrow, tws, l);
+        T* o0 = ch.out[2 * q];
+        T* o1 = ch.out[2 * q + 1];
+        if (o0) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) sto(o0 + blockbase, (uint32_t)(r * N + l + P * e), v[e].x);
+        }
+        if (q == 0 && ch.dup) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) sto(ch.dup + blockbase, (uint32_t)(r * N + l + P * e), v[e].x);
+        }
+        if (o1) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) sto(o1 + blockbase, (uint32_t)(r * N + l + P * e), v[e].y);
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) cur[q][e] = v[e];
     });
+
+    // products: the lower orders' raw rows, DEPTH elements ahead, with the latest
+    // order's values from registers
+    constexpr int NL = 4 * (NORD - 2), NR = 4 * (NORD - 1);
+    cpx<T> a[E], b[E];
+    auto combine = [&](const T* lower, int e) {
+        T raw[NR];
+#pragma unroll
+        for (int i = 0; i < NL; ++i) raw[i] = lower[i];
+        raw[NL] = cur[0][e].x;
+        raw[NL + 1] = cur[0][e].y;
+        raw[NL + 2] = cur[1][e].x;
+        raw[NL + 3] = cur[1][e].y;
+        combine_products<T, NORD>(raw, a[e], b[e]);
+    };
+    if constexpr (NORD == 2) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) combine(nullptr, e);
+    } else {
+        constexpr int DEPTH = (48 / NL) < 2 ? 2 : ((48 / NL) > 4 ? 4 : (48 / NL));
+        T raw[DEPTH][NL];
+#pragma unroll
+        for (int e = 0; e < DEPTH - 1; ++e)
+            load_raw<T, NORD - 1>(pin, blockbase, (uint32_t)(r * N + l + P * e), raw[e]);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (e + DEPTH - 1 < E)
+                load_raw<T, NORD - 1>(pin, blockbase, (uint32_t)(r * N + l + P * (e + DEPTH - 1)),
+                                      raw[(e + DEPTH - 1) % DEPTH]);
+            combine(raw[e % DEPTH], e);
+            keep_here(a[e]);
+            keep_here(b[e]);
+        }
+    }
+    __syncthreads();  // the inverse transforms' exchanges are done with the LDS
+    zfwd_readout<T, N, V, 2, true>(a, b, lds, tws, s1, s1_field, x, y0, Kz);
 }
 
 // --------------------------------------------------------------------------
@@ -1076,6 +1238,7 @@ template <typename T>
 struct ZJobs {
     int f[8];  // S4 field indices
     T* out[8];
+    T* dup[8];  // a second output of the same field, or null
 };
 
 template <typename T, int N, int V>
@@ -1139,11 +1302,15 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zinv(const cpx<T>*
     }
     __syncthreads();  // every wave has read the staged runs before the exchanges reuse the LDS
     fft_row_split<PL, +1, T>(v, row, tws, l);
-    T* out = zptr(zj.out[job], zs) + q0 * N;
+    auto store = [&](T* base) {
+        T* out = zptr(base, zs) + q0 * N;
 #pragma unroll
-    for (int e = 0; e < E; ++e) sto(out, (uint32_t)(r * N + l + P * e), v[e].x);
+        for (int e = 0; e < E; ++e) sto(out, (uint32_t)(r * N + l + P * e), v[e].x);
 #pragma unroll
-    for (int e = 0; e < E; ++e) sto(out, (uint32_t)((r + RPB) * N + l + P * e), v[e].y);
+        for (int e = 0; e < E; ++e) sto(out, (uint32_t)((r + RPB) * N + l + P * e), v[e].y);
+    };
+    store(zj.out[job]);
+    if (zj.dup[job]) store(zj.dup[job]);
 }
 
 }  // namespace gridspt

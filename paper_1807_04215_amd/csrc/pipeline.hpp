@@ -181,6 +181,33 @@ struct Pipe {
         });
     }
 
+    // P5 of the latest order's delta, u (S4 fields of ch, in B) chained into P1
+    // with the products of order n -> S1 fields 0..3 (V_x, V_y, V_z, W) in A
+    int zchain(int n, const ProductInputs<T>& pin, ChainArgs<T> ch) {
+        ch.s4 = B();
+        ch.s4_field = (size_t)L.b_field_s4;
+        return with_variant<T, N>(tu.v[KD_ZFWD_PRODUCTS], [&](auto vc) {
+            constexpr int V = decltype(vc)::value;
+            using RW = Rows<T, N, V>;
+            int nst = ch.dup ? 1 : 0;
+            for (int i = 0; i < 4; ++i) nst += ch.out[i] ? 1 : 0;
+            const double bytes = nb() * ((4.0 * (n - 2) + nst) * d.ncell() * d.real_bytes +
+                                         (4.0 * N * N * cd.Kz + 4.0 * d.s1()) * d.cpx_bytes);
+            const dim3 grid(N * (N / RW::RPB), 1, nz()), block(RW::THREADS);
+            auto go = [&](auto kern) {
+                return launch(c, KD_ZFWD_PRODUCTS, bytes, grid, block, 0, kern, pin, ch, A(), (size_t)L.a_field_s1,
+                              (const cpx<T>*)tw(), (int)d.Kz, bt.zs);
+            };
+            switch (n) {
+                case 2: return go(k_zchain<T, N, V, 2>);
+                case 3: return go(k_zchain<T, N, V, 3>);
+                case 4: return go(k_zchain<T, N, V, 4>);
+                case 5: return go(k_zchain<T, N, V, 5>);
+                default: return (int)GRIDSPT_EINVAL;
+            }
+        });
+    }
+
     // P2: nf fields S1 (A) -> S2 (B)
     int yfwd(int nf) {
         return with_variant<T, N>(tu.v[KD_YFWD], [&](auto vc) {
@@ -287,8 +314,10 @@ struct Pipe {
         return with_variant<T, N>(tu.v[KD_ZINV], [&](auto vc) {
             constexpr int V = decltype(vc)::value;
             using RW = Rows<T, N, V>;
-            const double bytes =
-                nb() * njobs * ((double)N * N * cd.Kz * d.cpx_bytes + (double)d.ncell() * d.real_bytes);
+            int ndup = 0;
+            for (int j = 0; j < njobs; ++j) ndup += zj.dup[j] != nullptr;
+            const double bytes = nb() * (njobs * (double)N * N * cd.Kz * d.cpx_bytes +
+                                         (njobs + ndup) * (double)d.ncell() * d.real_bytes);
             return launch(c, KD_ZINV, bytes, dim3((unsigned)(N * N / (2 * RW::RPB)), njobs, nz()),
                           dim3(RW::THREADS), 0, k_zinv<T, N, V>, (const cpx<T>*)B(), (size_t)L.b_field_s4, zj,
                           (const cpx<T>*)tw(), cd, bt.zs);
@@ -296,8 +325,8 @@ struct Pipe {
     }
 
     // P4 + P5 for nf <= 8 fields of S3 into real outputs out[0..nf-1], one z
-    // inverse job per field
-    int to_real(int nf, T* const* out) {
+    // inverse job per field; dup0, if set, receives a second copy of field 0
+    int to_real(int nf, T* const* out, T* dup0 = nullptr) {
         if (nf < 1 || nf > 8) return GRIDSPT_EINVAL;
         GRIDSPT_CHECK(yinv(nf));
         ZJobs<T> zj{};
@@ -305,12 +334,8 @@ struct Pipe {
             zj.f[i] = i;
             zj.out[i] = out[i];
         }
+        zj.dup[0] = dup0;
         return zinv(zj, nf);
-    }
-
-    int copy(const T* src, T* dst) {
-        return launch(c, KD_COPY, nb() * 2.0 * d.ncell() * d.real_bytes, dim3(2048, 1, nz()), dim3(256), 0, k_copy<T>,
-                      src, dst, (size_t)d.ncell(), bt.zs);
     }
 };
 
@@ -376,33 +401,51 @@ int run_orders(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, i
         GRIDSPT_CHECK(p.zfwd_single(static_cast<const T*>(delta1), false, 0, 0));
     }
     GRIDSPT_CHECK(p.yfwd(1));
+    ChainArgs<T> chain{};
     {
         const int nout = nmax > 1 ? 4 : 1;
         cpx<T>* ct = (tk(0) && tk(0) != dk(0)) ? tk(0) : nullptr;
         XArgs<T> a = make_xargs<T>(p.d, g, 1, nout, lp ? lp->n2max : n2max1, dk(0), ct);
         a.amp = p.amp();
         GRIDSPT_CHECK(p.xfused(lp ? XM_LIN_ORDER1 : XM_ORDER1, a));
-        T* out[4] = {static_cast<T*>(delta[0]), p.U(1, 0), p.U(1, 1), p.U(1, 2)};
-        GRIDSPT_CHECK(p.to_real(nout, out));
-        if (theta[0] && theta[0] != delta[0])
-            GRIDSPT_CHECK(p.copy(static_cast<const T*>(delta[0]), static_cast<T*>(theta[0])));
+        // theta_1 = delta_1: the z inverse stores the same rows twice
+        T* t1 = (theta[0] && theta[0] != delta[0]) ? static_cast<T*>(theta[0]) : nullptr;
+        if (nmax == 1) {
+            T* out[1] = {static_cast<T*>(delta[0])};
+            return p.to_real(1, out, t1);
+        }
+        GRIDSPT_CHECK(p.yinv(4));
+        chain = ChainArgs<T>{nullptr, 0, {0, 1, 2, 3}, {static_cast<T*>(delta[0]), nullptr, nullptr, nullptr}, t1};
     }
-    // orders n >= 2
+    // orders n >= 2.  The z inverse of delta_{n-1}, u_{n-1} runs inside order n's
+    // product pass (k_zchain); u_m is stored only while a later product pass
+    // reads it from HBM (m < nmax - 1).
     for (int n = 2; n <= nmax; ++n) {
+        if (n - 1 < nmax - 1)
+            for (int j = 0; j < 3; ++j) chain.out[1 + j] = p.U(n - 1, j);
         ProductInputs<T> pin{};
-        for (int m = 1; m < n; ++m) {
+        for (int m = 1; m < n - 1; ++m) {
             pin.d[m - 1] = static_cast<const T*>(delta[m - 1]);
             for (int j = 0; j < 3; ++j) pin.u[m - 1][j] = p.U(m, j);
         }
-        GRIDSPT_CHECK(p.zfwd_products(n, pin));
+        GRIDSPT_CHECK(p.zchain(n, pin, chain));
         GRIDSPT_CHECK(p.yfwd_products());
         const int nout = n < nmax ? 5 : 2;
         XArgs<T> a = make_xargs<T>(p.d, g, n, nout, n2max2, dk(n - 1), tk(n - 1));
         GRIDSPT_CHECK(p.xfused(XM_ORDER, a));
-        T* out[5] = {static_cast<T*>(delta[n - 1]), static_cast<T*>(theta[n - 1]), nullptr, nullptr, nullptr};
-        if (n < nmax)
-            for (int j = 0; j < 3; ++j) out[2 + j] = p.U(n, j);
-        GRIDSPT_CHECK(p.to_real(nout, out));
+        if (n == nmax) {
+            T* out[2] = {static_cast<T*>(delta[n - 1]), static_cast<T*>(theta[n - 1])};
+            return p.to_real(2, out);
+        }
+        // S4 fields delta_n, theta_n, u_n: theta_n to real space now, the rest in
+        // the next order's chained pass
+        GRIDSPT_CHECK(p.yinv(5));
+        ZJobs<T> zj{};
+        zj.f[0] = 1;
+        zj.out[0] = static_cast<T*>(theta[n - 1]);
+        GRIDSPT_CHECK(p.zinv(zj, 1));
+        chain = ChainArgs<T>{nullptr, 0, {0, 2, 3, 4}, {static_cast<T*>(delta[n - 1]), nullptr, nullptr, nullptr},
+                             nullptr};
     }
     return GRIDSPT_OK;
 }
@@ -512,9 +555,7 @@ int run_orders_pform(gridspt_ctx* c, const gridspt_grid* g, int nmax, int64_t n2
         XArgs<T> a = make_xargs<T>(p.d, g, 1, 1, n2max1, c1, nullptr);
         GRIDSPT_CHECK(p.xfused(XM_ORDER1, a));
         T* out[1] = {static_cast<T*>(delta[0])};
-        GRIDSPT_CHECK(p.to_real(1, out));
-        if (theta[0] && theta[0] != delta[0])
-            GRIDSPT_CHECK(p.copy(static_cast<const T*>(delta[0]), static_cast<T*>(theta[0])));
+        GRIDSPT_CHECK(p.to_real(1, out, (theta[0] && theta[0] != delta[0]) ? static_cast<T*>(theta[0]) : nullptr));
         if (theta_k && theta_k[0] && theta_k[0] != (void*)c1)
             GRIDSPT_CHECK(launch(c, KD_COPY, 4.0 * p.d.cube() * p.d.real_bytes, dim3(512), dim3(256), 0, k_copy<T>,
                                  (const T*)c1, (T*)theta_k[0], (size_t)(2 * p.d.cube()), (size_t)0));
