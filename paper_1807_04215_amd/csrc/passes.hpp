@@ -218,13 +218,12 @@ __device__ __forceinline__ cpx<T> unpack_real_pair(cpx<T> c, cpx<T> m, int which
 // SRC 0: one real field, SRC 1: Gaussian noise generated in place.  A block
 //   covers 2 RPB consecutive y at one x; team r transforms rows y0 + r (real
 //   part) and y0 + RPB + r (imaginary part) together.
-// SRC 2: the products of order NORD, V = sum_m delta_m u_{n-m} and
-//   W = sum_m u_m . u_{n-m} (the divergence form of the sources of Eq. 10),
-//   packed as V_x + i V_y and V_z + i W; a block covers RPB consecutive y.
 // SRC 3: four real fields pin.d[0..3] (the reverse mode's g delta, g u),
 //   packed as d0 + i d1 and d2 + i d3; a block covers RPB consecutive y.
 // SRC 4: two real fields pin.d[0..1] (the printed sources S_delta, S_theta),
 //   packed as d0 + i d1; a block covers RPB consecutive y.
+// The products of an order, the remaining source of P1, are formed in
+// k_zchain below.
 // --------------------------------------------------------------------------
 // base[idx] where ok, zero elsewhere, with no branch around the load: the caller passes
 // an index that names a valid element also where ok is false, so every lane loads and
@@ -319,7 +318,7 @@ __device__ __forceinline__ void zfwd_readout(const cpx<T> (&a)[Rows<T, N, V>::E]
     });
 }
 
-template <typename T, int N, int V, int SRC, int NORD>
+template <typename T, int N, int V, int SRC>
 __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __restrict__ f, ProductInputs<T> pin,
                                                                     uint64_t seed, uint64_t stream,
                                                                     cpx<T>* __restrict__ s1, size_t s1_field,
@@ -327,7 +326,8 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __re
     using RW = Rows<T, N, V>;
     using PL = typename RW::PL;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
-    constexpr bool PACK4 = SRC == 2 || SRC == 3 || SRC == 4;  // field pairs packed per row
+    static_assert(SRC >= 0 && SRC <= 4 && SRC != 2, "sources 0, 1, 3, 4");
+    constexpr bool PACK4 = SRC == 3 || SRC == 4;  // field pairs packed per row
     constexpr int YB = PACK4 ? RPB : 2 * RPB;  // rows of y per block
     __shared__ cpx<T> lds[RPB * ROWE];
     // twiddles in LDS for FP32 (this pass's LDS traffic is light), else from the cache
@@ -341,14 +341,6 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __re
     if constexpr (SRC == 3 || SRC == 4) {
 #pragma unroll
         for (int m = 0; m < (SRC == 3 ? 4 : 2); ++m) pin.d[m] = zptr(pin.d[m], zs);
-    }
-    if constexpr (SRC == 2) {
-#pragma unroll
-        for (int m = 0; m < NORD - 1; ++m) {
-            pin.d[m] = zptr(pin.d[m], zs);
-#pragma unroll
-            for (int j = 0; j < 3; ++j) pin.u[m][j] = zptr(pin.u[m][j], zs);
-        }
     }
     stream += blockIdx.z;  // realisation r of a batch draws Philox stream `stream + r`
     constexpr uint32_t groups = N / YB;
@@ -392,40 +384,23 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __re
             a[e] = {ldo(pin.d[0] + blockbase, o), ldo(pin.d[1] + blockbase, o)};
             if constexpr (SRC == 3) b[e] = {ldo(pin.d[2] + blockbase, o), ldo(pin.d[3] + blockbase, o)};
         }
-    } else {
-        // The packed products are formed here, not after the first transform, so the raw
-        // inputs are dead before the FFTs start.  The raw loads run DEPTH elements ahead of
-        // the products (about 48 values in flight per lane), so a wave waits for memory
-        // once per DEPTH elements rather than once per element.
-        constexpr int NR = 4 * (NORD - 1);
-        constexpr int DEPTH = (48 / NR) < 2 ? 2 : ((48 / NR) > 4 ? 4 : (48 / NR));
-        T raw[DEPTH][NR];
-#pragma unroll
-        for (int e = 0; e < DEPTH - 1; ++e) load_raw<T, NORD>(pin, blockbase, (uint32_t)(r * N + l + P * e), raw[e]);
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            if (e + DEPTH - 1 < E)
-                load_raw<T, NORD>(pin, blockbase, (uint32_t)(r * N + l + P * (e + DEPTH - 1)),
-                                  raw[(e + DEPTH - 1) % DEPTH]);
-            combine_products<T, NORD>(raw[e % DEPTH], a[e], b[e]);
-            keep_here(a[e]);
-            keep_here(b[e]);
-        }
     }
 
-    constexpr int NPACK = (SRC == 2 || SRC == 3) ? 2 : 1;
+    constexpr int NPACK = SRC == 3 ? 2 : 1;
     zfwd_readout<T, N, V, NPACK, PACK4>(a, b, lds, tws, s1, s1_field, x, y0, Kz);
 }
 
 // --------------------------------------------------------------------------
 // P5 of order NORD - 1 chained into P1 of order NORD.  The products of order
-// NORD read delta_m, u_m of the lower orders as real rows; the latest order's
-// four (delta, u_x, u_y, u_z) come straight from their S4 spectra here: the z
-// inverse of delta + i u_x and of u_y + i u_z (the two-fields-per-transform
-// packing of the header), the real rows stored where an output is set (a
-// field that no later pass reads is not stored), then used in the products
-// without a round trip through HBM.  A block covers RPB consecutive y at one
-// x, as for SRC 2 of k_zfwd; the rest of the pass is that of SRC 2.
+// NORD are V = sum_m delta_m u_{n-m} and W = sum_m u_m . u_{n-m} (the
+// divergence form of the sources of Eq. 10), packed as V_x + i V_y and
+// V_z + i W.  They read delta_m, u_m of the lower orders as real rows.  The
+// latest order's four fields (delta, u_x, u_y, u_z) come straight from their
+// S4 spectra: the z inverse of delta + i u_x and of u_y + i u_z (the
+// two-fields-per-transform packing of the header) runs here, its real rows
+// are stored where an output is set (a field no later pass reads is not) and
+// go into the products without a round trip through HBM.  A block covers RPB
+// consecutive y at one x, the layout of SRC 3 of k_zfwd.
 // --------------------------------------------------------------------------
 template <typename T>
 struct ChainArgs {
@@ -524,8 +499,11 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zchain(ProductInpu
         for (int e = 0; e < E; ++e) cur[q][e] = v[e];
     });
 
-    // products: the lower orders' raw rows, DEPTH elements ahead, with the latest
-    // order's values from registers
+    // products, with the latest order's values from registers.  The packed products
+    // are formed before the forward transforms, so the raw inputs are dead when they
+    // start.  The lower orders' raw loads run DEPTH elements ahead of the products
+    // (about 48 values in flight per lane), so a wave waits for memory once per DEPTH
+    // elements rather than once per element.
     constexpr int NL = 4 * (NORD - 2), NR = 4 * (NORD - 1);
     cpx<T> a[E], b[E];
     auto combine = [&](const T* lower, int e) {

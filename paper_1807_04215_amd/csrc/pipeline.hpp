@@ -80,9 +80,9 @@ struct Pipe {
             const double bytes = nb() * ((noise ? 0.0 : (double)d.ncell() * d.real_bytes) + (double)d.s1() * d.cpx_bytes);
             const dim3 grid(N * (N / (2 * RW::RPB)), 1, nz()), block(RW::THREADS);  // two rows per transform
             if (noise)
-                return launch(c, kind, bytes, grid, block, 0, k_zfwd<T, N, V, 1, 0>, f, pin, seed, stream, A(),
+                return launch(c, kind, bytes, grid, block, 0, k_zfwd<T, N, V, 1>, f, pin, seed, stream, A(),
                               (size_t)L.a_field_s1, (const cpx<T>*)tw(), (int)d.Kz, bt.zs);
-            return launch(c, kind, bytes, grid, block, 0, k_zfwd<T, N, V, 0, 0>, f, pin, seed, stream, A(),
+            return launch(c, kind, bytes, grid, block, 0, k_zfwd<T, N, V, 0>, f, pin, seed, stream, A(),
                           (size_t)L.a_field_s1, (const cpx<T>*)tw(), (int)d.Kz, bt.zs);
         });
     }
@@ -96,7 +96,7 @@ struct Pipe {
             for (int i = 0; i < 4; ++i) pin.d[i] = f[i];
             const double bytes = nb() * (4.0 * d.ncell() * d.real_bytes + 4.0 * d.s1() * d.cpx_bytes);
             return launch(c, KD_ZFWD_ADJ, bytes, dim3(N * (N / RW::RPB), 1, nz()), dim3(RW::THREADS), 0,
-                          k_zfwd<T, N, V, 3, 0>, (const T*)nullptr, pin, (uint64_t)0, (uint64_t)0, A(),
+                          k_zfwd<T, N, V, 3>, (const T*)nullptr, pin, (uint64_t)0, (uint64_t)0, A(),
                           (size_t)L.a_field_s1, (const cpx<T>*)tw(), (int)d.Kz, bt.zs);
         });
     }
@@ -111,7 +111,7 @@ struct Pipe {
             pin.d[1] = f1;
             const double bytes = nb() * (2.0 * d.ncell() * d.real_bytes + 2.0 * d.s1() * d.cpx_bytes);
             return launch(c, KD_ZFWD_PAIR, bytes, dim3(N * (N / RW::RPB), 1, nz()), dim3(RW::THREADS), 0,
-                          k_zfwd<T, N, V, 4, 0>, (const T*)nullptr, pin, (uint64_t)0, (uint64_t)0, A(),
+                          k_zfwd<T, N, V, 4>, (const T*)nullptr, pin, (uint64_t)0, (uint64_t)0, A(),
                           (size_t)L.a_field_s1, (const cpx<T>*)tw(), (int)d.Kz, bt.zs);
         });
     }
@@ -157,27 +157,6 @@ struct Pipe {
             const double bytes = nb() * (2.0 * d.cube() + 4.0 * d.s3()) * d.cpx_bytes;
             return launch(c, KD_XREGEN, bytes, dim3((unsigned)(d.Kz * ((d.Ky + RW::RPB - 1) / RW::RPB)), 1, nz()),
                           dim3(RW::THREADS), 0, k_xregen<T, N, V>, r, (const cpx<T>*)tw(), cd, bt.zs);
-        });
-    }
-
-    // P1 with the products of order n -> S1 fields 0..3 (V_x, V_y, V_z, W) in A
-    int zfwd_products(int n, const ProductInputs<T>& pin) {
-        return with_variant<T, N>(tu.v[KD_ZFWD_PRODUCTS], [&](auto vc) {
-            constexpr int V = decltype(vc)::value;
-            using RW = Rows<T, N, V>;
-            const double bytes = nb() * (4.0 * (n - 1) * d.ncell() * d.real_bytes + 4.0 * d.s1() * d.cpx_bytes);
-            const dim3 grid(N * (N / RW::RPB), 1, nz()), block(RW::THREADS);
-            auto go = [&](auto kern) {
-                return launch(c, KD_ZFWD_PRODUCTS, bytes, grid, block, 0, kern, (const T*)nullptr, pin, (uint64_t)0,
-                              (uint64_t)0, A(), (size_t)L.a_field_s1, (const cpx<T>*)tw(), (int)d.Kz, bt.zs);
-            };
-            switch (n) {
-                case 2: return go(k_zfwd<T, N, V, 2, 2>);
-                case 3: return go(k_zfwd<T, N, V, 2, 3>);
-                case 4: return go(k_zfwd<T, N, V, 2, 4>);
-                case 5: return go(k_zfwd<T, N, V, 2, 5>);
-                default: return (int)GRIDSPT_EINVAL;
-            }
         });
     }
 

@@ -230,7 +230,8 @@ inline Dims dims_of(const gridspt_grid* g) {
 
 // Workspace of the transform pipeline: twiddles | radial amplitude table
 // ((Kc + 1)^2 doubles) | buffer A (S1, S3) | buffer B (S2, S4) | u_m real
-// fields.  S1/S3 and S2/S4 are never live at once.
+// fields for m <= nmax - 2 (the product pass of order nmax takes u_{nmax-1}
+// from registers).  S1/S3 and S2/S4 are never live at once.
 struct Layout {
     int64_t tw, amp, a, b, u, end;
     int64_t a_field_s1, a_field_s3, b_field_s2, b_field_s4;  // field strides (elements)
@@ -245,7 +246,7 @@ inline Layout layout_of(const Dims& d, int nmax) {
     L.b = align_up(L.a + asz);
     const int64_t bsz = std::max(4 * d.s2(), 5 * d.s4()) * d.cpx_bytes;
     L.u = align_up(L.b + bsz);
-    const int nu = std::max(nmax - 1, 0) * 3;
+    const int nu = std::max(nmax - 2, 0) * 3;
     L.end = align_up(L.u + (int64_t)nu * d.ncell() * d.real_bytes);
     L.a_field_s1 = d.s1();
     L.a_field_s3 = d.s3();
