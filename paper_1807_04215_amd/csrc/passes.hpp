@@ -396,8 +396,8 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zfwd(const T* __re
 // divergence form of the sources of Eq. 10), packed as V_x + i V_y and
 // V_z + i W.  They read delta_m, u_m of the lower orders as real rows.  The
 // latest order's four fields (delta, u_x, u_y, u_z) come straight from their
-// S4 spectra: the z inverse of delta + i u_x and of u_y + i u_z (the
-// two-fields-per-transform packing of the header) runs here, its real rows
+// S4 spectra (u_z as phi, times kz here): the z inverse of delta + i u_x and
+// of u_y + i u_z (the two-fields-per-transform packing of the header) runs here, its real rows
 // are stored where an output is set (a field no later pass reads is not) and
 // go into the products without a round trip through HBM.  A block covers RPB
 // consecutive y at one x, the layout of SRC 3 of k_zfwd.
@@ -406,13 +406,14 @@ template <typename T>
 struct ChainArgs {
     const cpx<T>* s4;
     size_t s4_field;
-    int f[4];   // S4 fields of delta, u_x, u_y, u_z of order NORD - 1
+    int f[4];   // S4 fields of delta, u_x, u_y and phi (u_z = kz phi) of order NORD - 1
     T* out[4];  // their real rows, or null
     T* dup;     // a second copy of delta, or null
 };
 
 template <typename T, int N, int V, int NORD>
-__global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zchain(ProductInputs<T> pin, ChainArgs<T> ch,
+__global__ __launch_bounds__((Rows<T, N, V>::THREADS))
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_zchain(ProductInputs<T> pin, ChainArgs<T> ch,
                                                                       cpx<T>* __restrict__ s1, size_t s1_field,
                                                                       const cpx<T>* __restrict__ tw, int Kz,
                                                                       size_t zs) {
@@ -464,8 +465,10 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zchain(ProductInpu
         for (int it = 0; it < IT; ++it) {
             const int idx = (int)threadIdx.x + RW::THREADS * it;
             if (idx < Kz * RPB) {
+                // the second pair's B field is phi: u_z = kz phi at the stored kz = idx / RPB
+                const cpx<T> b = q == 1 ? cscale(gb[it], (T)(idx / RPB)) : gb[it];
                 stage[(idx % RPB) * SROW + idx / RPB] = ga[it];
-                stage[(RPB + idx % RPB) * SROW + idx / RPB] = gb[it];
+                stage[(RPB + idx % RPB) * SROW + idx / RPB] = b;
             }
         }
         __syncthreads();
@@ -843,13 +846,16 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
         }
     }
     if constexpr (MODE != XM_FORWARD) {
-        // outputs.  ORDER: delta, theta, u_x, u_y, u_z;  ORDER1: delta, u_x, u_y, u_z;  LINEAR: delta;
+        // outputs.  ORDER: delta, theta, u_x, phi;  ORDER1: delta, u_x, phi;  LINEAR: delta;
         // ADJ: g V_x, g V_y, g V_z, g W;  ADJ1: g w
         // PFORM: delta, theta
+        // phi = (-i / k^2) theta: along this row ky and kz are constant, so u_y = ky phi and
+        // u_z = kz phi share one transform here; the inverse y pass (k_yinv<..., true>)
+        // applies ky, the inverse z pass (k_zchain) kz.
         constexpr int NOUT_MAX =
-            (MODE == XM_ORDER) ? 5
-                               : ((MODE == XM_ORDER1 || MODE == XM_LIN_ORDER1 || MODE == XM_ADJ) ? 4
-                                                                                                  : (MODE == XM_PFORM ? 2 : 1));
+            (MODE == XM_ORDER || MODE == XM_ADJ)
+                ? 4
+                : ((MODE == XM_ORDER1 || MODE == XM_LIN_ORDER1) ? 3 : (MODE == XM_PFORM ? 2 : 1));
         constexpr int FIRST_U = (MODE == XM_ORDER || MODE == XM_PFORM) ? 2 : 1;
         const size_t outbase = ((size_t)kz * cd.Ky + ky0) * N;
         static_for<NOUT_MAX>([&](auto oc) {
@@ -876,15 +882,16 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
 #pragma unroll
                     for (int e = 0; e < E; ++e) v[e] = (o == 0) ? sd[e] : st[e];
                 } else {
-                    // u_j(k) = (-i k_j / k^2) theta(k); the factor k_j / (kF n^2) is formed in FP64
-                    // and rounded once (u feeds every later order's products)
+                    // u_x(k) = (-i kx / k^2) theta(k), then phi; the factors kx / (kF n^2) and
+                    // 1 / (kF n^2) are formed in FP64 and rounded once (u feeds every later
+                    // order's products)
                     constexpr int comp = o - FIRST_U;
 #pragma unroll
                     for (int e = 0; e < E; ++e) {
                         const int kx = signed_pos(l + P * e, N);
                         const int n2 = kx * kx + ky * ky + kz * kz;
-                        const int kj = comp == 0 ? kx : (comp == 1 ? ky : kz);
-                        const T s = n2 > 0 ? (T)((double)kj / (a.kF * (double)n2)) : (T)0;
+                        const double num = comp == 0 ? (double)kx : 1.0;
+                        const T s = n2 > 0 ? (T)(num / (a.kF * (double)n2)) : (T)0;
                         v[e] = {st[e].y * s, -st[e].x * s};
                     }
                 }
@@ -1167,8 +1174,11 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xsmooth(SmoothArgs
 // P4: y pass, inverse.  Rows (kz, x) along ky' of S3 (Ky values, zero-extended
 // to N); block = RPB consecutive x at one kz (runs of RPB elements of S3);
 // grid.y = field.  Writes S4 rows (x, kz) of N values.
+// YZ (grid.y = 1): the input is phi of the x pass; output field 0 is the
+// transform of ky phi (u_y), output field 1 that of phi itself, which the
+// inverse z pass turns into u_z = kz phi.
 // --------------------------------------------------------------------------
-template <typename T, int N, int V>
+template <typename T, int N, int V, bool YZ = false>
 __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yinv(const cpx<T>* __restrict__ s3, size_t s3_field,
                                                                     cpx<T>* __restrict__ s4, size_t s4_field,
                                                                     const cpx<T>* __restrict__ tw, CubeDims cd,
@@ -1198,9 +1208,19 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yinv(const cpx<T>*
     scatter_runs_split<T, N, V>(
         g, lds, row, l, cd.Ky, [&](int q) { return compact_to_pos(q, cd.Kc, N); },
         [&](int p) { return pos_to_compact(p, cd.Kc, N) >= 0; }, v);
-    fft_row_split<PL, +1, T>(v, row, tws, l);
     // S4 row (x0 + r, kz)
     cpx<T>* out = s4 + (size_t)blockIdx.y * s4_field + ((size_t)x0 * cd.Kz + kz) * N;
+    if constexpr (YZ) {
+        cpx<T> w[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) w[e] = cscale(v[e], (T)signed_pos(l + P * e, N));
+        fft_row_split<PL, +1, T>(w, row, tws, l);
+#pragma unroll
+        for (int e = 0; e < E; ++e) sto(out, (uint32_t)(r * cd.Kz * N + l + P * e), w[e]);
+        out += s4_field;
+        wave_sync();  // every lane of this row's team is done with its exchanges
+    }
+    fft_row_split<PL, +1, T>(v, row, tws, l);
 #pragma unroll
     for (int e = 0; e < E; ++e) sto(out, (uint32_t)(r * cd.Kz * N + l + P * e), v[e]);
 }

@@ -288,6 +288,20 @@ struct Pipe {
         });
     }
 
+    // P4 of phi (S3 field f in A) -> S4 fields f (the transform of ky phi, u_y) and
+    // f + 1 (phi, u_z / kz) in B
+    int yinv_yz(int f) {
+        return with_variant<T, N>(tu.v[KD_YINV], [&](auto vc) {
+            constexpr int V = decltype(vc)::value;
+            using RW = Rows<T, N, V>;
+            const double bytes = nb() * ((double)cd.Kz * N * cd.Ky + 2.0 * N * N * cd.Kz) * d.cpx_bytes;
+            return launch(c, KD_YINV, bytes, dim3((unsigned)(cd.Kz * (N / RW::RPB)), 1, nz()), dim3(RW::THREADS), 0,
+                          k_yinv<T, N, V, true>, (const cpx<T>*)(A() + (size_t)f * L.a_field_s3),
+                          (size_t)L.a_field_s3, B() + (size_t)f * L.b_field_s4, (size_t)L.b_field_s4,
+                          (const cpx<T>*)tw(), cd, bt.zs);
+        });
+    }
+
     // P5: S4 (B) -> real outputs, two real rows per complex transform
     int zinv(const ZJobs<T>& zj, int njobs) {
         return with_variant<T, N>(tu.v[KD_ZINV], [&](auto vc) {
@@ -382,7 +396,7 @@ int run_orders(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, i
     GRIDSPT_CHECK(p.yfwd(1));
     ChainArgs<T> chain{};
     {
-        const int nout = nmax > 1 ? 4 : 1;
+        const int nout = nmax > 1 ? 3 : 1;  // delta_1 (, u_x, phi)
         cpx<T>* ct = (tk(0) && tk(0) != dk(0)) ? tk(0) : nullptr;
         XArgs<T> a = make_xargs<T>(p.d, g, 1, nout, lp ? lp->n2max : n2max1, dk(0), ct);
         a.amp = p.amp();
@@ -393,7 +407,8 @@ int run_orders(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, i
             T* out[1] = {static_cast<T*>(delta[0])};
             return p.to_real(1, out, t1);
         }
-        GRIDSPT_CHECK(p.yinv(4));
+        GRIDSPT_CHECK(p.yinv(2));     // delta_1, u_x
+        GRIDSPT_CHECK(p.yinv_yz(2));  // phi -> u_y, phi
         chain = ChainArgs<T>{nullptr, 0, {0, 1, 2, 3}, {static_cast<T*>(delta[0]), nullptr, nullptr, nullptr}, t1};
     }
     // orders n >= 2.  The z inverse of delta_{n-1}, u_{n-1} runs inside order n's
@@ -409,16 +424,17 @@ int run_orders(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, i
         }
         GRIDSPT_CHECK(p.zchain(n, pin, chain));
         GRIDSPT_CHECK(p.yfwd_products());
-        const int nout = n < nmax ? 5 : 2;
+        const int nout = n < nmax ? 4 : 2;  // delta_n, theta_n (, u_x, phi)
         XArgs<T> a = make_xargs<T>(p.d, g, n, nout, n2max2, dk(n - 1), tk(n - 1));
         GRIDSPT_CHECK(p.xfused(XM_ORDER, a));
         if (n == nmax) {
             T* out[2] = {static_cast<T*>(delta[n - 1]), static_cast<T*>(theta[n - 1])};
             return p.to_real(2, out);
         }
-        // S4 fields delta_n, theta_n, u_n: theta_n to real space now, the rest in
-        // the next order's chained pass
-        GRIDSPT_CHECK(p.yinv(5));
+        // S4 fields delta_n, theta_n, u_x, u_y, phi: theta_n to real space now, the
+        // rest in the next order's chained pass
+        GRIDSPT_CHECK(p.yinv(3));     // delta_n, theta_n, u_x
+        GRIDSPT_CHECK(p.yinv_yz(3));  // phi -> u_y, phi
         ZJobs<T> zj{};
         zj.f[0] = 1;
         zj.out[0] = static_cast<T*>(theta[n - 1]);

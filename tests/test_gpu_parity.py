@@ -265,3 +265,42 @@ def test_tuned_context_matches_untuned():
         e = (torch.linalg.vector_norm((a.delta[i] - b.delta[i]).double()) /
              torch.linalg.vector_norm(a.delta[i].double())).item()
         assert e < 2e-6, (i + 1, e)
+
+
+def _own_theta1(grid, nmax):
+    """Orders outputs where theta_1 and its spectrum have buffers of their own,
+    filled with NaN so that a missed store shows."""
+    out = g.alloc_orders(grid, nmax, True)
+    out.theta[0] = torch.full_like(out.delta[0], float("nan"))
+    out.theta_k[0] = torch.full_like(out.delta_k[0], float("nan"))
+    return out
+
+
+@pytest.mark.parametrize("dtype", [g.F64, g.F32])
+@pytest.mark.parametrize("nmax", [1, 2, 3, 5])
+def test_separate_theta1_buffers(ctx, dtype, nmax):
+    """theta_1 = delta_1 (growing mode): with theta_1 in its own buffer the library
+    writes it as a second copy of delta_1, bit for bit, on the two-call path
+    (delta_1 given), the seeded path and the P-form; every order still matches
+    the oracle."""
+    n, box, seed = 32, 200.0, 41
+    cut = g.cut_n2max(n, box)
+    grid = g.Grid(n, box, g.cube_kc(cut), dtype)
+    lp = g.LinearSpectrum(amp=_amp(), ns=NS, gamma=GAMMA, growth=1.0, n2max=cut, seed=seed, stream=2)
+    ref1 = _rounded(oracle.linear_field(n, box, lp.amp, NS, GAMMA, 1.0, cut, seed, 2), grid)
+    refs = {form: oracle.orders(ref1, box, nmax, cut, cut, form=form, spectra=False)[:2] for form in "DP"}
+    runs = {
+        "given": lambda o: g.orders(ctx, grid, nmax, cut, cut, _to_dev(ref1, grid), out=o),
+        "seeded": lambda o: g.orders_linear(ctx, grid, lp, nmax, cut, out=o),
+        "pform": lambda o: g.orders_pform(ctx, grid, nmax, cut, cut, _to_dev(ref1, grid), out=o),
+    }
+    for name, run in runs.items():
+        out = _own_theta1(grid, nmax)
+        run(out)
+        ctx.sync()
+        assert torch.equal(out.theta[0], out.delta[0]), name
+        assert torch.equal(out.theta_k[0], out.delta_k[0]), name
+        rd, rt = refs["P" if name == "pform" else "D"]
+        for i in range(nmax):
+            assert rel_l2(out.delta[i].cpu().numpy(), rd[i]) < TOL[dtype], (name, i + 1)
+            assert rel_l2(out.theta[i].cpu().numpy(), rt[i]) < TOL[dtype], (name, i + 1)
