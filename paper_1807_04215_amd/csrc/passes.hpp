@@ -162,14 +162,16 @@ __device__ __forceinline__ void stage_row(const cpx<T> (&v)[PL::E], cpx<T>* row,
 // rr, read from in[q * stride + rr].  Every lane loads (items past `count`
 // read item count - 1, rows past `nrows` read row 0; both are dropped later),
 // so all loads are in flight together and can be issued before other work.
+// tid: the thread's index within its team of THREADS (default: the block).
 template <typename T, int N, int V, int ITEMS>
 __device__ __forceinline__ void gather_runs(cpx<T> (&g)[ITEMS], const cpx<T>* in, uint32_t stride, int count,
-                                           int nrows) {
+                                           int nrows, int tid = -1) {
     using RW = Rows<T, N, V>;
     constexpr int RPB = RW::RPB;
+    const int t = tid < 0 ? (int)threadIdx.x : tid;
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
-        const int idx = min((int)threadIdx.x + RW::THREADS * it, count * RPB - 1);
+        const int idx = min(t + RW::THREADS * it, count * RPB - 1);
         const int q = idx / RPB, rr = idx % RPB;
         g[it] = ldo(in, (uint32_t)q * stride + (uint32_t)(rr < nrows ? rr : 0));
     }
@@ -180,18 +182,20 @@ __device__ __forceinline__ void gather_runs(cpx<T> (&g)[ITEMS], const cpx<T>* in
 // parts first; afterwards v[e] holds position l + P e of this wave's row, or
 // zero where has(l + P e) is false.  Starts with a block barrier (the rows may
 // still be in use) and leaves every row free for this wave's own exchanges.
+// lds: the team's rows; tid as for gather_runs.
 template <typename T, int N, int V, int ITEMS, typename PosF, typename HasF, int E>
 __device__ __forceinline__ void scatter_runs_split(const cpx<T> (&g)[ITEMS], T* lds, const T* row, int l, int count,
-                                                   PosF pos, HasF has, cpx<T> (&v)[E]) {
+                                                   PosF pos, HasF has, cpx<T> (&v)[E], int tid = -1) {
     using RW = Rows<T, N, V>;
     constexpr int RPB = RW::RPB, ROWE = RW::ROWE, P = RW::P;
     static_assert(E == RW::E, "register count of the row");
+    const int t = tid < 0 ? (int)threadIdx.x : tid;
 #pragma unroll
     for (int part = 0; part < 2; ++part) {
         __syncthreads();
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
-            const int idx = (int)threadIdx.x + RW::THREADS * it;
+            const int idx = t + RW::THREADS * it;
             if (idx < count * RPB) lds[(idx % RPB) * ROWE + lds_pad(pos(idx / RPB))] = part ? g[it].y : g[it].x;
         }
         __syncthreads();
@@ -552,14 +556,16 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_zchain(Produ
 // field fewer; V_x and W go through a plain launch.
 // --------------------------------------------------------------------------
 template <typename T, int N, int V, bool COMB = false>
-__global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yfwd(const cpx<T>* __restrict__ s1, size_t s1_field,
-                                                                    cpx<T>* __restrict__ s2, size_t s2_field,
-                                                                    const cpx<T>* __restrict__ tw, CubeDims cd,
-                                                                    size_t zs, int in_step, int out_step) {
+__global__ __launch_bounds__(((COMB ? 2 : 1) * Rows<T, N, V>::THREADS)) void k_yfwd(
+    const cpx<T>* __restrict__ s1, size_t s1_field, cpx<T>* __restrict__ s2, size_t s2_field,
+    const cpx<T>* __restrict__ tw, CubeDims cd, size_t zs, int in_step, int out_step) {
     using RW = Rows<T, N, V>;
     using PL = typename RW::PL;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
-    __shared__ T lds[RPB * ROWE];  // real-valued rows (split exchange)
+    // COMB: two teams of THREADS, team 0 transforms V_y and team 1 V_z of the same rows
+    constexpr int TEAMS = COMB ? 2 : 1;
+    static_assert(TEAMS * RW::THREADS <= 1024, "block too large");
+    __shared__ T lds[TEAMS * RPB * ROWE];  // real-valued rows (split exchange), per team
     // twiddles in LDS for FP32 (this pass's LDS traffic is light), else from the cache
     constexpr bool LT = kLdsTwiddles<T> && true;
     __shared__ cpx<T> twl[LT ? PL::TW_ALLOC : 1];
@@ -573,16 +579,19 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yfwd(const cpx<T>*
     const uint32_t blk = xcd_block(blockIdx.x, N * groups);
     const int x = blk / groups, kz0 = (blk % groups) * RPB;
     const int nrows = min(RPB, cd.Kz - kz0);
-    const int r = threadIdx.x / P, l = threadIdx.x % P;
-    T* row = lds + r * ROWE;
+    const int team = COMB ? (int)threadIdx.x / RW::THREADS : 0;
+    const int tid = (int)threadIdx.x - team * RW::THREADS;
+    const int r = tid / P, l = tid % P;
+    T* tl = lds + team * RPB * ROWE;
+    T* row = tl + r * ROWE;
     // the S1 tile holding kz0 .. kz0 + nrows - 1 (RPB divides the tile width TZ)
     constexpr int TZ = kTileZ<T, N>;
     const int tb = kz0 / TZ * TZ, w = min(TZ, cd.Kz - tb);
     auto transform = [&](int f, cpx<T>(&v)[E]) {
         cpx<T> g[E];
         gather_runs<T, N, V>(g, s1 + (size_t)f * s1_field + (size_t)x * N * cd.Kz + (size_t)tb * N + (kz0 - tb),
-                             (uint32_t)w, N, nrows);
-        scatter_runs_split<T, N, V>(g, lds, row, l, N, [](int q) { return q; }, [](int) { return true; }, v);
+                             (uint32_t)w, N, nrows, tid);
+        scatter_runs_split<T, N, V>(g, tl, row, l, N, [](int q) { return q; }, [](int) { return true; }, v, tid);
         fft_row_split<PL, -1, T>(v, row, tws, l);
     };
     cpx<T> v[E];
@@ -591,15 +600,23 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_yfwd(const cpx<T>*
         transform((int)blockIdx.y * in_step, v);
     } else {
         // D = i ky V_y + i kz V_z (inputs 1 and 2), the y and z terms of i k.V (integer
-        // ky, kz; the x pass adds i kx V_x and applies kF)
-        cpx<T> vz[E];
-        transform(1, v);
-        transform(2, vz);
+        // ky, kz; the x pass adds i kx V_x and applies kF).  Team 1 hands its V_z rows to
+        // team 0 through LDS, as complex rows.
+        transform(1 + team, v);
+        __syncthreads();  // both teams are done with their exchange rows
+        cpx<T>* xrow = reinterpret_cast<cpx<T>*>(lds) + r * ROWE;
+        if (team == 1) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) xrow[lds_pad(l + P * e)] = v[e];
+        }
+        __syncthreads();
+        if (team == 1) return;
         const T kz = (T)(kz0 + r);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
+            const cpx<T> vz = xrow[lds_pad(l + P * e)];
             const T ky = (T)signed_pos(l + P * e, N);
-            v[e] = cmul_i(cpx<T>{ky * v[e].x + kz * vz[e].x, ky * v[e].y + kz * vz[e].y});
+            v[e] = cmul_i(cpx<T>{ky * v[e].x + kz * vz.x, ky * v[e].y + kz * vz.y});
         }
     }
     // S2 row (kz0 + r, x): the kept ky in compact order

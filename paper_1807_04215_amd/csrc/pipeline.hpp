@@ -211,8 +211,8 @@ struct Pipe {
             GRIDSPT_CHECK(launch(c, KD_YFWD, nb() * 2.0 * (d.s1() + d.s2()) * d.cpx_bytes, grid, block, 0,
                                  k_yfwd<T, N, V>, (const cpx<T>*)A(), (size_t)L.a_field_s1, B(),
                                  (size_t)L.b_field_s2, (const cpx<T>*)tw(), cd, bt.zs, 3, 2));
-            return launch(c, KD_YFWD, nb() * (2.0 * d.s1() + d.s2()) * d.cpx_bytes, dim3(grid.x, 1, nz()), block, 0,
-                          k_yfwd<T, N, V, true>, (const cpx<T>*)A(), (size_t)L.a_field_s1, B(), (size_t)L.b_field_s2,
+            return launch(c, KD_YFWD, nb() * (2.0 * d.s1() + d.s2()) * d.cpx_bytes, dim3(grid.x, 1, nz()),
+                          dim3(2 * RW::THREADS), 0, k_yfwd<T, N, V, true>, (const cpx<T>*)A(), (size_t)L.a_field_s1, B(), (size_t)L.b_field_s2,
                           (const cpx<T>*)tw(), cd, bt.zs, 0, 0);
         });
     }
