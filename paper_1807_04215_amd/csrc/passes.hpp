@@ -43,6 +43,17 @@ constexpr int pow2_floor(int v) {
     return p;
 }
 
+// Row stride (elements of `dw` dwords) at least `minimum` whose dword offset
+// between consecutive rows is 64 / RPB modulo 64: a transposed scatter, in
+// which consecutive lanes write the same position of consecutive rows, then
+// writes 64 distinct banks per 256 bytes.  `minimum` where that is impossible.
+constexpr int spread_stride(int minimum, int rpb, int dw) {
+    const int m = 64 / dw;  // elements per 64 dwords
+    if (rpb > 64 / dw || (64 / rpb) % dw != 0) return minimum;
+    const int want = 64 / rpb / dw;
+    return minimum + ((want - minimum % m) % m + m) % m;
+}
+
 // Block shape of a pass kernel.  Variant V (a launch-time choice of the
 // autotuner): bits 0-1 divide the rows per block by 2^(V & 3), bit 2 caps the
 // later FFT radices at 4.  Rows per block: about 64 KB of LDS, at most 32,
@@ -58,6 +69,14 @@ struct Rows {
     static constexpr int P = PL::P, E = PL::E;
     static constexpr int THREADS = RPB * P;
     static constexpr int ROWE = lds_row_elems(N);
+    // Row stride of the x pass's complex rows, into which it scatters transposed runs:
+    // spread over the banks where one wavefront holds one row (P = 64), so no exchange
+    // sees another row; else ROWE.
+    static constexpr int CPX_ROWE = P == 64 ? spread_stride(ROWE, RPB, 2 * (int)sizeof(T) / 4) : ROWE;
+    // Complex staging rows of the z inverse (two fields in the chained pass): at
+    // least N / 2 elements, at most ROWE / 2 (the LDS of RPB real rows).
+    static constexpr int SROW0 = spread_stride(N / 2, RPB, 2 * (int)sizeof(T) / 4);
+    static constexpr int SROW = SROW0 <= ROWE / 2 ? SROW0 : ROWE / 2;
     static_assert(THREADS <= 1024, "block too large");
 };
 
@@ -452,8 +471,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_zchain(Produ
     // z inverse of the latest order: pair q packs fields f[2q] + i f[2q+1].  The
     // staged runs of the two fields sit side by side in LDS (rows of SROW >= Kz
     // complex elements); position p of the Hermitian row takes kz = p or N - p.
-    constexpr int IT = E / 2, SROW = ROWE / 2;
-    static_assert(SROW >= N / 2, "a staged row holds every kept kz");
+    constexpr int IT = E / 2, SROW = RW::SROW;
+    static_assert(SROW >= N / 2 && 2 * SROW <= ROWE, "a staged row holds every kept kz");
     cpx<T>* stage = lds;
     T* xrow = reinterpret_cast<T*>(lds) + r * ROWE;
     auto src = [&](int p) { return p < Kz ? p : (p > N - Kz ? N - p : 0); };
@@ -687,7 +706,8 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
     using RW = Rows<T, N, V>;
     using PL = typename RW::PL;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
-    __shared__ cpx<T> lds[RPB * ROWE];
+    constexpr int CS = RW::CPX_ROWE;
+    __shared__ cpx<T> lds[RPB * CS];
     // FP32 twiddles in LDS: a global-table read at every pass would leave its latency
     // exposed at this pass's low occupancy
     constexpr bool LT = kLdsTwiddles<T> && true;
@@ -707,7 +727,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
     const bool active = kyc < cd.Ky;
     const int ky = active ? (kyc <= cd.Kc ? kyc : kyc - cd.Ky) : 0;
     const int nrows = min(RPB, cd.Ky - ky0);
-    cpx<T>* row = lds + r * ROWE;
+    cpx<T>* row = lds + r * CS;
 
     // k-space step: sd holds delta_n(k), st holds theta_n(k) afterwards
     cpx<T> sd[E], st[E];
@@ -748,7 +768,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
 #pragma unroll
         for (int it = 0; it < E; ++it) {
             const int idx = (int)threadIdx.x + RW::THREADS * it;
-            lds[(idx % RPB) * ROWE + lds_pad(idx / RPB)] = g[it];
+            lds[(idx % RPB) * CS + lds_pad(idx / RPB)] = g[it];
         }
         __syncthreads();
         cpx<T> v[E];
@@ -1266,8 +1286,8 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_zinv(const cpx<T>*
     // real-valued exchange rows (split exchange); before the transform the same
     // LDS holds the staged runs as complex rows of SROW >= Kz elements
     __shared__ __align__(16) T lds[RPB * ROWE];
-    constexpr int SROW = ROWE / 2;
-    static_assert(SROW >= N / 2, "a staged row holds every kept kz");
+    constexpr int SROW = RW::SROW;
+    static_assert(SROW >= N / 2 && 2 * SROW <= ROWE, "a staged row holds every kept kz");
     const int job = blockIdx.y;
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     const size_t q0 = (size_t)blk * 2 * RPB;  // first row (x N + y) of the block
