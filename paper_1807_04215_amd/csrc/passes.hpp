@@ -53,6 +53,9 @@ constexpr int spread_stride(int minimum, int rpb, int dw) {
     const int want = 64 / rpb / dw;
     return minimum + ((want - minimum % m) % m + m) % m;
 }
+static_assert(spread_stride(512, 8, 2) == 516 && spread_stride(512, 4, 2) == 520, "FP32 staging rows, N = 1024");
+static_assert(spread_stride(1089, 8, 2) == 1092 && spread_stride(1089, 4, 4) == 1092, "complex rows, N = 1024");
+static_assert(spread_stride(9, 64, 2) == 9, "no spread for more rows than 64-dword slots");
 
 // Block shape of a pass kernel.  Variant V (a launch-time choice of the
 // autotuner): bits 0-1 divide the rows per block by 2^(V & 3), bit 2 caps the
