@@ -532,17 +532,39 @@ struct MomentArgs {
     int nf;
     size_t ncell;
     double* partial;  // [gridDim.x][kStatsQ]
+    // one-point histograms (k_moments_partial<T, NF, true>): nbins bins of width
+    // 1 / scale from lo, per-block counts [nf][gridDim.x][nbins]; hcopies LDS
+    // copies (one per wavefront, or one per block when those would not fit)
+    uint32_t* hpart;
+    int nbins, hcopies;
+    double lo, scale;
 };
 
 __host__ __device__ constexpr int pair_index(int i, int j) {  // i < j < 8
     return i * kStatsMaxFields - i * (i + 1) / 2 + (j - i - 1);
 }
 
+template <typename T>
+__device__ __forceinline__ int bin_of(T x, double lo, double scale, int nbins) {
+    const double fb = floor(((double)x - lo) * scale);
+    return (fb >= 0.0 && fb < (double)nbins) ? (int)fb : -1;
+}
+
 // NF = a.nf fields, a template argument so that every load of a cell is
-// unconditional and all of them are in flight together.
-template <typename T, int NF>
+// unconditional and all of them are in flight together.  HIST: the same pass
+// also counts every field's one-point histogram, each wavefront into its own
+// LDS copy (fewer lanes collide on one bin's atomic; counts are integers, so
+// the order does not matter), so the fields are read once for both.
+template <typename T, int NF, bool HIST>
 __global__ __launch_bounds__(kStatsThreads) void k_moments_partial(MomentArgs<T> a) {
     __shared__ double red[kStatsQ * (kStatsThreads / 64)];
+    extern __shared__ uint32_t hl[];  // HIST: [hcopies][NF][nbins]
+    const int hsize = NF * a.nbins;
+    if constexpr (HIST) {
+        for (int i = threadIdx.x; i < a.hcopies * hsize; i += blockDim.x) hl[i] = 0u;
+        __syncthreads();
+    }
+    uint32_t* hw = hl + (int)(threadIdx.x / 64) % (a.hcopies > 0 ? a.hcopies : 1) * hsize;
     double s[kStatsMaxFields][4], x[kStatsQ - 4 * kStatsMaxFields];
 #pragma unroll
     for (int i = 0; i < kStatsMaxFields; ++i)
@@ -555,6 +577,13 @@ __global__ __launch_bounds__(kStatsThreads) void k_moments_partial(MomentArgs<T>
         double v[NF];
 #pragma unroll
         for (int i = 0; i < NF; ++i) v[i] = (double)a.f[i][c];
+        if constexpr (HIST) {
+#pragma unroll
+            for (int i = 0; i < NF; ++i) {
+                const int b = bin_of(v[i], a.lo, a.scale, a.nbins);
+                if (b >= 0) atomicAdd(&hw[i * a.nbins + b], 1u);
+            }
+        }
 #pragma unroll
         for (int i = 0; i < NF; ++i) {
             const double p2 = v[i] * v[i];
@@ -581,6 +610,15 @@ __global__ __launch_bounds__(kStatsThreads) void k_moments_partial(MomentArgs<T>
         double t = 0.0;
         for (int w = 0; w < NW; ++w) t += red[q * NW + w];
         out[q] = t;
+    }
+    if constexpr (HIST) {
+        // the waves' counts of this block (the barrier above ordered every atomic)
+        for (int i = threadIdx.x; i < hsize; i += blockDim.x) {
+            uint32_t t = 0u;
+            for (int w = 0; w < a.hcopies; ++w) t += hl[w * hsize + i];
+            const int f = i / a.nbins, b = i % a.nbins;
+            a.hpart[((size_t)f * gridDim.x + blockIdx.x) * a.nbins + b] = t;
+        }
     }
 }
 
@@ -620,40 +658,31 @@ static __global__ void k_moments_final(const double* sums, int nf, double ncell,
 template <typename T>
 struct HistArgs {
     const T* f[kStatsMaxFields];
-    int nbins;       // per axis
-    int joint;       // set by the caller for k_hist_partial<T, true>: joint of field 0 and field 1 + blockIdx.y
+    int nbins;  // per axis
     double lo, scale;
     size_t ncell;
-    uint32_t* partial;  // [gridDim.y][gridDim.x][nb], nb = nbins or nbins^2
+    uint32_t* partial;  // [gridDim.y][gridDim.x][nbins^2]
 };
 
+// Joint histogram of field 0 and field 1 + blockIdx.y.  Each wavefront counts
+// into its own LDS histogram (fewer lanes collide on one bin's atomic), the
+// block adds its wavefronts' counts at the end; counts are integers, so the
+// order does not matter.  A thread takes 16 bytes of consecutive cells of
+// each field per step (the tail, if any, one cell at a time).
 template <typename T>
-__device__ __forceinline__ int bin_of(T x, double lo, double scale, int nbins) {
-    const double fb = floor(((double)x - lo) * scale);
-    return (fb >= 0.0 && fb < (double)nbins) ? (int)fb : -1;
-}
-
-// Each wavefront counts into its own LDS histogram (fewer lanes collide on one
-// bin's atomic), the block adds its wavefronts' counts at the end; counts are
-// integers, so the order does not matter.  A thread takes 16 bytes of
-// consecutive cells per step (the tail, if any, one cell at a time).
-template <typename T, bool JOINT>
-__global__ __launch_bounds__(kStatsThreads) void k_hist_partial(HistArgs<T> a) {
-    extern __shared__ uint32_t h[];  // [waves][nb]
+__global__ __launch_bounds__(kStatsThreads) void k_joint_partial(HistArgs<T> a) {
+    extern __shared__ uint32_t h[];  // [waves][nbins^2]
     constexpr int NW = kStatsThreads / 64;
-    const int nb = JOINT ? a.nbins * a.nbins : a.nbins;
+    const int nb = a.nbins * a.nbins;
     for (int i = threadIdx.x; i < NW * nb; i += blockDim.x) h[i] = 0u;
     __syncthreads();
     uint32_t* hw = h + (threadIdx.x / 64) * nb;
-    const T* x = JOINT ? a.f[0] : a.f[blockIdx.y];
-    const T* y = JOINT ? a.f[1 + blockIdx.y] : nullptr;
+    const T* x = a.f[0];
+    const T* y = a.f[1 + blockIdx.y];
     auto count = [&](T xv, T yv) {
-        int b = bin_of(xv, a.lo, a.scale, a.nbins);
-        if (JOINT && b >= 0) {
-            const int b2 = bin_of(yv, a.lo, a.scale, a.nbins);
-            b = b2 >= 0 ? b * a.nbins + b2 : -1;
-        }
-        if (b >= 0) atomicAdd(&hw[b], 1u);
+        const int b = bin_of(xv, a.lo, a.scale, a.nbins);
+        const int b2 = bin_of(yv, a.lo, a.scale, a.nbins);
+        if (b >= 0 && b2 >= 0) atomicAdd(&hw[b * a.nbins + b2], 1u);
     };
     // U vectors per thread per step, all loaded before the first is counted
     constexpr int VW = 16 / (int)sizeof(T), U = 4;
@@ -667,7 +696,7 @@ __global__ __launch_bounds__(kStatsThreads) void k_hist_partial(HistArgs<T> a) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             vx[u] = xv[(s * U + u) * stride + t0];
-            vy[u] = JOINT ? yv[(s * U + u) * stride + t0] : vx[u];
+            vy[u] = yv[(s * U + u) * stride + t0];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -679,13 +708,13 @@ __global__ __launch_bounds__(kStatsThreads) void k_hist_partial(HistArgs<T> a) {
     }
     // the remaining vectors one at a time, then the cells past the last whole vector
     for (size_t c = nstep * U * stride + t0; c < nv; c += stride) {
-        const Vec vx = xv[c], vy = JOINT ? yv[c] : vx;
+        const Vec vx = xv[c], vy = yv[c];
         const T* px = reinterpret_cast<const T*>(&vx);
         const T* py = reinterpret_cast<const T*>(&vy);
 #pragma unroll
         for (int k = 0; k < VW; ++k) count(px[k], py[k]);
     }
-    for (size_t c = nv * VW + t0; c < a.ncell; c += stride) count(x[c], JOINT ? y[c] : x[c]);
+    for (size_t c = nv * VW + t0; c < a.ncell; c += stride) count(x[c], y[c]);
     __syncthreads();
     uint32_t* out = a.partial + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * nb;
     for (int i = threadIdx.x; i < nb; i += blockDim.x) {

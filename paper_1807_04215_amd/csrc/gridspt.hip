@@ -914,11 +914,13 @@ int gridspt_power(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, const 
 
 // ---- one-point statistics ----
 
+// kMomentBlocks: the moments pass (with the one-point histograms); kHistBlocks:
+// the joint histograms
 static constexpr int kMomentBlocks = 1024, kHistBlocks = 512;
 
 static int64_t stats_ws(int nfields, int nbins, int nbins2) {
     int64_t b = align_up((int64_t)kMomentBlocks * kStatsQ * 8) + align_up((int64_t)kStatsQ * 8);
-    if (nbins > 0) b += align_up((int64_t)nfields * kHistBlocks * nbins * 4);
+    if (nbins > 0) b += align_up((int64_t)nfields * kMomentBlocks * nbins * 4);
     if (nbins2 > 0 && nfields > 1) b += align_up((int64_t)(nfields - 1) * kHistBlocks * nbins2 * nbins2 * 4);
     return b;
 }
@@ -952,51 +954,56 @@ int gridspt_field_stats(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, 
     char* hbase = base + align_up((int64_t)kMomentBlocks * kStatsQ * 8) + align_up((int64_t)kStatsQ * 8);
     uint32_t* hpart = reinterpret_cast<uint32_t*>(hbase);
     uint32_t* jpart =
-        reinterpret_cast<uint32_t*>(hbase + (counts ? align_up((int64_t)nfields * kHistBlocks * nbins * 4) : 0));
+        reinterpret_cast<uint32_t*>(hbase + (counts ? align_up((int64_t)nfields * kMomentBlocks * nbins * 4) : 0));
     auto go = [&](auto tag) -> int {
         using T = typename decltype(tag)::type;
-        if (moments || corr) {
+        if (moments || corr || counts) {
+            // one pass over the fields: the moment sums and, if asked, the one-point counts
             MomentArgs<T> a{};
             for (int i = 0; i < nfields; ++i) a.f[i] = static_cast<const T*>(fields[i]);
             a.nf = nfields;
             a.ncell = ncell;
             a.partial = mpart;
+            a.hpart = hpart;
+            a.nbins = counts ? nbins : 0;
+            a.lo = lo;
+            a.scale = counts ? (double)nbins / (hi - lo) : 0.0;
+            // one LDS histogram per wavefront while they fit in 64 KB, else one per block
+            const size_t hone = (size_t)nfields * nbins * 4;
+            a.hcopies = (kStatsThreads / 64) * hone <= 65536 ? kStatsThreads / 64 : 1;
+            const size_t hlds = counts ? a.hcopies * hone : 0;
             int rc = GRIDSPT_OK;
             static_for<kStatsMaxFields>([&](auto k) {
                 constexpr int NF = decltype(k)::value + 1;
                 if (NF == nfields)
-                    rc = launch(c, KD_MOMENTS, (double)nfields * ncell * d.real_bytes, dim3(kMomentBlocks),
-                                dim3(kStatsThreads), 0, k_moments_partial<T, NF>, a);
+                    rc = counts ? launch(c, KD_MOMENTS, (double)nfields * ncell * d.real_bytes, dim3(kMomentBlocks),
+                                         dim3(kStatsThreads), hlds, k_moments_partial<T, NF, true>, a)
+                                : launch(c, KD_MOMENTS, (double)nfields * ncell * d.real_bytes, dim3(kMomentBlocks),
+                                         dim3(kStatsThreads), 0, k_moments_partial<T, NF, false>, a);
             });
             CHECK(rc);
-            CHECK(launch(c, KD_MOMENTS, (double)kMomentBlocks * kStatsQ * 8, dim3(kStatsQ), dim3(kReduceThreads), 0,
-                         k_power_reduce, (const double*)mpart, kMomentBlocks, kStatsQ, msum, (size_t)0));
-            CHECK(launch(c, KD_MOMENTS, 0.0, dim3(1), dim3(64), 0, k_moments_final, (const double*)msum, nfields,
-                         (double)ncell, moments, corr));
+            if (moments || corr) {
+                CHECK(launch(c, KD_MOMENTS, (double)kMomentBlocks * kStatsQ * 8, dim3(kStatsQ), dim3(kReduceThreads),
+                             0, k_power_reduce, (const double*)mpart, kMomentBlocks, kStatsQ, msum, (size_t)0));
+                CHECK(launch(c, KD_MOMENTS, 0.0, dim3(1), dim3(64), 0, k_moments_final, (const double*)msum, nfields,
+                             (double)ncell, moments, corr));
+            }
+            if (counts)
+                CHECK(launch(c, KD_HIST, 0.0, dim3((nbins + kHistRedBins - 1) / kHistRedBins, nfields),
+                             dim3(kHistRedBins, kHistRedSlices), 0, k_hist_reduce, (const uint32_t*)hpart,
+                             kMomentBlocks, nbins, counts));
         }
         HistArgs<T> h{};
         for (int i = 0; i < nfields; ++i) h.f[i] = static_cast<const T*>(fields[i]);
         h.lo = lo;
         h.ncell = ncell;
-        if (counts) {
-            h.nbins = nbins;
-            h.joint = 0;
-            h.scale = (double)nbins / (hi - lo);
-            h.partial = hpart;
-            CHECK(launch(c, KD_HIST, (double)nfields * ncell * d.real_bytes, dim3(kHistBlocks, nfields),
-                         dim3(kStatsThreads), (size_t)nbins * 4 * (kStatsThreads / 64), k_hist_partial<T, false>, h));
-            CHECK(launch(c, KD_HIST, 0.0, dim3((nbins + kHistRedBins - 1) / kHistRedBins, nfields),
-                         dim3(kHistRedBins, kHistRedSlices), 0, k_hist_reduce, (const uint32_t*)hpart, kHistBlocks,
-                         nbins, counts));
-        }
         if (joint) {
             const int nb2 = nbins2 * nbins2;
             h.nbins = nbins2;
-            h.joint = 1;
             h.scale = (double)nbins2 / (hi - lo);
             h.partial = jpart;
             CHECK(launch(c, KD_HIST, 2.0 * (nfields - 1) * ncell * d.real_bytes, dim3(kHistBlocks, nfields - 1),
-                         dim3(kStatsThreads), (size_t)nb2 * 4 * (kStatsThreads / 64), k_hist_partial<T, true>, h));
+                         dim3(kStatsThreads), (size_t)nb2 * 4 * (kStatsThreads / 64), k_joint_partial<T>, h));
             CHECK(launch(c, KD_HIST, 0.0, dim3((nb2 + kHistRedBins - 1) / kHistRedBins, nfields - 1),
                          dim3(kHistRedBins, kHistRedSlices), 0, k_hist_reduce, (const uint32_t*)jpart, kHistBlocks,
                          nb2, joint));

@@ -104,3 +104,24 @@ def test_stats_properties_at_512(ctx):
     c = cor.cpu().numpy()
     assert abs(c[0, 2] - 1.0) < 1e-12 and abs(c[0, 1] + 1.0) < 1e-12
     assert abs(mom[0, 1].item() - 1.0) < 1e-3
+
+
+@pytest.mark.parametrize("dtype", [g.F64, g.F32])
+def test_histograms_many_bins_and_moments_alone(ctx, dtype):
+    """Eight fields and 1024 bins (the one-point counts then share one LDS copy
+    per block instead of one per wavefront) against the oracle's histogram; the
+    moments without histograms equal, bit for bit, those of the pass that also
+    counts (the same cells in the same order)."""
+    n = 32
+    grid = g.Grid(n, 200.0, 10, dtype)
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    fields = [torch.randn((n,) * 3, generator=gen, device="cuda", dtype=grid.real_dtype) * (0.5 + 0.1 * i)
+              for i in range(8)]
+    mom, cor, cnt, _ = g.field_stats(ctx, grid, fields, nbins=1024, lo=-3.0, hi=3.0)
+    mom0, cor0, cnt0, _ = g.field_stats(ctx, grid, fields, nbins=0)
+    ctx.sync()
+    assert cnt0 is None
+    assert torch.equal(mom, mom0) and torch.equal(cor, cor0)
+    for i, f in enumerate(fields):
+        ref = stats.histogram(f.cpu().numpy().astype(np.float64), -3.0, 3.0, 1024)
+        assert np.array_equal(cnt[i].cpu().numpy(), ref), i
