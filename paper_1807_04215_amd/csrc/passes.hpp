@@ -1181,31 +1181,30 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xsmooth(SmoothArgs
         const double n2 = (double)((int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz);
         w[e] = (active && pos_to_compact(p, cd.Kc, N) >= 0) ? (T)exp(g * n2) : (T)0;
     }
+    // cumulative: the running sum sum_{i <= o} coef_i F_i, each spectrum read once
+    // (the same additions in the same order as summing each output afresh)
+    cpx<T> acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = {(T)0, (T)0};
     static_for<5>([&](auto oc) {
         constexpr int o = decltype(oc)::value;
         if (o >= a.nin) return;
+        if (!a.cumulative) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e] = {(T)0, (T)0};
+        }
+        // uniform branch on the mode; the loads inside are unconditional (w = 0 off the cube)
+        const cpx<T>* cb = zptr(a.cube[o], zs);
+        const T co = (T)a.coef[o];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int ic = pos_to_compact(l + P * e, cd.Kc, N);
+            const bool ok = active && ic >= 0;
+            acc[e] = cadd(acc[e], cscale(load_or_zero(cb, ok ? cbase + ic : 0, ok), co));
+        }
         cpx<T> v[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = {(T)0, (T)0};
-        // uniform branch on the mode; the loads inside are unconditional (w = 0 off the cube)
-        auto add = [&](int i) {
-            const cpx<T>* cb = zptr(a.cube[i], zs);
-            const T ci = (T)a.coef[i];
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int ic = pos_to_compact(l + P * e, cd.Kc, N);
-                const bool ok = active && ic >= 0;
-                v[e] = cadd(v[e], cscale(load_or_zero(cb, ok ? cbase + ic : 0, ok), ci));
-            }
-        };
-        if (a.cumulative) {
-#pragma unroll
-            for (int i = 0; i <= o; ++i) add(i);
-        } else {
-            add(o);
-        }
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = cscale(v[e], w[e]);
+        for (int e = 0; e < E; ++e) v[e] = cscale(acc[e], w[e]);
         x_inverse_store<T, N, V>(v, row, tws, l, s3 + (size_t)o * a.s3_field + outbase, r, active);
     });
 }
