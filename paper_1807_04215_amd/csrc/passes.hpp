@@ -1101,6 +1101,18 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xderived(RegenArgs
     cpx<T>* s3 = zptr(a.s3, zs);
     cpx<T>* row = lds + r * ROWE;
     const size_t outbase = ((size_t)kz * cd.Ky + ky0) * N;
+    // the row of each source spectrum, loaded once for the chunk's five outputs
+    // (delta for fields 0-2, theta for the rest)
+    constexpr int NSRC = CHUNK == 0 ? 2 : 1;
+    cpx<T> srcv[NSRC][E];
+#pragma unroll
+    for (int k = 0; k < NSRC; ++k)
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int ic = pos_to_compact(l + P * e, cd.Kc, N);
+            const bool ok = active && ic >= 0;
+            srcv[k][e] = load_or_zero((CHUNK == 0 && k == 0) ? cdl : ctl, ok ? cbase + ic : 0, ok);
+        }
     static_for<5>([&](auto oc) {
         constexpr int o = decltype(oc)::value;
         constexpr int fld = 5 * CHUNK + o;
@@ -1108,9 +1120,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xderived(RegenArgs
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int p = l + P * e;
-            const int ic = pos_to_compact(p, cd.Kc, N);
-            const bool ok = active && ic >= 0;
-            const cpx<T> src = load_or_zero(fld < 3 ? cdl : ctl, ok ? cbase + ic : 0, ok);
+            const cpx<T> src = srcv[(CHUNK == 0 && fld >= 3) ? 1 : 0][e];
             const int kx = signed_pos(p, N);
             auto kc = [&](int axis) { return axis == 0 ? kx : (axis == 1 ? ky : kz); };
             const int n2 = kx * kx + ky * ky + kz * kz;
