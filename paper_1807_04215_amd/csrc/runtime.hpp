@@ -24,7 +24,7 @@ enum Kind {
     KD_TWIDDLE,
     KD_ZFWD_FIELD,
     KD_ZFWD_NOISE,
-    KD_ZFWD_PRODUCTS,
+    KD_ZFWD_PRODUCTS,  // the product pass of an order (k_zchain: z inverse of order n - 1 + P1)
     KD_YFWD,
     KD_XFUSED_LINEAR,
     KD_XFUSED_ORDER1,
