@@ -234,10 +234,11 @@ __global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T>
     }
 }
 
-// One block per (bin, q): sum the block partials in a fixed order (strided
-// per thread, then an LDS tree) into sums[bin][q].
+// One block per item (gridDim.x items, e.g. bin * nq + q): sum the block
+// partials [nblocks][items] in a fixed order (strided per thread, then an LDS
+// tree) into sums[item].
 constexpr int kReduceThreads = 256;
-static __global__ __launch_bounds__(kReduceThreads) void k_power_reduce(const double* partial, int nblocks, int nq,
+static __global__ __launch_bounds__(kReduceThreads) void k_power_reduce(const double* partial, int nblocks,
                                                                  double* sums, size_t zs) {
     __shared__ double red[kReduceThreads];
     partial = zptr(partial, zs);

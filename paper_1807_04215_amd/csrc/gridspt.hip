@@ -121,7 +121,7 @@ int power_enqueue(gridspt_ctx* c, const gridspt_grid* g, const void* const* fiel
                 default: CHECK(launch(c, KD_POWER, pbytes, pgrid, pblock, shm, k_power_partial<T, 0>, a, cdims, bt.zs));
             }
             CHECK(launch(c, KD_POWER_FINAL, (double)nz * nblk * nbins * nq * 8.0, dim3(nbins * nq, 1, nz),
-                         dim3(kReduceThreads), 0, k_power_reduce, (const double*)partial, nblk, nq, sums, bt.zs));
+                         dim3(kReduceThreads), 0, k_power_reduce, (const double*)partial, nblk, sums, bt.zs));
             CHECK(launch(c, KD_POWER_FINAL, 0.0, dim3((nbins + 63) / 64, 1, nz), dim3(64), 0, k_power_final,
                          (const double*)sums, nbins, nq, np, pc, g->box * g->box * g->box, pk + (size_t)p0 * nbins,
                          nbins, p0 == 0 ? kmean : nullptr, p0 == 0 ? nmodes : nullptr, bt.zs));
@@ -984,7 +984,7 @@ int gridspt_field_stats(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, 
             CHECK(rc);
             if (moments || corr) {
                 CHECK(launch(c, KD_MOMENTS, (double)kMomentBlocks * kStatsQ * 8, dim3(kStatsQ), dim3(kReduceThreads),
-                             0, k_power_reduce, (const double*)mpart, kMomentBlocks, kStatsQ, msum, (size_t)0));
+                             0, k_power_reduce, (const double*)mpart, kMomentBlocks, msum, (size_t)0));
                 CHECK(launch(c, KD_MOMENTS, 0.0, dim3(1), dim3(64), 0, k_moments_final, (const double*)msum, nfields,
                              (double)ncell, moments, corr));
             }

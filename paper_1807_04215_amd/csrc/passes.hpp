@@ -708,7 +708,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
                                                                       CubeDims cd, size_t zs) {
     using RW = Rows<T, N, V>;
     using PL = typename RW::PL;
-    constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
+    constexpr int P = RW::P, RPB = RW::RPB, E = RW::E;
     constexpr int CS = RW::CPX_ROWE;
     __shared__ cpx<T> lds[RPB * CS];
     // FP32 twiddles in LDS: a global-table read at every pass would leave its latency
