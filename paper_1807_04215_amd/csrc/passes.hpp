@@ -477,7 +477,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_zchain(Produ
     constexpr int IT = E / 2, SROW = RW::SROW;
     static_assert(SROW >= N / 2 && 2 * SROW <= ROWE, "a staged row holds every kept kz");
     cpx<T>* stage = lds;
-    T* xrow = reinterpret_cast<T*>(lds) + r * ROWE;
+    cpx<T>* crow = lds + r * ROWE;  // this row's complex exchange row
     auto src = [&](int p) { return p < Kz ? p : (p > N - Kz ? N - p : 0); };
     const cpx<T>* s4x = ch.s4 + (size_t)x * Kz * N + y0;
     cpx<T> cur[2][E];
@@ -509,7 +509,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_zchain(Produ
             v[e] = p < Kz ? lo : (p > N - Kz ? hi : zero);
         }
         __syncthreads();  // every wave has read the staged runs before the exchanges reuse the LDS
-        fft_row_split<PL, +1, T>(v, xrow, tws, l);
+        fft_row<PL, +1, T>(v, crow, tws, l);
         T* o0 = ch.out[2 * q];
         T* o1 = ch.out[2 * q + 1];
         if (o0) {
