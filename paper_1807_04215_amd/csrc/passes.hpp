@@ -703,9 +703,13 @@ __device__ __forceinline__ void x_inverse_store(cpx<T> (&v)[E], cpx<T>* row, TW 
     }
 }
 
+// The orders' step in FP32 at N = 1024 asks for three waves per SIMD: it fits
+// 168 VGPRs with a few spills in the variants with larger blocks, and runs
+// faster than at two waves (at smaller N the same request spills more).
 template <typename T, int N, int V, int MODE>
-__global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a, const cpx<T>* __restrict__ tw,
-                                                                      CubeDims cd, size_t zs) {
+__global__ __launch_bounds__((Rows<T, N, V>::THREADS))
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && N == 1024 && MODE == XM_ORDER ? 3 : 1))) void k_xfused(
+    XArgs<T> a, const cpx<T>* __restrict__ tw, CubeDims cd, size_t zs) {
     using RW = Rows<T, N, V>;
     using PL = typename RW::PL;
     constexpr int P = RW::P, RPB = RW::RPB, E = RW::E;
@@ -792,10 +796,11 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
 #pragma unroll
                 for (int e = 0; e < E; ++e) st[e] = v[e];
             }
+            // pin only what has been assigned: a pinned all-zero row would hold 32 VGPRs
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 keep_here(sd[e]);
-                keep_here(st[e]);
+                if constexpr (f == 2) keep_here(st[e]);
             }
         } else if constexpr (MODE == XM_PFORM) {
             // the printed sources of Eq. 10, transformed as they are
@@ -804,7 +809,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
                 if constexpr (f == 0) sd[e] = v[e];
                 else st[e] = v[e];
                 keep_here(sd[e]);
-                keep_here(st[e]);
+                if constexpr (f > 0) keep_here(st[e]);
             }
         } else if constexpr (ADJ) {
             if constexpr (f == 0) {
@@ -824,7 +829,7 @@ __global__ __launch_bounds__((Rows<T, N, V>::THREADS)) void k_xfused(XArgs<T> a,
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 keep_here(sd[e]);
-                keep_here(st[e]);
+                if constexpr (f > 0) keep_here(st[e]);
             }
         } else {
 #pragma unroll
