@@ -703,12 +703,14 @@ __device__ __forceinline__ void x_inverse_store(cpx<T> (&v)[E], cpx<T>* row, TW 
     }
 }
 
-// The orders' step in FP32 at N = 1024 asks for three waves per SIMD: it fits
-// 168 VGPRs with a few spills in the variants with larger blocks, and runs
-// faster than at two waves (at smaller N the same request spills more).
+// The orders' step in FP32 at N = 1024 with blocks of at most four waves asks
+// for three waves per SIMD: it then fits 168 VGPRs with a few spills and runs
+// faster than at two waves.  Blocks of eight waves would still fit only one per
+// CU, and at smaller N the same request spills more.
 template <typename T, int N, int V, int MODE>
 __global__ __launch_bounds__((Rows<T, N, V>::THREADS))
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && N == 1024 && MODE == XM_ORDER ? 3 : 1))) void k_xfused(
+__attribute__((amdgpu_waves_per_eu(
+    sizeof(T) == 4 && N == 1024 && Rows<T, N, V>::THREADS <= 256 && MODE == XM_ORDER ? 3 : 1))) void k_xfused(
     XArgs<T> a, const cpx<T>* __restrict__ tw, CubeDims cd, size_t zs) {
     using RW = Rows<T, N, V>;
     using PL = typename RW::PL;
