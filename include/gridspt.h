@@ -59,7 +59,8 @@ typedef enum {
     GRIDSPT_EUNSUPPORTED = -2, /* valid, but not built: N not 2^a in [16, 1024] or 3 2^a in [48, 768], ... */
     GRIDSPT_EWORKSPACE = -3,   /* work is null or smaller than required */
     GRIDSPT_EALIGN = -4,       /* a device pointer is null or not 256-byte aligned */
-    GRIDSPT_EHIP = -5          /* the HIP runtime reported an error */
+    GRIDSPT_EHIP = -5,         /* the HIP runtime reported an error */
+    GRIDSPT_ENONFINITE = -6    /* an input field holds a NaN or an infinity (only with GRIDSPT_CHECK_FINITE) */
 } gridspt_status;
 
 typedef enum { GRIDSPT_F32 = 0, GRIDSPT_F64 = 1 } gridspt_dtype;
@@ -70,8 +71,18 @@ typedef struct {
     double box;    /* side L > 0 [Mpc/h] */
     int32_t kc;    /* half-width of the spectral cube, 1 <= kc < N/2; every mask
                       used with this grid needs floor(sqrt(n2max)) <= kc */
-    int32_t reserved;
+    uint32_t flags; /* 0, or GRIDSPT_CHECK_FINITE; other bits are GRIDSPT_EINVAL */
 } gridspt_grid;
+
+/* Grid flags.
+ * GRIDSPT_CHECK_FINITE: gridspt_forward, gridspt_orders, gridspt_orders_pform,
+ *   gridspt_noise_field and gridspt_adjoint first check every real input field
+ *   (delta1, field, noise, gdelta) on the device and return
+ *   GRIDSPT_ENONFINITE, with nothing else enqueued, if any value is a NaN or
+ *   an infinity.  The check waits for the context's stream (the call is then
+ *   not asynchronous) and reads each input once more; it uses the first 256
+ *   bytes of `work`.  Batches ignore the flag (they have no input fields). */
+enum { GRIDSPT_CHECK_FINITE = 1 };
 
 /* Linear power spectrum P0(k) = amp k^ns T_BBKS(k / gamma)^2 (k in h/Mpc,
  * Bardeen et al. 1986 transfer function), the growth factor multiplying the
@@ -122,9 +133,12 @@ int gridspt_growth(double om, double ol, double z, double* d);
 
 /* ---- hot path ---- */
 
-/* Device scratch needed by gridspt_linear_field, gridspt_forward and
- * gridspt_orders(nmax) on grid g. */
-int64_t gridspt_workspace_bytes(const gridspt_grid* g, int32_t nmax);
+/* Device scratch needed by gridspt_linear_field, gridspt_forward,
+ * gridspt_orders(nmax) and gridspt_orders_linear(nmax) on grid g, for calls
+ * made with the grid flags `flags | g->flags` (unknown bits:
+ * GRIDSPT_EINVAL).  Every workspace of this library already holds the 256
+ * bytes GRIDSPT_CHECK_FINITE uses, so no current flag changes the size. */
+int64_t gridspt_workspace_bytes(const gridspt_grid* g, int32_t nmax, uint32_t flags);
 
 /* Step (1) of Sec. II C.  delta1(x) = inverse transform of
  * W1(k) sqrt(P0(k) N^3 / L^3) D w(k), where w(k) is the forward transform of
@@ -142,6 +156,18 @@ int gridspt_linear_field(gridspt_ctx* ctx, const gridspt_grid* g, const gridspt_
  * field_k(k) = [0 < |n|^2 <= n2max] N^-3 sum_x field(x) e^{-ik.x}. */
 int gridspt_forward(gridspt_ctx* ctx, const gridspt_grid* g, int64_t n2max, const void* field, void* field_k,
                     void* work, int64_t work_bytes);
+
+/* A cube-layout spectrum in the usual half layout of a real-to-complex
+ * transform (the coefficients of Eq. 17): half is interleaved complex
+ * [ix][iy][iz], N x N x (N/2 + 1) elements, ix and iy the grid positions of
+ * signed modes (position i < N/2 is mode i, else i - N), iz = kz >= 0; every
+ * mode outside the cube (|n_i| > Kc, and the Nyquist planes) is written as
+ * zero.  For consumers that expect that layout (an inverse transform of
+ * another library, numpy's irfftn); the library's own estimators read cubes.
+ * The cube layout stays the library's output because every masked spectrum
+ * lives inside it: at 1024^3 with the strict 2/3 cut a cube is 1.28 GB in
+ * FP32 against 4.3 GB for the half layout. */
+int gridspt_spectrum_half(gridspt_ctx* ctx, const gridspt_grid* g, const void* cube, void* half);
 
 /* The recursion of Eq. 10 (n >= 2) and Eq. 11 (n = 1) up to nmax in [1, 5].
  * delta1: N^3 real input (any field; the mask W1 = n2max1 and the removal of
@@ -256,7 +282,8 @@ int gridspt_power(gridspt_ctx* ctx, const gridspt_grid* g, int32_t nfields, cons
                   int32_t npairs, const int32_t* pairs, int32_t nbins, const int64_t* edge_n2, double* pk,
                   double* kmean, double* nmodes, void* work, int64_t work_bytes);
 
-/* Device scratch needed by gridspt_bispectrum for these triangles and terms. */
+/* Device scratch needed by gridspt_bispectrum for these triangles and terms
+ * (room for the FP64 indicator transforms included). */
 int64_t gridspt_bispectrum_workspace_bytes(const gridspt_grid* g, int32_t ntri, const int32_t* tri_bins,
                                            int32_t nterms, const int32_t* terms);
 
@@ -265,8 +292,16 @@ int64_t gridspt_bispectrum_workspace_bytes(const gridspt_grid* g, int32_t ntri, 
  * the indicator of shell b; for term (fa, fb, fc, tri) with shells (b1, b2, b3)
  *   T = N^-3 sum_x I_fa^b1 I_fb^b2 I_fc^b3,  ntriangles = N^-3 sum_x J^b1 J^b2 J^b3,
  *   bk = L^6 T / ntriangles.
- * T counts triangles that close modulo N, which equals exact closure
- * (k1 + k2 + k3 = 0) when every shell lies below N/3.
+ * The sum over x counts the triangles that close modulo N; Eq. 22-23 ask for
+ * exact closure, k1 + k2 + k3 = 0.  The two agree when every component of
+ * the sum lies in (-N, N), which holds when the outer radii of the three
+ * shells (r_b = floor(sqrt(edge_n2[b + 1] - 1)), the largest |n| of shell b)
+ * add up to less than N.  A triangle whose radii reach N or more is rejected
+ * with GRIDSPT_EINVAL (under the strict 2/3 cut every shell has r_b < N/3 and
+ * never is).
+ * ntriangles is an exact integer count of ordered closed triangles: the
+ * indicator transforms and their triple sums run in FP64 whatever the grid's
+ * precision, and the count is rounded to the nearest integer.
  * tri_bins: host 3 * ntri bin indices (ntri <= 4096); terms: host 4 * nterms
  * (fa, fb, fc, tri), nterms <= 16384;
  * edge_n2 as for gridspt_power.  bk: device [nterms]; ntriangles: device
@@ -315,7 +350,7 @@ int gridspt_adjoint(gridspt_ctx* ctx, const gridspt_grid* g, const gridspt_linpk
  * standard deviation of every spectrum bin and bispectrum term (the
  * realisation averages of Sec. IV). */
 typedef struct {
-    gridspt_grid grid;       /* size class; grid.kc must hold both masks */
+    gridspt_grid grid;       /* size class; grid.kc must hold both masks; grid.flags is ignored */
     int32_t nreal;           /* realisations >= 1 */
     int32_t nmax;            /* orders 1..nmax, nmax in [1, 5] */
     int64_t n2max2;          /* W2 of orders n >= 2 (W1 is lin.n2max) */
@@ -325,7 +360,7 @@ typedef struct {
     int32_t nbins;           /* spectrum bins, 1..256 */
     const int64_t* edge_n2;  /* host, nbins + 1, as for gridspt_power */
     int32_t ntri;            /* bispectrum triangles, 0 for none */
-    const int32_t* tri_bins; /* host, 3 * ntri bins of edge_n2 */
+    const int32_t* tri_bins; /* host, 3 * ntri bins of edge_n2 (closure rule of gridspt_bispectrum) */
     int32_t nterms;          /* bispectrum terms */
     const int32_t* terms;    /* host, 4 * nterms (fa, fb, fc, tri), fields in [0, nmax) */
 } gridspt_batch_group;
@@ -386,6 +421,13 @@ int gridspt_batch_tuning(const gridspt_batch* b, int32_t group, int32_t max, cha
  * above).  Returns the number of kinds reported; reading resets the record. */
 int gridspt_set_profiling(gridspt_ctx* ctx, int32_t enable);
 int gridspt_profile_read(gridspt_ctx* ctx, int32_t max, char* names, int64_t* launches, double* ms, double* bytes);
+/* The same launches grouped by the order of the recursion they belong to, as
+ * of the last gridspt_profile_read: ms[i] and bytes[i] (host, max entries) for
+ * order i, where order 1 includes the linear field of gridspt_orders_linear,
+ * the product pass of order n >= 2 (which also finishes the z inverse of
+ * order n - 1) counts for order n, and index 0 collects launches of no order
+ * (estimators, sums).  Returns the highest order with launches. */
+int gridspt_profile_orders(const gridspt_ctx* ctx, int32_t max, double* ms, double* bytes);
 
 #ifdef __cplusplus
 }

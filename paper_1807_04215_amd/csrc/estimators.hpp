@@ -370,8 +370,10 @@ static __global__ __launch_bounds__(kReduceThreads) void k_triple_final(const do
     }
 }
 
-// bk = L^6 T / J for terms u0 .. u0+nu-1 (both sums over x of the same grid, so
-// the N^-3 cancels); ntriangles = N^-3 J for triangles u0 .. u0+nt-1.
+// ntriangles = N^-3 J rounded to the nearest integer (J comes from FP64
+// indicator transforms, so N^-3 J lies within far less than 1/2 of the count
+// of closed triangles) for triangles u0 .. u0+nt-1, and bk = L^6 N^-3 T /
+// ntriangles for terms u0 .. u0+nu-1.
 struct TriMap {
     int tri[64];  // triangle of term u0 + i
     int rep[64];  // the term whose sum term u0 + i takes
@@ -386,10 +388,10 @@ static __global__ void k_bisp_final(const double* tsum, const double* jsum, TriM
     bk = zptr(bk, zs);
     ntriangles = zptr(ntriangles, zs);
     if (i < nu) {
-        const double j = jsum[m.tri[i]];
-        bk[u0 + i] = j != 0.0 ? vol2 * tsum[m.rep[i]] / j : 0.0;
+        const double cnt = rint(jsum[m.tri[i]] * invN3);
+        bk[u0 + i] = cnt != 0.0 ? vol2 * (tsum[m.rep[i]] * invN3) / cnt : 0.0;
     }
-    if (i < nt) ntriangles[u0 + i] = jsum[u0 + i] * invN3;
+    if (i < nt) ntriangles[u0 + i] = rint(jsum[u0 + i] * invN3);
 }
 
 // out(x) = sum_n coef_n delta_n(x) in FP64
@@ -420,6 +422,54 @@ __global__ void k_sum_orders(SumArgs<T> s) {
         double2* o = reinterpret_cast<double2*>(s.out + 4 * i);
         o[0] = make_double2(acc[0], acc[1]);
         o[1] = make_double2(acc[2], acc[3]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Input check (GRIDSPT_CHECK_FINITE): *flag = 1 if any of the n values of f is
+// a NaN or an infinity.  Every writer stores the same value, so the unordered
+// stores need no atomic.  n is a multiple of 4 and f 16-byte aligned.
+// ---------------------------------------------------------------------------
+static __global__ void k_clear_word(uint32_t* w) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *w = 0u;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_nonfinite(const T* __restrict__ f, size_t n, uint32_t* flag) {
+    using Vec = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    constexpr int VW = 16 / (int)sizeof(T);
+    const Vec* fv = reinterpret_cast<const Vec*>(f);
+    const size_t nv = n / VW, stride = (size_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
+        const Vec v = fv[i];
+        const T* x = reinterpret_cast<const T*>(&v);
+#pragma unroll
+        for (int k = 0; k < VW; ++k) bad = bad || !isfinite(x[k]);
+    }
+    if (__any(bad) && (threadIdx.x % 64) == 0) *flag = 1u;
+}
+
+// ---------------------------------------------------------------------------
+// A cube-layout spectrum in the half layout [ix][iy][iz] (N x N x (N/2 + 1)
+// complex, zero outside the cube): one output element per thread and step,
+// consecutive threads on consecutive outputs.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_spectrum_half(const cpx<T>* __restrict__ cube, cpx<T>* __restrict__ half,
+                                                       int n, CubeDims cd) {
+    const int h = n / 2 + 1;
+    const size_t total = (size_t)n * n * h, stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const int iz = (int)(i % h);
+        const size_t r = i / h;
+        const int iy = (int)(r % n), ix = (int)(r / n);
+        const int ky = iy < n / 2 ? iy : iy - n, kx = ix < n / 2 ? ix : ix - n;
+        const bool in = iz <= cd.Kc && abs(ky) <= cd.Kc && abs(kx) <= cd.Kc;
+        const int cy = ky >= 0 ? ky : ky + cd.Ky, cx = kx >= 0 ? kx : kx + cd.Ky;
+        const size_t at = in ? ((size_t)iz * cd.Ky + cy) * cd.Ky + cx : 0;
+        const cpx<T> v = cube[at];  // unconditional: no branch around the load
+        half[i] = in ? v : cpx<T>{(T)0, (T)0};
     }
 }
 

@@ -237,31 +237,55 @@ BispPlan bisp_make_plan(int ntri, const int32_t* tri_bins, int nterms, const int
     return bp;
 }
 
-// scratch of the estimator: slots | triple partials | sums (nterms + ntri),
-// after a pipeline workspace (layout_of(d, 1)) in the single-call API
+// scratch of the estimator: sums (nterms term sums, then ntri triangle sums) |
+// triple partials | slots.  The first two do not depend on the precision of
+// the slots, so the triangle counts (made in FP64) and the term sums (in the
+// grid's precision) share them.
 struct BispLayout {
-    int64_t slots, partial, sums, end;
+    int64_t sums, partial, slots, end;
 };
-BispLayout bisp_layout(const Dims& d, const BispPlan& bp, int nterms, int ntri, int64_t start) {
+BispLayout bisp_layout(const Dims& d, int max_slots, int nterms, int ntri) {
     BispLayout b;
-    b.slots = start;
-    b.partial = align_up(b.slots + (int64_t)bp.max_slots * d.ncell() * d.real_bytes);
-    b.sums = align_up(b.partial + (int64_t)kTripleBlocks * 8 * 8);
-    b.end = align_up(b.sums + (int64_t)(nterms + ntri) * 8);
+    b.sums = 0;
+    b.partial = align_up(b.sums + (int64_t)(nterms + ntri) * 8);
+    b.slots = align_up(b.partial + (int64_t)kTripleBlocks * 8 * 8);
+    b.end = align_up(b.slots + (int64_t)max_slots * d.ncell() * d.real_bytes);
     return b;
 }
 
-// pipe: a pipeline workspace (layout_of(d, 1) or larger); scratch: the
-// estimator's own region (bisp_layout from 0)
+// The grid on which the triangle counts are made: the same grid in FP64, so
+// that N_123 comes out as an exact integer whatever the fields' precision.
+gridspt_grid count_grid(const gridspt_grid* g) {
+    gridspt_grid c = *g;
+    c.dtype = GRIDSPT_F64;
+    c.flags = 0;
+    return c;
+}
+
+// Exact closure (Eq. 22-23 ask for k1 + k2 + k3 = 0; the estimator's sum over
+// cells closes modulo N): every component of k1 + k2 + k3 lies within the sum
+// of the shells' outer radii, so the two agree when that sum is below N.
+int check_closure(const gridspt_grid* g, int ntri, const int32_t* tri_bins, const int64_t* edge_n2) {
+    auto radius = [&](int b) { return edge_n2[b + 1] > edge_n2[b] ? isqrt64(edge_n2[b + 1] - 1) : 0; };
+    for (int t = 0; t < ntri; ++t) {
+        const int32_t* b = tri_bins + 3 * t;
+        if (radius(b[0]) + radius(b[1]) + radius(b[2]) >= g->n) return GRIDSPT_EINVAL;
+    }
+    return GRIDSPT_OK;
+}
+
+// pipe: a pipeline workspace (layout_of(d, 1) or larger); est: the
+// estimator's own region (bisp_layout).  The plan's slots are made on grid g
+// (count_grid(g) for the triangle counts).
 // final: also form bk and ntriangles from the sums; jzs: byte stride of the
 // triangle counts between realisations (0: realisation 0's, made once)
 int bisp_enqueue(gridspt_ctx* c, const gridspt_grid* g, const void* const* fields_k, const BispPlan& bp, int ntri,
                  int nterms, const int32_t* terms, const int64_t* edge_n2, double* bk, double* ntriangles, void* pipe,
-                 void* scratch, const Tuning& tu, Batch bt, bool final = true, size_t jzs = SIZE_MAX) {
+                 void* est, const Tuning& tu, Batch bt, bool final = true, size_t jzs = SIZE_MAX) {
     if (jzs == SIZE_MAX) jzs = bt.zs;
     const Dims d = dims_of(g);
-    const BispLayout bl = bisp_layout(d, bp, nterms, ntri, 0);
-    char* base = static_cast<char*>(scratch);
+    const BispLayout bl = bisp_layout(d, bp.max_slots, nterms, ntri);
+    char* base = static_cast<char*>(est);
     double* partial = reinterpret_cast<double*>(base + bl.partial);
     double* sums = reinterpret_cast<double*>(base + bl.sums);
     const unsigned nz = (unsigned)bt.nreal;
@@ -360,6 +384,7 @@ const char* gridspt_status_string(int s) {
         case GRIDSPT_EWORKSPACE: return "workspace missing or too small";
         case GRIDSPT_EALIGN: return "device pointer null or not 256-byte aligned";
         case GRIDSPT_EHIP: return "HIP runtime error";
+        case GRIDSPT_ENONFINITE: return "an input field holds a NaN or an infinity";
         default: return "unknown status";
     }
 }
@@ -401,12 +426,16 @@ int gridspt_profile_read(gridspt_ctx* c, int32_t max, char* names, int64_t* laun
     if (hipStreamSynchronize(c->stream) != hipSuccess) return GRIDSPT_EHIP;
     double tot_ms[KD_COUNT] = {0}, tot_b[KD_COUNT] = {0};
     int64_t cnt[KD_COUNT] = {0};
+    for (int i = 0; i <= gridspt_ctx::kMaxOrderTag; ++i) c->order_ms[i] = c->order_bytes[i] = 0.0;
     for (auto& r : c->recs) {
         float t = 0.f;
         if (hipEventElapsedTime(&t, r.start, r.stop) != hipSuccess) return GRIDSPT_EHIP;
         tot_ms[r.kind] += t;
         tot_b[r.kind] += r.bytes;
         cnt[r.kind] += 1;
+        const int o = std::min(std::max(r.order, 0), gridspt_ctx::kMaxOrderTag);
+        c->order_ms[o] += t;
+        c->order_bytes[o] += r.bytes;
         c->pool.push_back(r.start);
         c->pool.push_back(r.stop);
     }
@@ -424,6 +453,19 @@ int gridspt_profile_read(gridspt_ctx* c, int32_t max, char* names, int64_t* laun
         ++k;
     }
     return k;
+}
+
+int gridspt_profile_orders(const gridspt_ctx* c, int32_t max, double* ms, double* bytes) {
+    if (!c || max < 0) return GRIDSPT_EINVAL;
+    int top = 0;
+    for (int i = 0; i <= gridspt_ctx::kMaxOrderTag; ++i) {
+        if (c->order_ms[i] > 0.0 || c->order_bytes[i] > 0.0) top = i;
+        if (i < max) {
+            if (ms) ms[i] = c->order_ms[i];
+            if (bytes) bytes[i] = c->order_bytes[i];
+        }
+    }
+    return top;
 }
 
 int64_t gridspt_cut_n2max(int32_t n, double box, double kcut) {
@@ -523,11 +565,38 @@ int gridspt_growth(double om, double ol, double z, double* dz) {
     return GRIDSPT_OK;
 }
 
-int64_t gridspt_workspace_bytes(const gridspt_grid* g, int32_t nmax) {
+int64_t gridspt_workspace_bytes(const gridspt_grid* g, int32_t nmax, uint32_t flags) {
     const int rc = check_grid(g);
     if (rc != GRIDSPT_OK) return rc;
     if (nmax < 1 || nmax > 5) return GRIDSPT_EINVAL;
-    return layout_of(dims_of(g), nmax).end;
+    if (flags & ~(uint32_t)GRIDSPT_CHECK_FINITE) return GRIDSPT_EINVAL;
+    return layout_of(dims_of(g), nmax).end;  // the check's flag word is part of every layout
+}
+
+// The pipeline workspace of the entry points below (their grid flags are checked by check_grid)
+static int64_t pipe_bytes(const gridspt_grid* g, int nmax) { return layout_of(dims_of(g), nmax).end; }
+
+// GRIDSPT_CHECK_FINITE: every real input field is scanned on the device, the
+// flag word at the head of `work` comes back to the host, and a non-finite
+// value ends the call with GRIDSPT_ENONFINITE before anything else is enqueued.
+static int check_finite(gridspt_ctx* c, const gridspt_grid* g, const void* const* fields, int nf, void* work) {
+    if (!(g->flags & GRIDSPT_CHECK_FINITE)) return GRIDSPT_OK;
+    const Dims d = dims_of(g);
+    uint32_t* flag = reinterpret_cast<uint32_t*>(static_cast<char*>(work) + layout_of(d, 1).chk);
+    CHECK(launch(c, KD_COPY, 4.0, dim3(1), dim3(64), 0, k_clear_word, flag));
+    for (int i = 0; i < nf; ++i) {
+        const double bytes = (double)d.ncell() * d.real_bytes;
+        if (g->dtype == GRIDSPT_F64)
+            CHECK(launch(c, KD_COPY, bytes, dim3(2048), dim3(256), 0, k_nonfinite<double>,
+                         static_cast<const double*>(fields[i]), (size_t)d.ncell(), flag));
+        else
+            CHECK(launch(c, KD_COPY, bytes, dim3(2048), dim3(256), 0, k_nonfinite<float>,
+                         static_cast<const float*>(fields[i]), (size_t)d.ncell(), flag));
+    }
+    uint32_t h = 0;
+    if (hipMemcpyAsync(&h, flag, sizeof h, hipMemcpyDeviceToHost, c->stream) != hipSuccess) return GRIDSPT_EHIP;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return GRIDSPT_EHIP;
+    return h ? GRIDSPT_ENONFINITE : GRIDSPT_OK;
 }
 
 static int check_linpk(const gridspt_grid* g, const gridspt_linpk* lp) {
@@ -547,7 +616,7 @@ int gridspt_linear_field(gridspt_ctx* c, const gridspt_grid* g, const gridspt_li
     if (delta1_k) CHECK(check_ptr(delta1_k));
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
-    if (work_bytes < gridspt_workspace_bytes(g, 1)) return GRIDSPT_EWORKSPACE;
+    if (work_bytes < pipe_bytes(g, 1)) return GRIDSPT_EWORKSPACE;
     const Tuning& tu = c->tuning(g);
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
@@ -566,7 +635,8 @@ int gridspt_noise_field(gridspt_ctx* c, const gridspt_grid* g, const gridspt_lin
     if (delta1_k) CHECK(check_ptr(delta1_k));
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
-    if (work_bytes < gridspt_workspace_bytes(g, 1)) return GRIDSPT_EWORKSPACE;
+    if (work_bytes < pipe_bytes(g, 1)) return GRIDSPT_EWORKSPACE;
+    CHECK(check_finite(c, g, &noise, 1, work));
     const Tuning& tu = c->tuning(g);
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
@@ -605,6 +675,7 @@ int gridspt_adjoint(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* 
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
     if (work_bytes < gridspt_adjoint_workspace_bytes(g, nmax)) return GRIDSPT_EWORKSPACE;
+    CHECK(check_finite(c, g, gdelta, nmax, work));
     const Tuning& tu = c->tuning(g);
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
@@ -622,13 +693,30 @@ int gridspt_forward(gridspt_ctx* c, const gridspt_grid* g, int64_t n2max, const 
     CHECK(check_ptr(field_k));
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
-    if (work_bytes < gridspt_workspace_bytes(g, 1)) return GRIDSPT_EWORKSPACE;
+    if (work_bytes < pipe_bytes(g, 1)) return GRIDSPT_EWORKSPACE;
+    CHECK(check_finite(c, g, &field, 1, work));
     const Tuning& tu = c->tuning(g);
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
         constexpr int N = decltype(nc)::value;
         return run_forward<T, N>(c, g, n2max, field, field_k, work, tu, Batch{});
     });
+}
+
+int gridspt_spectrum_half(gridspt_ctx* c, const gridspt_grid* g, const void* cube, void* half) {
+    if (!c) return GRIDSPT_EINVAL;
+    CHECK(check_grid(g));
+    CHECK(check_ptr(cube));
+    CHECK(check_ptr(half));
+    const Dims d = dims_of(g);
+    const CubeDims cd{(int)d.Kc, (int)d.Kz, (int)d.Ky};
+    const double bytes = ((double)d.N * d.N * (d.N / 2 + 1) + (double)d.cube()) * d.cpx_bytes;
+    const unsigned blocks = (unsigned)std::min<int64_t>(8192, (d.N * d.N * (d.N / 2 + 1) + 255) / 256);
+    if (g->dtype == GRIDSPT_F64)
+        return launch(c, KD_COPY, bytes, dim3(blocks), dim3(256), 0, k_spectrum_half<double>,
+                      static_cast<const cpx<double>*>(cube), static_cast<cpx<double>*>(half), g->n, cd);
+    return launch(c, KD_COPY, bytes, dim3(blocks), dim3(256), 0, k_spectrum_half<float>,
+                  static_cast<const cpx<float>*>(cube), static_cast<cpx<float>*>(half), g->n, cd);
 }
 
 int gridspt_orders(gridspt_ctx* c, const gridspt_grid* g, int32_t nmax, int64_t n2max1, int64_t n2max2,
@@ -650,7 +738,8 @@ int gridspt_orders(gridspt_ctx* c, const gridspt_grid* g, int32_t nmax, int64_t 
     }
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
-    if (work_bytes < gridspt_workspace_bytes(g, nmax)) return GRIDSPT_EWORKSPACE;
+    if (work_bytes < pipe_bytes(g, nmax)) return GRIDSPT_EWORKSPACE;
+    CHECK(check_finite(c, g, &delta1, 1, work));
     const Tuning& tu = c->tuning(g);
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
@@ -678,7 +767,7 @@ int gridspt_orders_linear(gridspt_ctx* c, const gridspt_grid* g, const gridspt_l
     }
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
-    if (work_bytes < gridspt_workspace_bytes(g, nmax)) return GRIDSPT_EWORKSPACE;
+    if (work_bytes < pipe_bytes(g, nmax)) return GRIDSPT_EWORKSPACE;
     const Tuning& tu = c->tuning(g);
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
@@ -711,7 +800,7 @@ int gridspt_tune_orders(gridspt_ctx* c, const gridspt_grid* g, const gridspt_lin
     }
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
-    if (work_bytes < gridspt_workspace_bytes(g, nmax)) return GRIDSPT_EWORKSPACE;
+    if (work_bytes < pipe_bytes(g, nmax)) return GRIDSPT_EWORKSPACE;
     int vl[8];
     const int nv = variant_list(g->dtype, g->n, vl);
     gridspt_ctx::Tuned best{g->n, g->dtype, Tuning{}, {}};
@@ -833,6 +922,7 @@ int gridspt_orders_pform(gridspt_ctx* c, const gridspt_grid* g, int32_t nmax, in
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
     if (work_bytes < gridspt_pform_workspace_bytes(g, nmax)) return GRIDSPT_EWORKSPACE;
+    CHECK(check_finite(c, g, &delta1, 1, work));
     const Tuning& tu = c->tuning(g);
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
@@ -855,7 +945,7 @@ int gridspt_smooth(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, const
     }
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
-    if (work_bytes < gridspt_workspace_bytes(g, 1)) return GRIDSPT_EWORKSPACE;
+    if (work_bytes < pipe_bytes(g, 1)) return GRIDSPT_EWORKSPACE;
     const Tuning& tu = c->tuning(g);
     return dispatch(g, [&](auto tag, auto nc) -> int {
         using T = typename decltype(tag)::type;
@@ -1014,6 +1104,22 @@ int gridspt_field_stats(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, 
     return go(tag_t<float>{});
 }
 
+// Single-call bispectrum workspace: a pipeline workspace for the slot
+// transforms of either precision, then the estimator's region, sized for the
+// term slots (grid precision) and the triangle-count slots (FP64).
+struct BispSizes {
+    int64_t pipe, end;
+};
+BispSizes bisp_sizes(const gridspt_grid* g, const BispPlan& bt, const BispPlan& bj, int nterms, int ntri) {
+    const gridspt_grid g64 = count_grid(g);
+    const Dims d = dims_of(g), d64 = dims_of(&g64);
+    BispSizes z;
+    z.pipe = std::max(layout_of(d, 1).end, layout_of(d64, 1).end);
+    z.end = z.pipe + std::max(bisp_layout(d, bt.max_slots, nterms, ntri).end,
+                              bisp_layout(d64, bj.max_slots, nterms, ntri).end);
+    return z;
+}
+
 int64_t gridspt_bispectrum_workspace_bytes(const gridspt_grid* g, int32_t ntri, const int32_t* tri_bins,
                                            int32_t nterms, const int32_t* terms) {
     const int rc = check_grid(g);
@@ -1023,9 +1129,9 @@ int64_t gridspt_bispectrum_workspace_bytes(const gridspt_grid* g, int32_t ntri, 
         if (tri_bins[t] < 0) return GRIDSPT_EINVAL;
     for (int u = 0; u < nterms; ++u)
         if (terms[4 * u + 3] < 0 || terms[4 * u + 3] >= ntri) return GRIDSPT_EINVAL;
-    const BispPlan bp = bisp_make_plan(ntri, tri_bins, nterms, terms, INT_MAX);
-    const Dims d = dims_of(g);
-    return bisp_layout(d, bp, nterms, ntri, layout_of(d, 1).end).end;
+    const BispPlan bt = bisp_make_plan(ntri, tri_bins, nterms, terms, INT_MAX, true, false);
+    const BispPlan bj = bisp_make_plan(ntri, tri_bins, nterms, terms, INT_MAX, false, true);
+    return bisp_sizes(g, bt, bj, nterms, ntri).end;
 }
 
 int gridspt_bispectrum(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, const void* const* fields_k,
@@ -1035,17 +1141,24 @@ int gridspt_bispectrum(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, c
     CHECK(check_grid(g));
     CHECK(check_bisp_args(nfields, ntri, tri_bins, nterms, terms, nbins, edge_n2));
     if (isqrt64(edge_n2[nbins] - 1) > g->kc) return GRIDSPT_EINVAL;  // shells must lie inside the cube
+    CHECK(check_closure(g, ntri, tri_bins, edge_n2));
     for (int i = 0; i < nfields; ++i) CHECK(check_ptr(fields_k[i]));
     CHECK(check_ptr(bk));
     CHECK(check_ptr(ntriangles));
     if (!work) return GRIDSPT_EWORKSPACE;
     CHECK(check_ptr(work));
-    const BispPlan bp = bisp_make_plan(ntri, tri_bins, nterms, terms, INT_MAX);
-    const Dims d = dims_of(g);
-    const int64_t pipe = layout_of(d, 1).end;
-    if (work_bytes < bisp_layout(d, bp, nterms, ntri, pipe).end) return GRIDSPT_EWORKSPACE;
-    return bisp_enqueue(c, g, fields_k, bp, ntri, nterms, terms, edge_n2, bk, ntriangles, work,
-                        static_cast<char*>(work) + pipe, c->tuning(g), Batch{});
+    const BispPlan bt = bisp_make_plan(ntri, tri_bins, nterms, terms, INT_MAX, true, false);
+    const BispPlan bj = bisp_make_plan(ntri, tri_bins, nterms, terms, INT_MAX, false, true);
+    const BispSizes z = bisp_sizes(g, bt, bj, nterms, ntri);
+    if (work_bytes < z.end) return GRIDSPT_EWORKSPACE;
+    char* est = static_cast<char*>(work) + z.pipe;
+    // the triangle counts in FP64 (indicator slots read no spectrum), then the terms
+    const gridspt_grid g64 = count_grid(g);
+    const void* none[1] = {nullptr};
+    CHECK(bisp_enqueue(c, &g64, none, bj, ntri, nterms, terms, edge_n2, nullptr, nullptr, work, est, c->tuning(&g64),
+                       Batch{}, false));
+    return bisp_enqueue(c, g, fields_k, bt, ntri, nterms, terms, edge_n2, bk, ntriangles, work, est, c->tuning(g),
+                        Batch{});
 }
 
 }  // extern "C"
@@ -1083,7 +1196,11 @@ int64_t plan_group(GroupPlan& p) {
         return at;
     };
     const int nmax = p.g.nmax;
-    p.o_pipe = take(layout_of(d, nmax).end);
+    // the triangle counts (FP64, once, in realisation 0's arena) reuse the
+    // pipeline workspace and the estimator region
+    const gridspt_grid g64 = count_grid(&p.g.grid);
+    const Dims d64 = dims_of(&g64);
+    p.o_pipe = take(std::max(layout_of(d, nmax).end, p.g.ntri > 0 ? layout_of(d64, 1).end : 0));
     p.o_delta = take((int64_t)nmax * d.ncell() * d.real_bytes);
     p.o_theta = take((int64_t)std::max(nmax - 1, 0) * d.ncell() * d.real_bytes);
     p.o_cube = take((int64_t)nmax * d.cube() * d.cpx_bytes);
@@ -1093,7 +1210,8 @@ int64_t plan_group(GroupPlan& p) {
     p.o_nmodes = take((int64_t)p.g.nbins * 8);
     if (p.g.ntri > 0) {
         // the bispectrum's transforms reuse the pipeline workspace (the orders are done)
-        p.o_bws = take(bisp_layout(d, p.bp, p.g.nterms, p.g.ntri, 0).end);
+        p.o_bws = take(std::max(bisp_layout(d, p.bp.max_slots, p.g.nterms, p.g.ntri).end,
+                                bisp_layout(d64, p.bpj.max_slots, p.g.nterms, p.g.ntri).end));
         p.o_bk = take((int64_t)p.g.nterms * 8);
         p.o_ntri = take((int64_t)p.g.ntri * 8);
     } else {
@@ -1113,6 +1231,7 @@ int check_group(const gridspt_batch_group& g) {
     if (g.ntri > 0) {
         CHECK(check_bisp_args(g.nmax, g.ntri, g.tri_bins, g.nterms, g.terms, g.nbins, g.edge_n2));
         if (isqrt64(g.edge_n2[g.nbins] - 1) > g.grid.kc) return GRIDSPT_EINVAL;
+        CHECK(check_closure(&g.grid, g.ntri, g.tri_bins, g.edge_n2));
     }
     return GRIDSPT_OK;
 }
@@ -1132,11 +1251,11 @@ int make_group(const gridspt_batch_group& src, GroupPlan& p) {
     p.g.terms = p.terms.empty() ? nullptr : p.terms.data();
     p.d = dims_of(&p.g.grid);
     if (src.ntri > 0) {
-        // term sums in every launch of the batch; triangle counts once, at plan creation
+        // term sums in every launch of the batch; triangle counts once, at plan
+        // creation, in FP64 (half as many slots of twice the size for FP32 grids)
+        const int jcap = src.grid.dtype == GRIDSPT_F64 ? kBatchSlotCap : kBatchSlotCap / 2;
         p.bp = bisp_make_plan(src.ntri, p.g.tri_bins, src.nterms, p.g.terms, kBatchSlotCap, true, false);
-        p.bpj = bisp_make_plan(src.ntri, p.g.tri_bins, src.nterms, p.g.terms, kBatchSlotCap, false, true);
-        // one scratch layout for both plans: the counts must stay where the term pass reads them
-        p.bp.max_slots = p.bpj.max_slots = std::max(p.bp.max_slots, p.bpj.max_slots);
+        p.bpj = bisp_make_plan(src.ntri, p.g.tri_bins, src.nterms, p.g.terms, jcap, false, true);
     }
     return GRIDSPT_OK;
 }
@@ -1209,7 +1328,7 @@ int enqueue_group(gridspt_ctx* c, gridspt_batch* b, GroupPlan& p, const Tuning& 
             // the tuner times the shell transforms of the first chunk
             const BispChunk& ch = p.bp.chunks.front();
             const int ns = (int)ch.slots.size();
-            const BispLayout bl = bisp_layout(d, p.bp, g.nterms, g.ntri, 0);
+            const BispLayout bl = bisp_layout(d, p.bp.max_slots, g.nterms, g.ntri);
             std::vector<const void*> cubes(ns);
             std::vector<int64_t> lo(ns), hi(ns);
             std::vector<void*> outs(ns);
@@ -1273,12 +1392,14 @@ int tune_group(gridspt_batch* b, GroupPlan& p) {
 }
 
 // The triangle counts N_123 of a group's bispectrum depend only on the grid
-// and the bins: made once, in realisation 0's sums, before any launch of the batch.
+// and the bins: made once, in FP64, in realisation 0's sums, before any launch
+// of the batch (FP64 compiles only the default launch variant).
 int setup_triangles(gridspt_batch* b, GroupPlan& p) {
     if (p.g.ntri == 0) return GRIDSPT_OK;
     const void* none[1] = {nullptr};  // indicator slots read no spectrum
-    return bisp_enqueue(b->ctx, &p.g.grid, none, p.bpj, p.g.ntri, p.g.nterms, p.g.terms, p.g.edge_n2, nullptr,
-                        nullptr, arena(b, p, p.o_pipe), arena(b, p, p.o_bws), p.tu, Batch{1, 0}, false, 0);
+    const gridspt_grid g64 = count_grid(&p.g.grid);
+    return bisp_enqueue(b->ctx, &g64, none, p.bpj, p.g.ntri, p.g.nterms, p.g.terms, p.g.edge_n2, nullptr, nullptr,
+                        arena(b, p, p.o_pipe), arena(b, p, p.o_bws), Tuning{}, Batch{1, 0}, false, 0);
 }
 
 void release(gridspt_batch* b) {

@@ -383,6 +383,7 @@ int run_orders(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, i
     Pipe<T, N> p(c, g, work, nmax, tu, b);
     auto dk = [&](int i) { return delta_k ? (cpx<T>*)delta_k[i] : nullptr; };
     auto tk = [&](int i) { return theta_k ? (cpx<T>*)theta_k[i] : nullptr; };
+    OrderTag tag(c, 1);  // launches of order 1 (with the linear field), then of each order n
     GRIDSPT_CHECK(p.twiddles());
 
     // order 1: delta_1 = theta_1 = W1 delta1_in (or the linear field of lp);
@@ -415,6 +416,7 @@ int run_orders(gridspt_ctx* c, const gridspt_grid* g, const gridspt_linpk* lp, i
     // product pass (k_zchain); u_m is stored only while a later product pass
     // reads it from HBM (m < nmax - 1).
     for (int n = 2; n <= nmax; ++n) {
+        tag.set(n);
         if (n - 1 < nmax - 1)
             for (int j = 0; j < 3; ++j) chain.out[1 + j] = p.U(n - 1, j);
         ProductInputs<T> pin{};
@@ -527,6 +529,7 @@ int run_orders_pform(gridspt_ctx* c, const gridspt_grid* g, int nmax, int64_t n2
         return own ? (cpx<T>*)theta_k[i] : wcube_t;
     };
     const double kF = 2.0 * M_PI / g->box;
+    OrderTag tag(c, 1);  // per-order timing: order 1, then each order n with its derived fields
     GRIDSPT_CHECK(p.twiddles());
     // the derived fields of order m from its spectra
     auto make_derived = [&](int m, const cpx<T>* cd_, const cpx<T>* ct_) -> int {
@@ -557,6 +560,7 @@ int run_orders_pform(gridspt_ctx* c, const gridspt_grid* g, int nmax, int64_t n2
         if (nmax > 1) GRIDSPT_CHECK(make_derived(1, c1, c1));
     }
     for (int n = 2; n <= nmax; ++n) {
+        tag.set(n);
         PFormProducts<T> pp{};
         for (int m = 1; m < n; ++m) {
             pp.f[m - 1][0] = static_cast<const T*>(delta[m - 1]);

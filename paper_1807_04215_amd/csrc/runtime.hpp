@@ -96,6 +96,7 @@ inline int variant_list(int dtype, int n, int* out) {
 struct gridspt_ctx {
     struct Record {
         int kind;
+        int order;  // order of the recursion the launch belongs to, 0 for none
         hipEvent_t start, stop;
         double bytes;
     };
@@ -106,7 +107,11 @@ struct gridspt_ctx {
     };
     hipStream_t stream = nullptr;
     bool profile = false;
+    int order_tag = 0;  // stamped on every record (set by the orders' pass sequences)
     std::vector<Record> recs;
+    // per order 0..kMaxOrderTag, from the last gridspt_profile_read
+    static constexpr int kMaxOrderTag = 8;
+    double order_ms[kMaxOrderTag + 1] = {}, order_bytes[kMaxOrderTag + 1] = {};
     std::vector<hipEvent_t> pool;
     std::vector<Tuned> tuned;  // autotuner choices per grid (size, precision)
     const gridspt::Tuning& tuning(const gridspt_grid* g) const {
@@ -135,7 +140,7 @@ inline hipEvent_t take_event(gridspt_ctx* c) {
 template <typename Kern, typename... Args>
 int launch(gridspt_ctx* c, int kind, double bytes, dim3 grid, dim3 block, size_t shmem, Kern kern, Args... args) {
     if (grid.x == 0 || grid.y == 0 || grid.z == 0) return GRIDSPT_OK;
-    gridspt_ctx::Record r{kind, nullptr, nullptr, bytes};
+    gridspt_ctx::Record r{kind, c->order_tag, nullptr, nullptr, bytes};
     if (c->profile) {
         r.start = take_event(c);
         r.stop = take_event(c);
@@ -150,6 +155,15 @@ int launch(gridspt_ctx* c, int kind, double bytes, dim3 grid, dim3 block, size_t
     }
     return GRIDSPT_OK;
 }
+
+// Stamps the launches enqueued while it lives with order n (per-order timing).
+struct OrderTag {
+    gridspt_ctx* c;
+    int saved;
+    OrderTag(gridspt_ctx* ctx, int n) : c(ctx), saved(ctx->order_tag) { c->order_tag = n; }
+    void set(int n) { c->order_tag = n; }
+    ~OrderTag() { c->order_tag = saved; }
+};
 
 #define GRIDSPT_CHECK(x)                   \
     do {                                   \
@@ -182,6 +196,7 @@ inline int64_t isqrt64(int64_t v) {
 
 inline int check_grid(const gridspt_grid* g) {
     if (!g) return GRIDSPT_EINVAL;
+    if (g->flags & ~(uint32_t)GRIDSPT_CHECK_FINITE) return GRIDSPT_EINVAL;
     if (g->dtype != GRIDSPT_F32 && g->dtype != GRIDSPT_F64) return GRIDSPT_EINVAL;
     if (!(g->box > 0.0) || !std::isfinite(g->box)) return GRIDSPT_EINVAL;
     if (g->n < 2 || (g->n & 1)) return GRIDSPT_EINVAL;
@@ -228,19 +243,21 @@ inline Dims dims_of(const gridspt_grid* g) {
     return d;
 }
 
-// Workspace of the transform pipeline: twiddles | radial amplitude table
-// ((Kc + 1)^2 doubles) | buffer A (S1, S3) | buffer B (S2, S4) | u_m real
-// fields for m <= nmax - 2 (the product pass of order nmax takes u_{nmax-1}
-// from registers).  S1/S3 and S2/S4 are never live at once.
+// Workspace of the transform pipeline: the input check's flag word (256 bytes)
+// | twiddles | radial amplitude table ((Kc + 1)^2 doubles) | buffer A (S1, S3)
+// | buffer B (S2, S4) | u_m real fields for m <= nmax - 2 (the product pass of
+// order nmax takes u_{nmax-1} from registers).  S1/S3 and S2/S4 are never live
+// at once.
 struct Layout {
-    int64_t tw, amp, a, b, u, end;
+    int64_t chk, tw, amp, a, b, u, end;
     int64_t a_field_s1, a_field_s3, b_field_s2, b_field_s4;  // field strides (elements)
 };
 
 inline Layout layout_of(const Dims& d, int nmax) {
     Layout L;
-    L.tw = 0;
-    L.amp = align_up(d.N * d.cpx_bytes);
+    L.chk = 0;
+    L.tw = kAlign;
+    L.amp = align_up(L.tw + d.N * d.cpx_bytes);
     L.a = align_up(L.amp + (d.Kc + 1) * (d.Kc + 1) * 8);
     const int64_t asz = std::max(4 * d.s1(), 5 * d.s3()) * d.cpx_bytes;
     L.b = align_up(L.a + asz);

@@ -33,8 +33,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings_and_version():
     lib = g.lib()
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, -6):
         assert lib.gridspt_status_string(code)
+    assert b"NaN" in lib.gridspt_status_string(-6)
     assert lib.gridspt_version() >= 100
 
 
@@ -117,14 +118,14 @@ def test_validation_before_any_gpu_work():
         assert lib.gridspt_orders(h, ctypes.byref(G), 3, 455, 455, ws, d, d, None, None, ws, 1024) == -3
         assert lib.gridspt_orders(h, ctypes.byref(G), 3, 455, 455, ws, d, d, None, None, None, 1 << 40) == -3
         # grid: odd, non power of two, kc too large, bad dtype, bad box
-        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(n=63)), 3) == -1
-        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(n=144, kc=47)), 3) == -2  # 9 * 16: not built
-        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(n=200, kc=60)), 3) == -2  # factor 5
-        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(n=192, kc=63)), 3) > 0    # 3 * 64: radix-3 plan
-        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(n=48, kc=15)), 3) > 0
-        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(kc=32)), 3) == -1
-        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(dtype=7)), 3) == -1
-        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(box=-1.0)), 3) == -1
+        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(n=63)), 3, 0) == -1
+        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(n=144, kc=47)), 3, 0) == -2  # 9 * 16: not built
+        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(n=200, kc=60)), 3, 0) == -2  # factor 5
+        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(n=192, kc=63)), 3, 0) > 0    # 3 * 64: radix-3 plan
+        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(n=48, kc=15)), 3, 0) > 0
+        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(kc=32)), 3, 0) == -1
+        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(dtype=7)), 3, 0) == -1
+        assert lib.gridspt_workspace_bytes(ctypes.byref(_grid(box=-1.0)), 3, 0) == -1
         # power: bad pair index, decreasing edges, edge[0] = 0
         f = (ctypes.c_void_p * 2)(4096 * 512, 4096 * 768)
         pairs = (ctypes.c_int32 * 2)(0, 2)
@@ -146,6 +147,64 @@ def test_validation_before_any_gpu_work():
         # linear field: non-positive Gamma
         lp = g._LinPk(1.0, 0.96, 0.0, 1.0, 455, 1, 0)
         assert lib.gridspt_linear_field(h, ctypes.byref(G), ctypes.byref(lp), ws, None, ws, 1 << 40) == -1
+        # grid flags: only GRIDSPT_CHECK_FINITE is defined
+        G2 = _grid()
+        G2.flags = 2
+        assert lib.gridspt_orders(h, ctypes.byref(G2), 3, 455, 455, ws, d, d, None, None, ws, 1 << 40) == -1
+        assert lib.gridspt_workspace_bytes(ctypes.byref(G), 3, 2) == -1
+        # half layout: misaligned or missing pointers
+        assert lib.gridspt_spectrum_half(h, ctypes.byref(G), ctypes.c_void_p(4096 * 256 + 8), ws) == -4
+        assert lib.gridspt_spectrum_half(h, ctypes.byref(G), ws, None) == -4
+        assert lib.gridspt_spectrum_half(None, ctypes.byref(G), ws, ws) == -1
+    finally:
+        lib.gridspt_destroy(h)
+
+
+def test_workspace_flags_and_profile_orders():
+    """The finiteness check's flag word is part of every workspace, so the flag
+    does not change the size; a fresh context reports no per-order timing."""
+    lib = g.lib()
+    G = _grid()
+    base = lib.gridspt_workspace_bytes(ctypes.byref(G), 3, 0)
+    assert base > 0
+    assert lib.gridspt_workspace_bytes(ctypes.byref(G), 3, g.CHECK_FINITE) == base
+    G.flags = g.CHECK_FINITE
+    assert lib.gridspt_workspace_bytes(ctypes.byref(G), 3, 0) == base
+    h = ctypes.c_void_p()
+    assert lib.gridspt_create(ctypes.byref(h), None) == 0
+    try:
+        ms = (ctypes.c_double * 9)()
+        assert lib.gridspt_profile_orders(h, 9, ms, None) == 0
+        assert all(v == 0.0 for v in ms)
+        assert lib.gridspt_profile_orders(None, 9, ms, None) == -1
+    finally:
+        lib.gridspt_destroy(h)
+
+
+def test_bispectrum_rejects_triangles_that_close_only_modulo_n():
+    """Eq. 22-23 sum over exactly closed triangles; the FFT estimator closes them
+    modulo N.  A triangle whose three shell radii add up to N or more could
+    close through a wrap, so the call rejects it; below N it proceeds (here
+    to the workspace check, with no device work)."""
+    lib = g.lib()
+    h = ctypes.c_void_p()
+    assert lib.gridspt_create(ctypes.byref(h), None) == 0
+    try:
+        G = _grid(n=64, kc=31)
+        f = (ctypes.c_void_p * 1)(4096 * 512)
+        out = ctypes.c_void_p(4096 * 2048)
+        ws = ctypes.c_void_p(4096 * 256)
+        edges = (ctypes.c_int64 * 3)(1, 400, 962)     # shell radii 19 and 31
+        for tri, want in (((0, 0, 0), -3), ((0, 0, 1), -1), ((1, 1, 1), -1), ((1, 0, 0), -1)):
+            tb = (ctypes.c_int32 * 3)(*tri)
+            tm = (ctypes.c_int32 * 4)(0, 0, 0, 0)
+            rc = lib.gridspt_bispectrum(h, ctypes.byref(G), 1, f, 1, tb, 1, tm, 2, edges, out, out, ws, 1024)
+            assert rc == want, (tri, rc)
+        # the same rule for a batch group (19 + 19 + 31 = 69 >= 64)
+        grp, keep = _bgroup(n=64, kc=31, n2=961, edges=(1, 400, 962), tris=(0, 0, 1), terms=(0, 0, 0, 0))
+        assert lib.gridspt_batch_workspace_bytes(1, ctypes.byref(grp)) == -1
+        grp, keep = _bgroup(n=64, kc=31, n2=961, edges=(1, 400, 962), tris=(0, 0, 0), terms=(0, 0, 0, 0))
+        assert lib.gridspt_batch_workspace_bytes(1, ctypes.byref(grp)) > 0
     finally:
         lib.gridspt_destroy(h)
 
@@ -185,7 +244,7 @@ def test_workspace_sizes_follow_layout():
     a = max(4 * kz * n * n, 5 * kz * n * ky) * 8
     b = max(4 * kz * ky * n, 5 * n * n * kz) * 8
     u = 9 * n ** 3 * 4                # u_1 .. u_3: the order-5 product pass holds u_4 in registers
-    got = g.lib().gridspt_workspace_bytes(ctypes.byref(G), 5)
+    got = g.lib().gridspt_workspace_bytes(ctypes.byref(G), 5, 0)
     amp = (341 + 1) ** 2 * 8          # radial amplitude table
     assert a + b + u + amp <= got <= a + b + u + amp + 5 * 256 + n * 8
     assert g.lib().gridspt_cube_elems(ctypes.byref(G)) == kz * ky * ky
@@ -215,7 +274,7 @@ def test_batch_validation_and_layout():
     assert lib.gridspt_batch_workspace_bytes(1, ctypes.byref(grp2)) == 2 * one
     # the per-realisation arena holds at least the fields, workspace and spectra
     n, nmax = 32, 3
-    assert one // 2 >= g.lib().gridspt_workspace_bytes(ctypes.byref(g._Grid(n, 0, 200.0, 10, 0)), nmax) \
+    assert one // 2 >= g.lib().gridspt_workspace_bytes(ctypes.byref(g._Grid(n, 0, 200.0, 10, 0)), nmax, 0) \
         + (2 * nmax - 1) * n ** 3 * 4
     arr = (g._BatchGroup * 2)(grp, grp2)
     assert lib.gridspt_batch_workspace_bytes(2, arr) == 3 * one
@@ -243,3 +302,36 @@ def test_batch_validation_and_layout():
         assert not b.value
     finally:
         lib.gridspt_destroy(h)
+
+
+class _HostCtx:
+    """Stands in for a Context in host-only checks of the binding's argument tests."""
+    device = None
+
+    def _uses(self, t):
+        raise AssertionError("a rejected tensor reached the stream bookkeeping")
+
+
+def test_binding_rejects_wrong_tensors_before_any_call():
+    """Every tensor address the binding passes on is checked first: a wrong
+    dtype (FP32 into an F64 grid), shape (a smaller out= buffer), layout (a
+    transposed view) or device (a CPU tensor) raises instead of reaching a
+    kernel that would read or write past the allocation."""
+    import torch
+    ctx = _HostCtx()
+    grid = g.Grid(16, 100.0, 5, g.F64)
+    ok = torch.zeros(grid.real_shape, dtype=torch.float64)
+    with pytest.raises(TypeError, match="dtype"):
+        g._real(ctx, grid, ok.float(), "delta1")
+    with pytest.raises(ValueError, match="shape"):
+        g._real(ctx, grid, torch.zeros((16, 16, 8), dtype=torch.float64), "out")
+    with pytest.raises(ValueError, match="shape"):
+        g._cube(ctx, grid, torch.zeros((6, 11, 11), dtype=torch.float64), "out_k")   # no trailing complex axis
+    with pytest.raises(ValueError, match="contiguous"):
+        g._real(ctx, grid, ok.transpose(0, 2), "delta1")
+    with pytest.raises(ValueError, match="GPU"):
+        g._real(ctx, grid, ok, "delta1")
+    with pytest.raises(ValueError, match="missing"):
+        g._real_array(ctx, grid, [None, ok], "delta")
+    with pytest.raises(TypeError):
+        g._real(ctx, grid, ok.numpy(), "delta1")

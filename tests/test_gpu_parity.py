@@ -194,19 +194,30 @@ def test_bispectrum_matches_oracle(ctx, dtype, n, box):
     bk, nt = g.bispectrum(ctx, grid, out.delta_k, tris, terms, edges)
     ctx.sync()
     rbk, rnt = oracle.bispectrum(list(rdk), box, tris, terms, edges)
-    assert np.allclose(nt.cpu().numpy(), rnt, rtol=1e-9 if dtype == g.F64 else 1e-5, atol=1e-6)
-    got = bk.cpu().numpy()
-    scale = np.abs(rbk).max()
-    assert np.all(np.abs(got - rbk) <= (1e-10 if dtype == g.F64 else 1e-4) * scale)
+    # N_123 is a count of closed triangles: exact, in either precision
+    assert np.array_equal(nt.cpu().numpy(), rnt)
+    # each term against the same triangle sum taken with |delta(k)| factors
+    sbk, _ = oracle.bispectrum([np.abs(x) for x in rdk], box, tris, terms, edges)
+    has = rnt[np.asarray(terms)[:, 3]] > 0
+    err = np.abs(bk.cpu().numpy() - rbk)[has] / sbk[has]
+    assert np.all(err <= (1e-12 if dtype == g.F64 else 1e-5)), err.max()
 
 
-def test_sum_orders(ctx):
-    n, box = 32, 200.0
-    grid, out, (rd, _, _, _) = _orders_case(ctx, g.F64, n, box, 4, 8)
-    coef = [0.5, 0.25, 0.125, 0.0625]
+@pytest.mark.parametrize("dtype", [g.F64, g.F32])
+def test_sum_orders(ctx, dtype):
+    """The FP64 sum of orders in both instantiations (FP32 fields are what the
+    benchmark sums): against the oracle's sum of the very fields the kernel was
+    given, and, through the whole path, against the oracle's FP64 fields."""
+    n, box = 64, 500.0
+    grid, out, (rd, _, _, _) = _orders_case(ctx, dtype, n, box, 5, 8)
+    coef = [0.9 ** (i + 1) for i in range(5)]
     s = g.sum_orders(ctx, grid, out.delta, coef)
     ctx.sync()
-    assert rel_l2(s.cpu().numpy(), oracle.sum_orders(rd, coef)) < 1e-12
+    got = s.cpu().numpy()
+    own = oracle.sum_orders(np.stack([d.cpu().numpy().astype(np.float64) for d in out.delta]), coef)
+    assert rel_l2(got, own) < 1e-15
+    assert np.abs(got - own).max() <= 4e-16 * np.abs(own).max() * 5
+    assert rel_l2(got, oracle.sum_orders(rd, coef)) < TOL[dtype]
 
 
 def test_zeldovich_planar_on_gpu(ctx):
