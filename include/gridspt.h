@@ -282,6 +282,19 @@ int gridspt_power(gridspt_ctx* ctx, const gridspt_grid* g, int32_t nfields, cons
                   int32_t npairs, const int32_t* pairs, int32_t nbins, const int64_t* edge_n2, double* pk,
                   double* kmean, double* nmodes, void* work, int64_t work_bytes);
 
+/* gridspt_power for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same arguments and results, without `work`.  Its scratch is a
+ * library-owned array of 24 MiB per GPU (every GPU the library runs on holds
+ * it until the process ends), enough for every valid call (at most about
+ * 17.8 MB is used); a call needing more returns GRIDSPT_EWORKSPACE.  The call
+ * allocates nothing.  All calls on one GPU share that GPU's array: calls that
+ * overlap in time on one GPU (several streams or threads) race and must be
+ * ordered by the caller. */
+int gridspt_power_static(gridspt_ctx* ctx, const gridspt_grid* g, int32_t nfields, const void* const* fields_k,
+                         int32_t npairs, const int32_t* pairs, int32_t nbins, const int64_t* edge_n2, double* pk,
+                         double* kmean, double* nmodes);
+
 /* Device scratch needed by gridspt_bispectrum for these triangles and terms
  * (room for the FP64 indicator transforms included). */
 int64_t gridspt_bispectrum_workspace_bytes(const gridspt_grid* g, int32_t ntri, const int32_t* tri_bins,

@@ -95,6 +95,7 @@ def lib():
             "gridspt_sum_orders": ([vp, gp, i32, vp, vp, vp], ctypes.c_int),
             "gridspt_power_workspace_bytes": ([gp, i32, i32], i64),
             "gridspt_power": ([vp, gp, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp, i64], ctypes.c_int),
+            "gridspt_power_static": ([vp, gp, i32, vp, i32, vp, i32, vp, vp, vp, vp], ctypes.c_int),
             "gridspt_bispectrum_workspace_bytes": ([gp, i32, vp, i32, vp], i64),
             "gridspt_bispectrum": ([vp, gp, i32, vp, i32, vp, i32, vp, i32, vp, vp, vp, vp, i64], ctypes.c_int),
             "gridspt_batch_workspace_bytes": ([i32, ctypes.POINTER(_BatchGroup)], i64),
@@ -645,6 +646,25 @@ def power(ctx: Context, grid: Grid, fields_k: Sequence[torch.Tensor], pairs, edg
     _check(lib().gridspt_power(ctx.handle, ctypes.byref(g), len(fields_k), _cube_array(ctx, grid, fields_k, "fields_k"),
                                npairs, pr.ctypes.data, nb, e.ctypes.data, _f64(ctx, pk, "pk", pk.shape),
                                _f64(ctx, km, "kmean", km.shape), _f64(ctx, nm, "nmodes", nm.shape), ws, nws), "power")
+    return pk, km, nm
+
+
+def power_static(ctx: Context, grid: Grid, fields_k: Sequence[torch.Tensor], pairs, edges, out=None):
+    """power() through gridspt_power_static: no workspace, the library's own
+    scratch array.  out: optional (pk, kmean, nmodes) float64 tensors to fill
+    (so that the call itself allocates nothing)."""
+    import numpy as np
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1))
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64))
+    npairs, nb = pr.size // 2, e.size - 1
+    if out is None:
+        out = (ctx.empty((npairs, nb), torch.float64), ctx.empty(nb, torch.float64), ctx.empty(nb, torch.float64))
+    pk, km, nm = out
+    g = grid.cstruct
+    _check(lib().gridspt_power_static(ctx.handle, ctypes.byref(g), len(fields_k),
+                                      _cube_array(ctx, grid, fields_k, "fields_k"), npairs, pr.ctypes.data, nb,
+                                      e.ctypes.data, _f64(ctx, pk, "pk", (npairs, nb)), _f64(ctx, km, "kmean", (nb,)),
+                                      _f64(ctx, nm, "nmodes", (nb,))), "power_static")
     return pk, km, nm
 
 

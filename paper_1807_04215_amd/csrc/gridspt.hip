@@ -6,6 +6,7 @@
 #include <array>
 #include <climits>
 #include <map>
+#include <mutex>
 #include <new>
 #include <set>
 #include <string>
@@ -130,6 +131,36 @@ int power_enqueue(gridspt_ctx* c, const gridspt_grid* g, const void* const* fiel
     };
     if (g->dtype == GRIDSPT_F64) return go(tag_t<double>{});
     return go(tag_t<float>{});
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of gridspt_power_static, for callers that cannot allocate: one array
+// per GPU, held for the life of the process.  Its largest use: 1024 blocks x
+// 1792 partial sums (nbins (pairs per launch + 2) <= 1792 for every nbins <=
+// 256) of 8 bytes, the reduced sums, and the bin table of the largest cube
+// (3 x 512^2 ints): about 17.8 MB.  In host code `scratch` only names the
+// symbol; the device address comes from hipGetSymbolAddress, once per device.
+// ---------------------------------------------------------------------------
+constexpr int64_t kStaticScratchBytes = 24ll << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch`.
+int static_scratch(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return GRIDSPT_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return GRIDSPT_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GRIDSPT_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GRIDSPT_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1000,6 +1031,23 @@ int gridspt_power(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, const 
     CHECK(check_ptr(work));
     if (work_bytes < gridspt_power_workspace_bytes(g, npairs, nbins)) return GRIDSPT_EWORKSPACE;
     return power_enqueue(c, g, fields_k, npairs, pairs, nbins, edge_n2, pk, kmean, nmodes, work, Batch{});
+}
+
+int gridspt_power_static(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, const void* const* fields_k,
+                         int32_t npairs, const int32_t* pairs, int32_t nbins, const int64_t* edge_n2, double* pk,
+                         double* kmean, double* nmodes) {
+    if (!c || !fields_k) return GRIDSPT_EINVAL;
+    CHECK(check_grid(g));
+    CHECK(check_power_args(nfields, npairs, pairs, nbins, edge_n2));
+    for (int i = 0; i < nfields; ++i) CHECK(check_ptr(fields_k[i]));
+    CHECK(check_ptr(pk));
+    if (kmean) CHECK(check_ptr(kmean));
+    if (nmodes) CHECK(check_ptr(nmodes));
+    if (power_ws(dims_of(g), npairs, nbins) > kStaticScratchBytes) return GRIDSPT_EWORKSPACE;
+    void* ws = nullptr;
+    CHECK(static_scratch(&ws));
+    // every word of the scratch the kernels read is written earlier in the same call
+    return power_enqueue(c, g, fields_k, npairs, pairs, nbins, edge_n2, pk, kmean, nmodes, ws, Batch{});
 }
 
 // ---- one-point statistics ----
