@@ -142,3 +142,25 @@ def test_adjoint_euler_identity_256(ctx, dtype):
     terms = [(i + 1) * (gd[i].double() * fwd.delta[i].double()).sum().item() for i in range(nmax)]
     tol = 1e-11 if dtype == g.F64 else 2e-5
     assert abs(lhs - sum(terms)) <= tol * sum(abs(t) for t in terms), (lhs, terms)
+
+
+def test_adjoint_256_matches_oracle(ctx):
+    """The reverse mode at the adjoint workload's size and setup (256^3,
+    L = 1000 Mpc/h, z = 1, n <= 3, FP32) against the oracle's own adjoint on
+    the same noise and objective gradients (rounded to FP32)."""
+    n, box, nmax = 256, 1000.0, 3
+    c = g.cut_n2max(n, box)
+    grid = g.Grid(n, box, g.cube_kc(c), g.F32)
+    dz = oracle.growth(0.279, 0.721, 1.0)
+    lp = g.LinearSpectrum(amp=oracle.sigma8_amp(0.8, NS, GAMMA), ns=NS, gamma=GAMMA, growth=dz, n2max=c)
+    rng = np.random.default_rng(256)
+    w = rng.standard_normal((n, n, n)).astype(np.float32).astype(np.float64)
+    gd = rng.standard_normal((nmax, n, n, n)).astype(np.float32).astype(np.float64)
+    d1 = g.noise_field(ctx, grid, lp, _dev(w, grid))
+    fwd = g.orders(ctx, grid, nmax, c, c, d1)
+    gw = g.adjoint(ctx, grid, lp, nmax, c, fwd.delta_k, fwd.theta_k, [_dev(x, grid) for x in gd])
+    ctx.sync()
+    ref = oracle.adjoint(w, box, lp.amp, NS, GAMMA, dz, nmax, c, c, gd)
+    err = rel_l2(gw.cpu().numpy(), ref)
+    print("adjoint 256^3 FP32, nmax 3: rel L2 %.2e" % err, flush=True)
+    assert err < TOL[g.F32], err
