@@ -40,17 +40,20 @@ FFT_KINDS = ("zfwd_field", "zfwd_noise", "zfwd_products", "yfwd", "xfused_linear
              "xfused_order", "yinv", "zinv")
 
 
-def cpu_baseline(n_sample: int = 256, box: float = 1000.0, nmax: int = 5):
+def cpu_baseline(n_sample: int = 256, box: float = 1000.0, nmax: int = 5, threads: int = 0):
     """The FP64 oracle (as it stands) on a bounded sample: linear field and
-    D-form orders 1..nmax on an n_sample^3 grid, all host threads."""
+    D-form orders 1..nmax on an n_sample^3 grid, on `threads` host threads
+    (0: all)."""
     import oracle
-    cores = oracle.set_threads(0)
+    prev = oracle.set_threads(0)  # the current count (0 changes nothing)
+    cores = oracle.set_threads(threads) if threads > 0 else prev
     amp = oracle.sigma8_amp(0.8, 0.96, 0.21)
     cut = oracle.cut_n2max_strict(n_sample)
     t0 = time.perf_counter()
     d1 = oracle.linear_field(n_sample, box, amp, 0.96, 0.21, 1.0, cut, 3)
     oracle.orders(d1, box, nmax, cut, cut, form="D", spectra=False)
     dt = time.perf_counter() - t0
+    oracle.set_threads(prev)
     return {"value": n_sample ** 3 / dt / 1e6, "unit": "Mcells/s", "cores": int(cores), "kind": "oracle",
             "sample": "%d^3 grid, L=%g, linear field + D-form orders 1..%d, FP64, %.1f s" % (n_sample, box, nmax, dt)}
 
@@ -87,61 +90,91 @@ def measured_traffic(kind: str, args):
     return None
 
 
-def precision_report(args) -> int:
-    """FP32 path vs FP64 path (linear field + orders 1..nmax from the same
-    seed) on the chosen workload: relative L2 of every delta_n and theta_n,
-    and the FP64 throughput.  FP32 fields wait in host memory while the FP64
-    path runs."""
+def _field_error(host, dev64, slab=64):
+    """(relative L2, max |diff| / max |ref|) of a host field against a GPU FP64 field, slab by slab."""
+    import torch
+    num = den = dmax = rmax = 0.0
+    for x0 in range(0, dev64.shape[0], slab):
+        a = host[x0:x0 + slab].to(dev64.device, torch.float64)
+        b = dev64[x0:x0 + slab]
+        d = a - b
+        num += float((d * d).sum())
+        den += float((b * b).sum())
+        dmax = max(dmax, float(d.abs().max()))
+        rmax = max(rmax, float(b.abs().max()))
+        del a, d
+    return (num / den) ** 0.5, dmax / rmax
+
+
+def fp64_leg(args, host32, steps: int = 2):
+    """The same step on the FP64 path from the same seed, after the timed FP32
+    steps: its rate, and the error of the FP32 results against it per order
+    (relative L2 and largest cell error of delta_n and theta_n), of the FP64
+    sum of orders, and per spectrum bin (|dP| against sqrt(P_aa P_bb), and
+    against the bound the 1e-5 field tolerance implies for white rounding
+    noise: t (sqrt(P_aa Pbar_bb) + sqrt(Pbar_aa P_bb)) + t^2 sqrt(Pbar_aa Pbar_bb),
+    Pbar the mean power over every kept mode).  host32: the FP32 step's
+    delta, theta, sum of orders and P in host memory."""
+    import gc
+
+    import numpy as np
     import torch
 
     import paper_1807_04215_amd as g
 
-    n, box, z, nmax, _, desc = WORKLOADS[args.workload]
+    n, box, z, nmax, nbins, _ = WORKLOADS[args.workload]
     cut = g.cut_n2max(n, box)
-    dz = g.growth(0.279, 0.721, z)
-    amp = g.sigma8_amp(0.8, 0.96, 0.21)
-    lp = g.LinearSpectrum(amp=amp, ns=0.96, gamma=0.21, growth=dz, n2max=cut, seed=3)
-    host = {}
-    rates = {}
-    for dtype in (g.F32, g.F64):
-        grid = g.Grid(n, box, g.cube_kc(cut), dtype)
-        ctx = g.Context()
-        out = g.alloc_orders(grid, nmax, spectra=False)
-        ctx.workspace(g.workspace_bytes(grid, nmax))
-        for rep in range(2):                       # the second run is timed
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            g.linear_field(ctx, grid, lp, out=out.delta[0])
-            g.orders(ctx, grid, nmax, cut, cut, out.delta[0], out=out, spectra=False)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-        rates["f32" if dtype == g.F32 else "f64"] = n ** 3 / dt / 1e6
-        if dtype == g.F32:
-            for i in range(nmax):
-                host[("delta", i)] = out.delta[i].cpu()
-                if i > 0:
-                    host[("theta", i)] = out.theta[i].cpu()
-        else:
-            errs = []
-            for i in range(nmax):
-                row = []
-                for kind, t64 in (("delta", out.delta[i]), ("theta", out.theta[i])):
-                    t32 = host[(kind, i)] if (kind, i) in host else host[("delta", 0)]  # theta_1 = delta_1
-                    d = t32.to("cuda", torch.float64)
-                    num = torch.linalg.vector_norm((d - t64).reshape(-1)).item()
-                    den = torch.linalg.vector_norm(t64.reshape(-1)).item()
-                    row.append(num / den)
-                    del d
-                errs.append(row)
-        del out, ctx
-        import gc
-        gc.collect()
-        torch.cuda.empty_cache()
-    res = {"workload": "%s: %s" % (args.workload, desc), "mcells_per_s": {k: round(v, 1) for k, v in rates.items()},
-           "fp32_vs_fp64_rel_l2": {"delta": ["%.3e" % e[0] for e in errs], "theta": ["%.3e" % e[1] for e in errs]},
-           "tolerance": 1e-5}
-    print(json.dumps(res), flush=True)
-    return 0 if all(max(e) <= 1e-5 for e in errs) else 1
+    grid = g.Grid(n, box, g.cube_kc(cut), g.F64)
+    lp = g.LinearSpectrum(amp=g.sigma8_amp(0.8, 0.96, 0.21), ns=0.96, gamma=0.21, growth=g.growth(0.279, 0.721, z),
+                          n2max=cut, seed=3)
+    edges = g.linear_edges(nbins, n, 3, cut)
+    pairs = [(a, b) for a in range(nmax) for b in range(a, nmax)]
+    ctx = g.Context()
+    out = g.alloc_orders(grid, nmax, spectra=False, ctx=ctx)
+    out.delta_k = [ctx.empty(grid.cube_shape, grid.real_dtype) for _ in range(nmax)]
+    total = ctx.empty(grid.real_shape, torch.float64)
+
+    def step():
+        g.orders_linear(ctx, grid, lp, nmax, cut, out=out)
+        g.sum_orders(ctx, grid, out.delta, [1.0] * nmax, out=total)
+        return g.power(ctx, grid, out.delta_k, pairs, edges)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pk = step()[0]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / steps
+    pbar = g.power(ctx, grid, out.delta_k, [(a, a) for a in range(nmax)], [1, cut + 1])[0].cpu().numpy()[:, 0]
+    pk = pk.cpu().numpy()
+    del out.delta_k
+    gc.collect()
+    ed, et = [], []
+    for i in range(nmax):
+        ed.append(_field_error(host32["delta"][i], out.delta[i]))
+        et.append(_field_error(host32["theta"][i], out.theta[i]))
+    es = _field_error(host32["sum"], total)
+    diag = [pk[pairs.index((a, a))] for a in range(nmax)]
+    t = 1e-5
+    worst_rel = worst_bound = 0.0
+    for p, (a, b) in enumerate(pairs):
+        dp = np.abs(host32["pk"][p] - pk[p])
+        ok = diag[a] * diag[b] > 0
+        worst_rel = max(worst_rel, float((dp[ok] / np.sqrt(diag[a] * diag[b])[ok]).max()))
+        bound = t * (np.sqrt(diag[a] * pbar[b]) + np.sqrt(pbar[a] * diag[b])) + t * t * np.sqrt(pbar[a] * pbar[b])
+        worst_bound = max(worst_bound, float((dp[ok] / bound[ok]).max()))
+    del out, total, ctx
+    gc.collect()
+    torch.cuda.empty_cache()
+    return {"value": round(n ** 3 / (ms / 1000.0) / 1e6, 3), "unit": "Mcells/s", "ms_per_step": round(ms, 3),
+            "steps": steps, "error_of_fp32": {
+                "delta_rel_l2": ["%.3e" % e[0] for e in ed], "theta_rel_l2": ["%.3e" % e[0] for e in et],
+                "delta_max_cell": ["%.3e" % e[1] for e in ed], "theta_max_cell": ["%.3e" % e[1] for e in et],
+                "sum_of_orders_rel_l2": "%.3e" % es[0],
+                "pk_max_bin_over_sqrt_paa_pbb": "%.3e" % worst_rel,
+                "pk_max_bin_over_tolerance_bound": "%.3f" % worst_bound,
+                "tolerance_rel_l2": 1e-5}}
 
 
 def batch_groups(g, amp, dz, seed0=40):
@@ -505,8 +538,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-spectra", action="store_true", help="skip the spectrum stores and P(k)")
     ap.add_argument("--kernels", action="store_true", help="also print the per-kernel table to stderr")
-    ap.add_argument("--precision", action="store_true",
-                    help="FP32 path against the FP64 path from the same seed: per-order errors and FP64 rate")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip the FP64 leg (its rate and the FP32 errors against it) after the timed FP32 steps")
     ap.add_argument("--copy-probe", action="store_true",
                     help="one 4 GiB device-to-device copy (calibrates HBM byte counters), then exit")
     args = ap.parse_args()
@@ -530,8 +563,6 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 << 30, "copy_probe_bytes_written": 4 << 30}))
         return 0
-    if args.precision:
-        return precision_report(args)
     if args.workload == "c4":
         return batch_bench(args)
     if args.workload == "c5":
@@ -552,9 +583,9 @@ def main() -> int:
     pairs = [(a, b) for a in range(nmax) for b in range(a, nmax)]
 
     ctx = g.Context()
-    out = g.alloc_orders(grid, nmax, spectra=spectra)
+    out = g.alloc_orders(grid, nmax, spectra=spectra, ctx=ctx)
     ctx.workspace(g.workspace_bytes(grid, nmax))
-    total = torch.empty((n,) * 3, dtype=torch.float64, device="cuda")
+    total = ctx.empty(grid.real_shape, torch.float64)
     coef = [1.0] * nmax
 
     tuning = g.tune_orders(ctx, grid, lp, nmax, cut, out=out) if not args.no_tune else None
@@ -562,8 +593,7 @@ def main() -> int:
     def step():
         g.orders_linear(ctx, grid, lp, nmax, cut, out=out)  # linear field + orders 1..nmax
         g.sum_orders(ctx, grid, out.delta, coef, out=total)
-        if spectra:
-            g.power(ctx, grid, out.delta_k, pairs, edges)
+        return g.power(ctx, grid, out.delta_k, pairs, edges)[0] if spectra else None
 
     for _ in range(args.warmup):
         step()
@@ -572,11 +602,12 @@ def main() -> int:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        pk = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.set_profiling(False)
     prof = ctx.profile_read()
+    per_order = ctx.profile_orders()
 
     ms_step = (t1 - t0) * 1000.0 / args.steps
     value = n ** 3 / (ms_step / 1000.0) / 1e6
@@ -590,6 +621,9 @@ def main() -> int:
         for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"]):
             print("%-16s launches %4d  %9.3f ms/step  %8.1f GB/s" % (
                 k, v["launches"], v["ms"] / args.steps, v["bytes"] / max(v["ms"], 1e-9) / 1e6), file=sys.stderr)
+        for o, v in sorted(per_order.items()):
+            print("order %d: %9.3f ms/step  %8.1f GB/s" % (o, v["ms"] / args.steps,
+                                                           v["bytes"] / max(v["ms"], 1e-9) / 1e6), file=sys.stderr)
 
     res = {
         "metric": METRIC,
@@ -615,9 +649,30 @@ def main() -> int:
         "fft_hbm_gbs": round(fft_b / (fft_ms / 1000.0) / 1e9, 1) if fft_ms > 0 else None,
         "kernel_ms_per_step": round(kern_ms / args.steps, 3),
         "path_gbs": round(sum(v["bytes"] for v in prof.values()) / (kern_ms / 1000.0) / 1e9, 1),
+        # kernel time of each order's passes (order 1 with the linear field; the product pass of
+        # order n, which also finishes the z inverse of order n - 1, counts for order n)
+        "per_order_mcells_s": {str(o): round(n ** 3 / (v["ms"] / args.steps / 1000.0) / 1e6, 1)
+                               for o, v in sorted(per_order.items()) if o > 0},
+        "per_order_gbs": {str(o): round(v["bytes"] / (v["ms"] / 1000.0) / 1e9, 1)
+                          for o, v in sorted(per_order.items()) if o > 0},
+        "estimators_ms_per_step": round(per_order.get(0, {"ms": 0.0})["ms"] / args.steps, 3),
     }
+    if dtype == g.F32 and not args.no_fp64:
+        # the FP64 leg, outside the timed region: the FP32 results wait in host memory
+        import gc
+        host32 = {"delta": [t.cpu() for t in out.delta], "theta": [t.cpu() for t in out.theta], "sum": total.cpu(),
+                  "pk": pk.cpu().numpy() if pk is not None else None}
+        del out, total, pk, ctx
+        gc.collect()
+        torch.cuda.empty_cache()
+        if spectra:
+            f64 = fp64_leg(args, host32)
+            f64["speedup_fp32_over_fp64"] = round(value / f64["value"], 3)
+            res["fp64"] = f64
+        del host32
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline()
+        res["cpu_baseline_1thread"] = cpu_baseline(n_sample=128, threads=1)
     print(json.dumps(res), flush=True)
     return 0
 
