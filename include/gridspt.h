@@ -285,9 +285,9 @@ int gridspt_power(gridspt_ctx* ctx, const gridspt_grid* g, int32_t nfields, cons
 /* gridspt_power for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation):
  * the same arguments and results, without `work`.  Its scratch is a
- * library-owned array of 24 MiB per GPU (every GPU the library runs on holds
+ * library-owned array of 16 MiB per GPU (every GPU the library runs on holds
  * it until the process ends), enough for every valid call (at most about
- * 17.8 MB is used); a call needing more returns GRIDSPT_EWORKSPACE.  The call
+ * 14.7 MB is used); a call needing more returns GRIDSPT_EWORKSPACE.  The call
  * allocates nothing.  All calls on one GPU share that GPU's array: calls that
  * overlap in time on one GPU (several streams or threads) race and must be
  * ordered by the caller. */

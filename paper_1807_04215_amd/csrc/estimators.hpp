@@ -29,86 +29,105 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// Cross spectra.  A wavefront walks half-rows of the cube: the kx >= 0 part
-// (|kx| ascending) and the kx < 0 part (|kx| descending), so the bins of 64
-// consecutive modes are monotone and every bin present forms one contiguous
-// run of lanes.  A segmented inclusive scan over the 64 lanes (fixed order)
-// leaves each run's total in its last lane, which adds it to the wavefront's
-// own LDS accumulator.  Quantities per bin: npairs pair sums w Re[F_a F_b^*],
-// then sum w and sum w |k|.  Block partials [block][bin][q] are reduced in a
-// fixed order by k_power_reduce, so the result is bitwise reproducible.
-// Every kernel here takes a realisation stride zs (see zptr): gridDim.z
-// realisations in one launch.
+// Cross spectra (Eq. 19-21).  Along a half-row of the cube (fixed ky and kz;
+// kx >= 0, or kx < 0) |n|^2 = kx^2 + ky^2 + kz^2 grows with a = |kx|, so the
+// modes of the half-row inside the bins form one stretch a0 <= a < a1, and
+// bin b holds the part [lo_b, hi_b) of it given by integer square roots of
+// the bin's edges.  A wavefront takes one half-row at a time:
+//  1. lane j takes the j-th bin the half-row meets: its stretch and its
+//     number of pieces P_j = ceil(L_j / s), the piece length s chosen so
+//     that the pieces of a half-row usually fit the 64 lanes;
+//  2. lane p takes piece p, piece i of bin j, made of the modes
+//     lo_j + i + k P_j (k = 0, 1, ...) inside the stretch: the lanes of one
+//     bin read consecutive modes.  It sums the per-mode quantities in FP64
+//     registers with no bin test per mode: the products Re[F_a F_b^*], the
+//     mode count and sum |k|;
+//  3. the pieces' sums go to LDS, and lane j adds those of its bin, in piece
+//     order and times the half-plane weight w, to the wavefront's own
+//     accumulator [bin][q] in LDS.
+// Modes outside the bins (k = 0, the corners of the cube past the last edge)
+// are never read.  The block partials [block][bin][q] are reduced in a fixed
+// order by k_power_reduce: every sum has a fixed order, so the result is
+// bitwise reproducible.  Every kernel here takes a realisation stride zs
+// (see zptr): gridDim.z realisations in one launch.
 // ---------------------------------------------------------------------------
 constexpr int kPowerPairsPerLaunch = 16;
+constexpr int kPowerWaves = 4;
+static_assert(kPowerWaves % 2 == 0, "the piece table after the FP64 arrays must be 16-byte aligned");
 
 template <typename T>
 struct PowerArgs {
     const cpx<T>* f[kMaxFields];  // distinct fields used by this launch
     int pa[kPowerPairsPerLaunch], pb[kPowerPairsPerLaunch];  // indices into f
-    const int* bins;  // bin of every |n|^2 < n2lim (k_power_bins), -1 outside the bins
-    int64_t n2lim;
     int nf, npairs, nbins;
     double kF;
     double* partial;  // [gridDim.x][nbins][npairs + 2]
 };
 
-// Bin of every integer |n|^2 below n2lim: b with edges[b] <= n2 < edges[b + 1], else -1.
+// Bin b holds the integer |n|^2 with e[b] <= |n|^2 < e[b + 1].
 struct BinEdges {
     int64_t e[kMaxBins + 1];
     int nbins;
 };
-static __global__ void k_power_bins(BinEdges be, int* bins, int64_t n2lim) {
-    const int64_t n2 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n2 >= n2lim) return;
-    int bin = -1;
-    if (n2 >= be.e[0] && n2 < be.e[be.nbins]) {
-        int lo = 0, hi = be.nbins;  // e[lo] <= n2 < e[hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (n2 >= be.e[mid]) lo = mid;
-            else hi = mid;
-        }
-        bin = lo;
-    }
-    bins[n2] = bin;
+
+// LDS bytes of k_power_partial beyond its static edge table: per wavefront
+// the accumulators [nbins][q], the piece sums [64][q] and the piece table.
+__host__ __device__ constexpr size_t power_shm_bytes(int nbins, int nq) {
+    return (size_t)kPowerWaves * (((size_t)nbins + 64) * nq * sizeof(double) + 64 * 4 * sizeof(int));
 }
 
-constexpr int kPowerWaves = 4;
-
-// Lane moves of the segmented scan, as DPP modifiers (VALU, no LDS traffic):
-// row shift right by S within rows of 16 lanes, lane 15 of a row to the next
-// row (rows 1 and 3), lane 31 to the upper half (rows 2 and 3).  Lanes
-// without a source, or outside the row mask, keep `old`.
+// DPP lane moves (VALU, no LDS traffic): row shift right by S within rows of
+// 16 lanes, lane 15 of a row to the next row, lane 31 to the upper half.
+// Lanes without a source, or in rows outside the row mask, get `old`.
 constexpr int kDppRowShr = 0x110, kDppBcast15 = 0x142, kDppBcast31 = 0x143;
 
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ int dpp_int(int old, int v) {
-    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWMASK, 0xf, false);
-}
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ double dpp_dbl(double old, double v) {
-    const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)x, CTRL, ROWMASK, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(x >> 32), CTRL, ROWMASK, 0xf, false);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+// Inclusive prefix sum of v over the 64 lanes: shifts 1, 2, 4, 8 within rows
+// of 16, then lane 15 into rows 1 and 3, then lane 31 into rows 2 and 3.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, kDppRowShr + 1, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, kDppRowShr + 2, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, kDppRowShr + 4, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, kDppRowShr + 8, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, kDppBcast15, 0xa, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, kDppBcast31, 0xc, 0xf, false);
+    return v;
 }
 
-// One step of the segmented inclusive scan: lane i adds the value of its
-// DPP source lane when that lane holds the same bin.  Bins are monotone along
-// the 64 lanes, so equal bins at the two ends mean the whole stretch between
-// them is one run.
-template <int CTRL, int ROWMASK, int NQ>
-__device__ __forceinline__ void seg_scan_step(int bin, double (&v)[NQ], int npairs, int qp) {
-    const int ob = dpp_int<CTRL, ROWMASK>(-2, bin);
-    const bool same = ob == bin;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        if (q < npairs || q >= qp) {
-            const double o = dpp_dbl<CTRL, ROWMASK>(0.0, v[q]);
-            if (same) v[q] += o;
-        }
-    }
+// sqrt(n) for an integer 1 <= n < 2^31: the hardware reciprocal square root y,
+// then one Goldschmidt step on (x y, y / 2) and one Newton step on the root;
+// within about an ulp of the correctly rounded root.
+__device__ __forceinline__ double root_of_int(int n) {
+    const double x = (double)n, y = __builtin_amdgcn_rsq(x);
+    double s = x * y, h = 0.5 * y;
+    const double r = fma(-h, s, 0.5);
+    s = fma(s, r, s);
+    h = fma(h, r, h);
+    return fma(fma(-s, s, x), h, s);
+}
+
+// The least a >= 0 with a^2 >= x, capped at kc1 (x >= kc1^2 gives kc1, kc1 < 46341):
+// the truncated root corrected to the exact floor, then rounded up.
+__device__ __forceinline__ int ceil_sqrt(int64_t x, int kc1) {
+    if (x <= 0) return 0;
+    if (x >= (int64_t)kc1 * kc1) return kc1;
+    const int n = (int)x;
+    int r = (int)root_of_int(n);
+    if (r * r > n) --r;
+    if ((r + 1) * (r + 1) <= n) ++r;
+    return r * r < n ? r + 1 : r;
+}
+
+// v & m: the AND is written as an instruction so that it stays one VALU
+// operation on the loaded word (a select on the converted FP64 value would
+// take two)
+__device__ __forceinline__ float and_bits(float v, unsigned m) {
+    float r;
+    asm("v_and_b32 %0, %1, %2" : "=v"(r) : "v"(v), "v"(m));
+    return r;
+}
+__device__ __forceinline__ double and_bits(double v, unsigned m) {
+    return __hiloint2double(__float_as_int(and_bits(__int_as_float(__double2hiint(v)), m)),
+                            __float_as_int(and_bits(__int_as_float(__double2loint(v)), m)));
 }
 
 // Row-major index of the pair (i, j), i <= j, among all pairs of TRI fields.
@@ -118,119 +137,173 @@ __host__ __device__ constexpr int tri_index(int i, int j, int tri) { return i * 
 // i <= j of the TRI fields (a.npairs = TRI (TRI + 1) / 2), each field loaded
 // once per mode; the requested pairs are picked out by k_power_final.
 template <typename T, int TRI>
-__global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T> a, CubeDims cd, size_t zs) {
+__global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T> a, BinEdges be, CubeDims cd,
+                                                                     size_t zs) {
     constexpr int QP = kPowerPairsPerLaunch;
-    extern __shared__ double acc[];  // [kPowerWaves][nbins][Q]
-    const int Q = a.npairs + 2;
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    for (int i = threadIdx.x; i < kPowerWaves * a.nbins * Q; i += blockDim.x) acc[i] = 0.0;
+    constexpr int NP = TRI > 0 ? TRI * (TRI + 1) / 2 : QP;  // pair sums held per lane
+    constexpr int NQ = NP + 2;                               // then the mode count and sum |k|
+    constexpr int NF = TRI > 0 ? TRI : 2 * QP;               // values loaded per mode
+    constexpr int G = TRI > 0 ? 2 : 1;                       // modes whose loads are issued together
+    extern __shared__ double smem[];
+    __shared__ int64_t edge[kMaxBins + 1];
+    // pair sums per mode (TRI > 0: all NP of them), quantities per bin
+    const int npairs = TRI > 0 ? NP : a.npairs, Q = npairs + 2, nb = be.nbins;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / 64), lane = threadIdx.x % 64;
+    for (int i = threadIdx.x; i < kPowerWaves * nb * Q; i += blockDim.x) smem[i] = 0.0;
+    for (int i = threadIdx.x; i <= nb; i += blockDim.x) edge[i] = be.e[i];
     __syncthreads();
-    double* my = acc + (size_t)wave * a.nbins * Q;
-    const int Kx = cd.Ky;
-    const long nhalf = 2L * cd.Kz * cd.Ky;  // half-rows
-    const long gw = (long)blockIdx.x * kPowerWaves + wave, nw = (long)gridDim.x * kPowerWaves;
-    for (long hr = gw; hr < nhalf; hr += nw) {
-        const long rowi = hr >> 1;
-        const int half = (int)(hr & 1);
-        const int kz = (int)(rowi / cd.Ky), kyc = (int)(rowi % cd.Ky);
-        const int ky = kyc <= cd.Kc ? kyc : kyc - cd.Ky;
+    double* acc = smem + (size_t)wave * nb * Q;                                    // [nbins][Q]
+    double* stage = smem + (size_t)kPowerWaves * nb * Q + (size_t)wave * 64 * Q;  // [64][Q]
+    int4* piece = reinterpret_cast<int4*>(smem + (size_t)kPowerWaves * (nb + 64) * Q) + wave * 64;
+    // the launch's field of load slot i (TRI > 0: field i; else pair i / 2, side i % 2)
+    auto field = [&](int i) -> const cpx<T>* {
+        if constexpr (TRI > 0) return zptr(a.f[i], zs);
+        else return zptr(a.f[(i & 1) ? a.pb[i >> 1] : a.pa[i >> 1]], zs);
+    };
+    const int Kc = cd.Kc, Kx = cd.Ky, kc1 = cd.Kc + 1;
+    const int nhalf = 2 * cd.Kz * cd.Ky;  // < 2^31 for every cube the library accepts
+    const int gw = blockIdx.x * kPowerWaves + wave, nw = gridDim.x * kPowerWaves;
+    for (int hr = gw; hr < nhalf; hr += nw) {
+        // everything of the half-row is uniform over the wavefront
+        const int rowi = hr >> 1, half = hr & 1;
+        const int kz = rowi / cd.Ky, kyc = rowi - kz * cd.Ky;
+        const int ky = kyc <= Kc ? kyc : kyc - cd.Ky;
+        const int c2 = ky * ky + kz * kz;
+        // the modes in the bins: a0 <= a < a1, a = |kx| (a >= 1 for kx < 0)
+        const int a0 = __builtin_amdgcn_readfirstlane(max(half, ceil_sqrt(edge[0] - c2, kc1)));
+        const int a1 = __builtin_amdgcn_readfirstlane(ceil_sqrt(edge[nb] - c2, kc1));
+        if (a0 >= a1) continue;
         const double w = kz == 0 ? 1.0 : 2.0;
-        const size_t base = (size_t)rowi * Kx;
-        const int c_begin = half ? cd.Kc + 1 : 0, c_end = half ? Kx : cd.Kc + 1;
-        // The raw loads of a chunk of 64 modes: unconditional (clamped to a valid mode of the
-        // row), so no branch waits on a load; U chunks are loaded before the first is used.
-        struct Chunk {
-            int bin;
-            int64_t n2;
-            cpx<T> x[TRI > 0 ? TRI : 2 * QP];
-        };
-        auto load = [&](int c0, Chunk& ch) {
-            const int kxc = c0 + lane;
-            const bool valid = kxc < c_end;
-            const int kx = kxc <= cd.Kc ? kxc : kxc - Kx;
-            ch.n2 = (int64_t)kx * kx + (int64_t)ky * ky + (int64_t)kz * kz;
-            const bool inb = valid && ch.n2 < a.n2lim;
-            const int b = a.bins[inb ? ch.n2 : 0];
-            ch.bin = inb ? b : -1;
-            const size_t at = base + (valid ? kxc : c_begin);
-            if constexpr (TRI > 0) {
+        const int L = a1 - a0;
+        // bins of the first and the last mode: the number of upper edges at or below their |n|^2
+        const int64_t n2f = (int64_t)a0 * a0 + c2, n2l = (int64_t)(a1 - 1) * (a1 - 1) + c2;
+        int bf = 0, bl = 0;
+        for (int g = 0; g < nb; g += 64) {
+            const int e = g + lane + 1;
+            const int64_t up = e <= nb ? edge[e] : (int64_t)0x7fffffffffffffffll;
+            bf += __popcll(__ballot(up <= n2f));
+            bl += __popcll(__ballot(up <= n2l));
+        }
+        const int nbr = bl - bf + 1;  // bins the half-row meets (some may hold no mode)
+        // piece length: the pieces fit the lanes when fewer than 64 bins are met,
+        // and stay within about twice the length of an even split of the stretch
+        const int even = (L + 63) / 64;
+        const int s = nbr < 64 ? max(1, min((L + 63 - nbr) / (64 - nbr), 2 * even + 2)) : even;
+        const float rs = 1.0f / (float)s;
+        const cpx<T>* row[NF];
 #pragma unroll
-                for (int i = 0; i < TRI; ++i) ch.x[i] = zptr(a.f[i], zs)[at];
-            } else {
-                // repeated fields of different pairs hit the cache
+        for (int i = 0; i < NF; ++i)
+            if (TRI > 0 || i < 2 * npairs) row[i] = field(i) + (size_t)rowi * Kx;
+        for (int g0 = 0; g0 < nbr; g0 += 64) {
+            // lane j: bin b = bf + g0 + j, its stretch [lo, hi) and its np pieces
+            const int j = g0 + lane, b = bf + j;
+            int lo = 0, hi = 0;
+            if (j < nbr) {
+                lo = max(a0, ceil_sqrt(edge[b] - c2, kc1));
+                hi = min(a1, ceil_sqrt(edge[b + 1] - c2, kc1));
+            }
+            const int len = max(0, hi - lo);
+            const int x = len + s - 1;  // np = floor(x / s): the float quotient is off by at most one
+            int np = (int)((float)x * rs);
+            if (np * s > x) --np;
+            if ((np + 1) * s <= x) ++np;
+            const int incl = wave_incl_scan(np);
+            const int off = incl - np;                               // first piece of bin j
+            const int npc = __builtin_amdgcn_readlane(incl, 63);     // pieces of this group of bins
+            for (int r0 = 0; r0 < npc; r0 += 64) {
+                // bin lanes: the table entry of each of their pieces in this round
+                const int t0 = max(off, r0), t1 = min(off + np, r0 + 64);
+                for (int t = t0; t < t1; ++t) piece[t - r0] = make_int4(lo + (t - off), np, hi, 0);
+                wave_sync();
+                // piece lanes: modes d.x + k d.y < d.z; a lane past the last piece has none
+                const bool act = r0 + lane < npc;
+                const int4 d = act ? piece[lane] : make_int4(a0, 1, a0, 0);
+                double v[NQ];
 #pragma unroll
-                for (int q = 0; q < QP; ++q) {
-                    if (q < a.npairs) {  // uniform
-                        ch.x[2 * q] = zptr(a.f[a.pa[q]], zs)[at];
-                        ch.x[2 * q + 1] = zptr(a.f[a.pb[q]], zs)[at];
+                for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+                for (int k = 0; __ballot(d.x + k * d.y < d.z); k += G) {
+                    int am[G];
+                    unsigned mk[G];  // all ones for a mode of the piece, else 0
+#pragma unroll
+                    for (int gg = 0; gg < G; ++gg) {
+                        const int m = d.x + (k + gg) * d.y;
+                        mk[gg] = m < d.z ? 0xffffffffu : 0u;
+                        am[gg] = m < d.z ? m : a0;  // a mode of the stretch: the load stays in the row
+                    }
+                    cpx<T> xs[G][NF];
+#pragma unroll
+                    for (int gg = 0; gg < G; ++gg) {
+                        const uint32_t o = (uint32_t)(half ? Kx - am[gg] : am[gg]);
+#pragma unroll
+                        for (int i = 0; i < NF; ++i)
+                            if (TRI > 0 || i < 2 * npairs) xs[gg][i] = ldo(row[i], o);  // uniform guard
+                    }
+                    // a mode past the piece adds zeros (its values masked to +0)
+#pragma unroll
+                    for (int gg = 0; gg < G; ++gg) {
+                        double re[NF], im[NF];
+#pragma unroll
+                        for (int i = 0; i < NF; ++i) {
+                            re[i] = (double)and_bits(xs[gg][i].x, mk[gg]);
+                            im[i] = (double)and_bits(xs[gg][i].y, mk[gg]);
+                        }
+                        if constexpr (TRI > 0) {
+#pragma unroll
+                            for (int i = 0; i < TRI; ++i)
+#pragma unroll
+                                for (int i2 = i; i2 < TRI; ++i2) {
+                                    double& t = v[tri_index(i, i2, TRI)];
+                                    t = fma(re[i], re[i2], t);
+                                    t = fma(im[i], im[i2], t);
+                                }
+                        } else {
+#pragma unroll
+                            for (int q = 0; q < QP; ++q) {
+                                if (q < npairs) {
+                                    v[q] = fma(re[2 * q], re[2 * q + 1], v[q]);
+                                    v[q] = fma(im[2 * q], im[2 * q + 1], v[q]);
+                                }
+                            }
+                        }
+                        v[NP] += and_bits(1.0, mk[gg]);
+                        v[NP + 1] = fma(and_bits(a.kF, mk[gg]), root_of_int(am[gg] * am[gg] + c2), v[NP + 1]);
                     }
                 }
-            }
-        };
-        auto accumulate = [&](const Chunk& ch) {
-            const int bin = ch.bin;
-            if (!__any(bin >= 0)) return;
-            // per-mode quantities (zero off the bins)
-            double v[QP + 2];
+                if (act) {
+                    double* dst = stage + lane * Q;
 #pragma unroll
-            for (int q = 0; q < QP; ++q) v[q] = 0.0;
-            const double wb = bin >= 0 ? w : 0.0;
-            if constexpr (TRI > 0) {
-                double re[TRI], im[TRI];
-#pragma unroll
-                for (int i = 0; i < TRI; ++i) {
-                    re[i] = (double)ch.x[i].x;
-                    im[i] = (double)ch.x[i].y;
+                    for (int q = 0; q < NP; ++q)
+                        if (q < npairs) dst[q] = v[q];
+                    dst[npairs] = v[NP];
+                    dst[npairs + 1] = v[NP + 1];
                 }
+                wave_sync();
+                // bin lanes: their pieces of this round in order, weighted, into the accumulator
+                if (t1 > t0) {
+                    double sum[NQ];
 #pragma unroll
-                for (int i = 0; i < TRI; ++i)
+                    for (int q = 0; q < NQ; ++q) sum[q] = 0.0;
+                    for (int t = t0; t < t1; ++t) {
+                        const double* src = stage + (t - r0) * Q;
 #pragma unroll
-                    for (int j = i; j < TRI; ++j) v[tri_index(i, j, TRI)] = wb * (re[i] * re[j] + im[i] * im[j]);
-            } else {
-#pragma unroll
-                for (int q = 0; q < QP; ++q) {
-                    if (q < a.npairs) {
-                        const cpx<T> x = ch.x[2 * q], y = ch.x[2 * q + 1];
-                        v[q] = wb * ((double)x.x * (double)y.x + (double)x.y * (double)y.y);
+                        for (int q = 0; q < NQ; ++q)
+                            if (q < Q) sum[q] += src[q];
                     }
+                    double* dst = acc + (size_t)b * Q;
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q)
+                        if (q < Q) dst[q] += w * sum[q];
                 }
+                wave_sync();
             }
-            v[QP] = wb;
-            v[QP + 1] = bin >= 0 ? w * a.kF * sqrt((double)ch.n2) : 0.0;
-            // segmented inclusive scan over runs of equal bin: shifts 1, 2, 4, 8
-            // within rows of 16 lanes, then the row-15 and row-31 broadcasts
-            seg_scan_step<kDppRowShr + 1, 0xf>(bin, v, a.npairs, QP);
-            seg_scan_step<kDppRowShr + 2, 0xf>(bin, v, a.npairs, QP);
-            seg_scan_step<kDppRowShr + 4, 0xf>(bin, v, a.npairs, QP);
-            seg_scan_step<kDppRowShr + 8, 0xf>(bin, v, a.npairs, QP);
-            seg_scan_step<kDppBcast15, 0xa>(bin, v, a.npairs, QP);
-            seg_scan_step<kDppBcast31, 0xc>(bin, v, a.npairs, QP);
-            const int nb = __shfl_down(bin, 1, 64);
-            const bool last = lane == 63 || nb != bin;
-            if (last && bin >= 0) {
-                double* dst = my + (size_t)bin * Q;
-#pragma unroll
-                for (int q = 0; q < QP; ++q)
-                    if (q < a.npairs) dst[q] += v[q];
-                dst[a.npairs] += v[QP];
-                dst[a.npairs + 1] += v[QP + 1];
-            }
-        };
-        constexpr int U = TRI > 0 ? 3 : 1;  // the pair path holds two loads per pair already
-        for (int c0 = c_begin; c0 < c_end; c0 += 64 * U) {
-            Chunk ch[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) load(c0 + 64 * u, ch[u]);
-#pragma unroll
-            for (int u = 0; u < U; ++u) accumulate(ch[u]);
         }
     }
     __syncthreads();
-    double* out = zptr(a.partial, zs) + (size_t)blockIdx.x * a.nbins * Q;
-    for (int i = threadIdx.x; i < a.nbins * Q; i += blockDim.x) {
-        double s = 0.0;
-        for (int wv = 0; wv < kPowerWaves; ++wv) s += acc[(size_t)wv * a.nbins * Q + i];
-        out[i] = s;
+    double* out = zptr(a.partial, zs) + (size_t)blockIdx.x * nb * Q;
+    for (int i = threadIdx.x; i < nb * Q; i += blockDim.x) {
+        double sum = 0.0;
+        for (int wv = 0; wv < kPowerWaves; ++wv) sum += smem[(size_t)wv * nb * Q + i];
+        out[i] = sum;
     }
 }
 

@@ -26,15 +26,58 @@ namespace {
 
 // per-wave LDS accumulators: nbins * (pairs + 2) doubles, at most 1792 (56 KB per block)
 int power_chunk(int nbins) { return std::max(1, std::min(kPowerPairsPerLaunch, 1792 / nbins - 2)); }
+// Block partials are sized for power_blocks (at most 1024 blocks); a launch
+// uses no more blocks than the GPU holds at once (power_launch_blocks), so that
+// every wavefront's share of half-rows runs in one round.
 int power_blocks(const Dims& d) {
     const int64_t halves = 2 * d.Kz * d.Ky;
     return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (halves + kPowerWaves - 1) / kPowerWaves));
 }
+template <typename Kern>
+int power_launch_blocks(const Dims& d, Kern kern, size_t shm, unsigned nz) {
+    const int most = power_blocks(d);
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+        hipSuccess || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * kPowerWaves, shm) != hipSuccess)
+        return most;
+    const int64_t resident = (int64_t)std::max(cus, 1) * std::max(per_cu, 1) / std::max(nz, 1u);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(most, resident));
+}
 int64_t power_ws(const Dims& d, int npairs, int nbins) {
     const int q = std::min(npairs, power_chunk(nbins)) + 2;
-    // block partials, the reduced sums, the bin of every |n|^2 inside the cube
-    return align_up((int64_t)power_blocks(d) * nbins * q * 8) + align_up((int64_t)nbins * q * 8) +
-           align_up((d.Kc + 1) * (d.Kc + 1) * 3 * 4);
+    // block partials and the reduced sums
+    return align_up((int64_t)power_blocks(d) * nbins * q * 8) + align_up((int64_t)nbins * q * 8);
+}
+
+// Modes of the cube with e0 <= |n|^2 < e1: what the cross-spectrum kernel
+// reads of each field (its algorithmic traffic, for the launch records).
+int64_t modes_in_shells(const Dims& d, int64_t e0, int64_t e1) {
+    static std::mutex mu;
+    static std::array<int64_t, 4> last{-1, -1, -1, -1};
+    std::lock_guard<std::mutex> lock(mu);
+    if (last[0] == d.Kc && last[1] == e0 && last[2] == e1) return last[3];
+    const int64_t kc = d.Kc, kc1 = kc + 1;
+    // the number of a in [0, Kc] with a^2 < x
+    auto below = [&](int64_t x) -> int64_t {
+        if (x <= 0) return 0;
+        if (x > kc * kc) return kc1;
+        int64_t r = (int64_t)std::sqrt((double)x);
+        while (r * r >= x) --r;
+        while ((r + 1) * (r + 1) < x) ++r;
+        return r + 1;
+    };
+    int64_t n = 0;
+    for (int64_t kz = 0; kz <= kc; ++kz)
+        for (int64_t ky = 0; ky <= kc; ++ky) {
+            const int64_t c2 = ky * ky + kz * kz;
+            // kx in [-Kc, Kc]: a = 0 once, a >= 1 twice
+            const int64_t lo = below(e0 - c2), hi = below(e1 - c2);
+            const int64_t in0 = hi > 0 && lo == 0 ? 1 : 0;  // a = 0 inside
+            const int64_t row = std::max<int64_t>(0, hi - lo) * 2 - in0;
+            n += ky == 0 ? row : 2 * row;
+        }
+    last = {d.Kc, e0, e1, n};
+    return n;
 }
 
 int check_power_args(int nfields, int npairs, const int32_t* pairs, int nbins, const int64_t* edge_n2) {
@@ -61,17 +104,11 @@ int power_enqueue(gridspt_ctx* c, const gridspt_grid* g, const void* const* fiel
         double* partial = static_cast<double*>(work);
         const int64_t part_bytes = align_up((int64_t)nblk * nbins * (std::min(npairs, chunk) + 2) * 8);
         double* sums = reinterpret_cast<double*>(static_cast<char*>(work) + part_bytes);
-        int* bins = reinterpret_cast<int*>(static_cast<char*>(work) + part_bytes +
-                                           align_up((int64_t)nbins * (std::min(npairs, chunk) + 2) * 8));
-        // every mode of the cube has |n|^2 <= 3 Kc^2 < 3 (Kc + 1)^2
-        const int64_t n2lim = std::min<int64_t>(edge_n2[nbins], 3 * (d.Kc + 1) * (d.Kc + 1));
-        {
-            BinEdges be{};
-            for (int b = 0; b <= nbins; ++b) be.e[b] = edge_n2[b];
-            be.nbins = nbins;
-            CHECK(launch(c, KD_POWER_FINAL, (double)n2lim * 4.0, dim3((unsigned)((n2lim + 255) / 256)), dim3(256), 0,
-                         k_power_bins, be, bins, n2lim));
-        }
+        BinEdges be{};
+        for (int b = 0; b <= nbins; ++b) be.e[b] = edge_n2[b];
+        be.nbins = nbins;
+        // modes read per field (only counted for the launch records)
+        const int64_t nread = c->profile ? modes_in_shells(d, edge_n2[0], edge_n2[nbins]) : 0;
         for (int p0 = 0; p0 < npairs; p0 += chunk) {
             const int np = std::min(chunk, npairs - p0);
             PowerArgs<T> a{};
@@ -101,28 +138,31 @@ int power_enqueue(gridspt_ctx* c, const gridspt_grid* g, const void* const* fiel
                 for (int q = 0; q < np; ++q)
                     pc.col[q] = tri_index(std::min(a.pa[q], a.pb[q]), std::max(a.pa[q], a.pb[q]), tri);
             }
-            a.bins = bins;
-            a.n2lim = n2lim;
             a.nf = nf;
             a.npairs = nacc;
             a.nbins = nbins;
             a.kF = 2.0 * M_PI / g->box;
             a.partial = partial;
             const int nq = nacc + 2;
-            const size_t shm = (size_t)kPowerWaves * nbins * nq * sizeof(double);
+            const size_t shm = power_shm_bytes(nbins, nq);
             const CubeDims cdims{(int)d.Kc, (int)d.Kz, (int)d.Ky};
-            const dim3 pgrid(nblk, 1, nz), pblock(64 * kPowerWaves);
-            const double pbytes = (double)nz * nf * d.cube() * d.cpx_bytes;
+            const dim3 pblock(64 * kPowerWaves);
+            const double pbytes = (double)nz * nf * nread * d.cpx_bytes;
+            int used = nblk;  // blocks of this launch (<= nblk, the partials' capacity)
+            auto go = [&](auto kern) {
+                used = power_launch_blocks(d, kern, shm, nz);
+                return launch(c, KD_POWER, pbytes, dim3(used, 1, nz), pblock, shm, kern, a, be, cdims, bt.zs);
+            };
             switch (tri) {
-                case 1: CHECK(launch(c, KD_POWER, pbytes, pgrid, pblock, shm, k_power_partial<T, 1>, a, cdims, bt.zs)); break;
-                case 2: CHECK(launch(c, KD_POWER, pbytes, pgrid, pblock, shm, k_power_partial<T, 2>, a, cdims, bt.zs)); break;
-                case 3: CHECK(launch(c, KD_POWER, pbytes, pgrid, pblock, shm, k_power_partial<T, 3>, a, cdims, bt.zs)); break;
-                case 4: CHECK(launch(c, KD_POWER, pbytes, pgrid, pblock, shm, k_power_partial<T, 4>, a, cdims, bt.zs)); break;
-                case 5: CHECK(launch(c, KD_POWER, pbytes, pgrid, pblock, shm, k_power_partial<T, 5>, a, cdims, bt.zs)); break;
-                default: CHECK(launch(c, KD_POWER, pbytes, pgrid, pblock, shm, k_power_partial<T, 0>, a, cdims, bt.zs));
+                case 1: CHECK(go(k_power_partial<T, 1>)); break;
+                case 2: CHECK(go(k_power_partial<T, 2>)); break;
+                case 3: CHECK(go(k_power_partial<T, 3>)); break;
+                case 4: CHECK(go(k_power_partial<T, 4>)); break;
+                case 5: CHECK(go(k_power_partial<T, 5>)); break;
+                default: CHECK(go(k_power_partial<T, 0>));
             }
-            CHECK(launch(c, KD_POWER_FINAL, (double)nz * nblk * nbins * nq * 8.0, dim3(nbins * nq, 1, nz),
-                         dim3(kReduceThreads), 0, k_power_reduce, (const double*)partial, nblk, sums, bt.zs));
+            CHECK(launch(c, KD_POWER_FINAL, (double)nz * used * nbins * nq * 8.0, dim3(nbins * nq, 1, nz),
+                         dim3(kReduceThreads), 0, k_power_reduce, (const double*)partial, used, sums, bt.zs));
             CHECK(launch(c, KD_POWER_FINAL, 0.0, dim3((nbins + 63) / 64, 1, nz), dim3(64), 0, k_power_final,
                          (const double*)sums, nbins, nq, np, pc, g->box * g->box * g->box, pk + (size_t)p0 * nbins,
                          nbins, p0 == 0 ? kmean : nullptr, p0 == 0 ? nmodes : nullptr, bt.zs));
@@ -137,11 +177,11 @@ int power_enqueue(gridspt_ctx* c, const gridspt_grid* g, const void* const* fiel
 // Scratch of gridspt_power_static, for callers that cannot allocate: one array
 // per GPU, held for the life of the process.  Its largest use: 1024 blocks x
 // 1792 partial sums (nbins (pairs per launch + 2) <= 1792 for every nbins <=
-// 256) of 8 bytes, the reduced sums, and the bin table of the largest cube
-// (3 x 512^2 ints): about 17.8 MB.  In host code `scratch` only names the
-// symbol; the device address comes from hipGetSymbolAddress, once per device.
+// 256) of 8 bytes, and the reduced sums: about 14.7 MB.  In host code
+// `scratch` only names the symbol; the device address comes from
+// hipGetSymbolAddress, once per device.
 // ---------------------------------------------------------------------------
-constexpr int64_t kStaticScratchBytes = 24ll << 20;
+constexpr int64_t kStaticScratchBytes = 16ll << 20;
 constexpr int kMaxDevices = 64;
 static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 

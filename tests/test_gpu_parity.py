@@ -181,6 +181,84 @@ def test_power_many_pairs_chunked(ctx):
     assert np.allclose(pk.cpu().numpy(), rpk, rtol=1e-10, atol=1e-12 * np.abs(rpk).max())
 
 
+def _random_cubes(grid, nf, seed):
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    return [torch.randn(grid.cube_shape, generator=gen, device="cuda", dtype=grid.real_dtype) for _ in range(nf)]
+
+
+def _cube_to_half(c, n, kc):
+    """cube [kz, ky', kx'] (complex numpy) -> half layout [ix, iy, iz], zero outside the cube"""
+    from tests.layouts import cube_positions
+    h = np.zeros((n, n, n // 2 + 1), dtype=np.complex128)
+    p = cube_positions(n, kc)
+    h[np.ix_(p, p, np.arange(kc + 1))] = np.transpose(c, (2, 1, 0))
+    return h
+
+
+@pytest.mark.parametrize("dtype", [g.F64, g.F32])
+@pytest.mark.parametrize("nf,npairs", [(5, 15), (6, 9)])
+def test_power_narrow_and_empty_bins(ctx, dtype, nf, npairs):
+    """256 bins a third of a mode step wide in |n| on a 256^3 grid (Kc = 85),
+    so that a half-row near the axis meets more than 64 bins and its pieces
+    take two groups of bins, and several rounds of 64 pieces where bins hold
+    many modes; two empty bins (equal edges).  All pairs of five fields (each
+    field loaded once per mode) and pairs over six fields.  Random spectra, so
+    every product counts.  Products of FP32 values are exact in FP64, so
+    both precisions are held to 1e-12 against the oracle's direct sum."""
+    n, box = 256, 1000.0
+    cut = g.cut_n2max(n, box)
+    kc = g.cube_kc(cut)
+    grid = g.Grid(n, box, kc, dtype)
+    r = np.sqrt(cut) * np.arange(1, 255) / 254.0
+    edges = np.concatenate([[1, 1, 2, 2], np.ceil(r * r).astype(np.int64)[1:]]).astype(np.int64)
+    edges = np.maximum.accumulate(edges)
+    edges[-1] = cut + 1
+    assert len(edges) == 257 and np.all(np.diff(edges) >= 0)
+    cubes = _random_cubes(grid, nf, 70 + nf)
+    if nf == 5:
+        pairs = [(a, b) for a in range(5) for b in range(a, 5)]
+    else:
+        pairs = [(0, 5), (1, 4), (2, 3), (5, 5), (3, 1), (4, 4), (0, 0), (2, 5), (1, 1)]
+    assert len(pairs) == npairs
+    pk, km, nm = g.power(ctx, grid, cubes, pairs, edges)
+    ctx.sync()
+    halves = [_cube_to_half(cube_from_tensor(c), n, kc) for c in cubes]
+    rpk, rkm, rnm = oracle.power(halves, box, pairs, edges)
+    assert np.array_equal(nm.cpu().numpy(), rnm)
+    assert rnm[0] == 0 and rnm[2] == 0 and rnm[1] == 6     # [1, 1) and [2, 2) are empty, [1, 2) holds |n| = 1
+    assert np.allclose(km.cpu().numpy(), rkm, rtol=1e-13, atol=0)
+    got = pk.cpu().numpy()
+    auto = {f: oracle.power([halves[f]], box, [(0, 0)], edges)[0][0] for f in range(nf)}
+    ok = rnm > 0
+    for p, (a, b) in enumerate(pairs):
+        err = np.abs(got[p] - rpk[p])[ok] / np.sqrt(auto[a] * auto[b])[ok]
+        assert err.max() < 1e-12, (pairs[p], err.max())
+
+
+@pytest.mark.parametrize("dtype", [g.F64, g.F32])
+def test_power_bins_past_the_cube_corners(ctx, dtype):
+    """A last edge past the cube's corners (3 (Kc + 1)^2): every stored mode but
+    k = 0 is binned, so sum_b N_b = (2 Kc + 1)^3 - 1 and sum_b N_b P_aa / L^3
+    is the weighted power of the whole cube; the first bin ends at the cut."""
+    n, box = 96, 300.0
+    cut = g.cut_n2max(n, box)
+    kc = g.cube_kc(cut)
+    grid = g.Grid(n, box, kc, dtype)
+    edges = [1, cut + 1, 3 * (kc + 1) ** 2 + 7]
+    cubes = _random_cubes(grid, 2, 81)
+    pk, km, nm = g.power(ctx, grid, cubes, [(0, 0), (0, 1)], edges)
+    ctx.sync()
+    nmv = nm.cpu().numpy()
+    assert nmv.sum() == (2 * kc + 1) ** 3 - 1
+    c = [cube_from_tensor(t).astype(np.complex128) for t in cubes]  # products in FP64, as on the GPU
+    kz = np.arange(kc + 1)[:, None, None]
+    w = np.where(kz == 0, 1.0, 2.0) * np.ones((1, 2 * kc + 1, 2 * kc + 1))
+    w[0, 0, 0] = 0.0                                   # k = 0 (cube index [0, 0, 0])
+    want = [(w * np.abs(c[0]) ** 2).sum(), (w * (c[0] * np.conj(c[1])).real).sum()]
+    got = (pk.cpu().numpy() * nmv).sum(axis=1) / box ** 3
+    assert np.allclose(got, want, rtol=1e-12, atol=0)
+
+
 @pytest.mark.parametrize("dtype", [g.F64, g.F32])
 @pytest.mark.parametrize("n,box", [(32, 300.0), (48, 450.0)])
 def test_bispectrum_matches_oracle(ctx, dtype, n, box):
