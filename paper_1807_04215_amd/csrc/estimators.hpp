@@ -33,18 +33,21 @@ __device__ __forceinline__ double wave_sum(double v) {
 // kx >= 0, or kx < 0) |n|^2 = kx^2 + ky^2 + kz^2 grows with a = |kx|, so the
 // modes of the half-row inside the bins form one stretch a0 <= a < a1, and
 // bin b holds the part [lo_b, hi_b) of it given by integer square roots of
-// the bin's edges.  A wavefront takes one half-row at a time:
-//  1. lane j takes the j-th bin the half-row meets: its stretch and its
-//     number of pieces P_j = ceil(L_j / s), the piece length s chosen so
-//     that the pieces of a half-row usually fit the 64 lanes;
-//  2. lane p takes piece p, piece i of bin j, made of the modes
-//     lo_j + i + k P_j (k = 0, 1, ...) inside the stretch: the lanes of one
-//     bin read consecutive modes.  It sums the per-mode quantities in FP64
-//     registers with no bin test per mode: the products Re[F_a F_b^*], the
-//     mode count and sum |k|;
+// the bin's edges.  The four half-rows (+ky and -ky; kx >= 0 and kx < 0) of
+// one (|ky|, kz) share ky^2 + kz^2 and the weight w, hence every stretch:
+// they form one work unit (two half-rows when ky = 0).  A wavefront takes one
+// unit at a time:
+//  1. lane j takes the j-th bin the unit meets: its stretch of a >= 1 and its
+//     number of pieces P_j = ceil(L_j / s), s the least piece length for
+//     which the pieces fit the 64 lanes (when fewer than 64 bins are met);
+//  2. lane p takes piece p, piece i of bin j: the modes a = lo_j + i + k P_j
+//     (k = 0, 1, ...) inside the stretch, in each half-row of the unit, so
+//     that the lanes of one bin read consecutive modes of a row.  It sums
+//     the per-mode quantities in FP64 registers with no bin test per mode:
+//     the products Re[F_a F_b^*], the mode count and sum |k|;
 //  3. the pieces' sums go to LDS, and lane j adds those of its bin, in piece
-//     order and times the half-plane weight w, to the wavefront's own
-//     accumulator [bin][q] in LDS.
+//     order and times w, to the wavefront's own accumulator [bin][q] in LDS;
+//     then the kx = 0 modes of the unit's rows, when they lie in the bins.
 // Modes outside the bins (k = 0, the corners of the cube past the last edge)
 // are never read.  The block partials [block][bin][q] are reduced in a fixed
 // order by k_power_reduce: every sum has a fixed order, so the result is
@@ -52,8 +55,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 // (see zptr): gridDim.z realisations in one launch.
 // ---------------------------------------------------------------------------
 constexpr int kPowerPairsPerLaunch = 16;
-constexpr int kPowerWaves = 4;
-static_assert(kPowerWaves % 2 == 0, "the piece table after the FP64 arrays must be 16-byte aligned");
+constexpr int kPowerWaves = 2;
+// Modes of a half-row's stretch staged in LDS at once (six per lane): the
+// staged form serves FP32 fields with all pairs of up to five fields
+// (TRI > 0) when a stretch fits; others load each mode directly.
+constexpr int kPowerStageModes = 384;
 
 template <typename T>
 struct PowerArgs {
@@ -70,10 +76,24 @@ struct BinEdges {
     int nbins;
 };
 
-// LDS bytes of k_power_partial beyond its static edge table: per wavefront
-// the accumulators [nbins][q], the piece sums [64][q] and the piece table.
-__host__ __device__ constexpr size_t power_shm_bytes(int nbins, int nq) {
-    return (size_t)kPowerWaves * (((size_t)nbins + 64) * nq * sizeof(double) + 64 * 4 * sizeof(int));
+// LDS of k_power_partial per wavefront, beyond the block's static edge
+// table: the accumulators [nbins][nq] (FP64), one region holding either the
+// piece sums [64][nq] or a staged stretch (stage_bytes), and the piece table
+// (64 x 16 bytes); each part 16-byte aligned.
+__host__ __device__ constexpr size_t power_align16(size_t b) { return (b + 15) / 16 * 16; }
+__host__ __device__ constexpr size_t power_acc_bytes(int nbins, int nq) {
+    return power_align16((size_t)nbins * nq * sizeof(double));
+}
+__host__ __device__ constexpr size_t power_region_bytes(int nq, size_t stage_bytes) {
+    return power_align16((size_t)64 * nq * sizeof(double) > stage_bytes ? (size_t)64 * nq * sizeof(double)
+                                                                        : stage_bytes);
+}
+__host__ __device__ constexpr size_t power_wave_bytes(int nbins, int nq, size_t stage_bytes) {
+    return power_acc_bytes(nbins, nq) + power_region_bytes(nq, stage_bytes) + 64 * 4 * sizeof(int);
+}
+template <typename T, int TRI>
+__host__ __device__ constexpr size_t power_stage_bytes() {
+    return TRI > 0 && sizeof(T) == 4 ? (size_t)TRI * kPowerStageModes * sizeof(cpx<T>) : 0;
 }
 
 // DPP lane moves (VALU, no LDS traffic): row shift right by S within rows of
@@ -90,6 +110,19 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
     v += __builtin_amdgcn_update_dpp(0, v, kDppRowShr + 8, 0xf, 0xf, false);
     v += __builtin_amdgcn_update_dpp(0, v, kDppBcast15, 0xa, 0xf, false);
     v += __builtin_amdgcn_update_dpp(0, v, kDppBcast31, 0xc, 0xf, false);
+    return v;
+}
+
+// Inclusive running maximum of v over the 64 lanes (lanes without a DPP
+// source take INT_MIN, which changes no maximum).
+__device__ __forceinline__ int wave_incl_max(int v) {
+    constexpr int lo = -0x7fffffff - 1;
+    v = max(v, __builtin_amdgcn_update_dpp(lo, v, kDppRowShr + 1, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(lo, v, kDppRowShr + 2, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(lo, v, kDppRowShr + 4, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(lo, v, kDppRowShr + 8, 0xf, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(lo, v, kDppBcast15, 0xa, 0xf, false));
+    v = max(v, __builtin_amdgcn_update_dpp(lo, v, kDppBcast31, 0xc, 0xf, false));
     return v;
 }
 
@@ -115,6 +148,16 @@ __device__ __forceinline__ int ceil_sqrt(int64_t x, int kc1) {
     if (r * r > n) --r;
     if ((r + 1) * (r + 1) <= n) ++r;
     return r * r < n ? r + 1 : r;
+}
+
+// ceil(len / s) for 0 <= len, 1 <= s < 2^11, with rs = 1 / s in FP32: the float
+// quotient of len + s - 1 is off by at most one and is corrected.
+__device__ __forceinline__ int ceil_div_small(int len, int s, float rs) {
+    const int x = len + s - 1;
+    int q = (int)((float)x * rs);
+    if (q * s > x) --q;
+    if ((q + 1) * s <= x) ++q;
+    return q;
 }
 
 // v & m: the AND is written as an instruction so that it stays one VALU
@@ -143,38 +186,74 @@ __global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T>
     constexpr int NP = TRI > 0 ? TRI * (TRI + 1) / 2 : QP;  // pair sums held per lane
     constexpr int NQ = NP + 2;                               // then the mode count and sum |k|
     constexpr int NF = TRI > 0 ? TRI : 2 * QP;               // values loaded per mode
-    constexpr int G = TRI > 0 ? 2 : 1;                       // modes whose loads are issued together
+    constexpr int H = TRI == 0 ? 1 : (sizeof(T) == 4 ? 4 : 2);  // direct form: half-rows loaded together
+    constexpr bool STAGED = power_stage_bytes<T, TRI>() > 0;
+    constexpr int W = kPowerStageModes, WL = W / 64;
     extern __shared__ double smem[];
     __shared__ int64_t edge[kMaxBins + 1];
     // pair sums per mode (TRI > 0: all NP of them), quantities per bin
     const int npairs = TRI > 0 ? NP : a.npairs, Q = npairs + 2, nb = be.nbins;
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / 64), lane = threadIdx.x % 64;
-    for (int i = threadIdx.x; i < kPowerWaves * nb * Q; i += blockDim.x) smem[i] = 0.0;
+    const size_t wave_bytes = power_wave_bytes(nb, Q, power_stage_bytes<T, TRI>());
+    auto acc_of = [&](int wv) { return reinterpret_cast<double*>(reinterpret_cast<char*>(smem) + wv * wave_bytes); };
+    for (int i = threadIdx.x; i < kPowerWaves * nb * Q; i += blockDim.x) acc_of(i / (nb * Q))[i % (nb * Q)] = 0.0;
     for (int i = threadIdx.x; i <= nb; i += blockDim.x) edge[i] = be.e[i];
     __syncthreads();
-    double* acc = smem + (size_t)wave * nb * Q;                                    // [nbins][Q]
-    double* stage = smem + (size_t)kPowerWaves * nb * Q + (size_t)wave * 64 * Q;  // [64][Q]
-    int4* piece = reinterpret_cast<int4*>(smem + (size_t)kPowerWaves * (nb + 64) * Q) + wave * 64;
+    double* acc = acc_of(wave);  // [nbins][Q]
+    char* region = reinterpret_cast<char*>(acc) + power_acc_bytes(nb, Q);
+    double* stage = reinterpret_cast<double*>(region);  // [64][Q] piece sums
+    cpx<T>* buf = reinterpret_cast<cpx<T>*>(region);    // [NF][W] a staged stretch
+    int4* piece = reinterpret_cast<int4*>(region + power_region_bytes(Q, power_stage_bytes<T, TRI>()));
     // the launch's field of load slot i (TRI > 0: field i; else pair i / 2, side i % 2)
     auto field = [&](int i) -> const cpx<T>* {
         if constexpr (TRI > 0) return zptr(a.f[i], zs);
         else return zptr(a.f[(i & 1) ? a.pb[i >> 1] : a.pa[i >> 1]], zs);
     };
+    // the unweighted products of one mode (values x) added to v; MASK: x & m
+    auto add_mode = [&](auto mask_tag, const cpx<T>(&x)[NF], unsigned m, double(&v)[NQ]) {
+        constexpr bool MASK = decltype(mask_tag)::value;
+        auto cv = [&](T t) -> double { return (double)(MASK ? and_bits(t, m) : t); };
+        if constexpr (TRI > 0) {
+            double re[TRI], im[TRI];
+#pragma unroll
+            for (int i = 0; i < TRI; ++i) {
+                re[i] = cv(x[i].x);
+                im[i] = cv(x[i].y);
+            }
+#pragma unroll
+            for (int i = 0; i < TRI; ++i)
+#pragma unroll
+                for (int i2 = i; i2 < TRI; ++i2) {
+                    double& t = v[tri_index(i, i2, TRI)];
+                    t = fma(re[i], re[i2], t);
+                    t = fma(im[i], im[i2], t);
+                }
+        } else {
+#pragma unroll
+            for (int q = 0; q < QP; ++q) {
+                if (q < npairs) {
+                    v[q] = fma(cv(x[2 * q].x), cv(x[2 * q + 1].x), v[q]);
+                    v[q] = fma(cv(x[2 * q].y), cv(x[2 * q + 1].y), v[q]);
+                }
+            }
+        }
+    };
     const int Kc = cd.Kc, Kx = cd.Ky, kc1 = cd.Kc + 1;
-    const int nhalf = 2 * cd.Kz * cd.Ky;  // < 2^31 for every cube the library accepts
+    const int nunit = kc1 * kc1;  // (|ky|, kz)
     const int gw = blockIdx.x * kPowerWaves + wave, nw = gridDim.x * kPowerWaves;
-    for (int hr = gw; hr < nhalf; hr += nw) {
-        // everything of the half-row is uniform over the wavefront
-        const int rowi = hr >> 1, half = hr & 1;
-        const int kz = rowi / cd.Ky, kyc = rowi - kz * cd.Ky;
-        const int ky = kyc <= Kc ? kyc : kyc - cd.Ky;
+    for (int uu = gw; uu < nunit; uu += nw) {
+        // everything of the unit is uniform over the wavefront
+        const int u = __builtin_amdgcn_readfirstlane(uu);
+        const int kz = u / kc1, ky = u - kz * kc1;  // ky = |ky|
         const int c2 = ky * ky + kz * kz;
-        // the modes in the bins: a0 <= a < a1, a = |kx| (a >= 1 for kx < 0)
-        const int a0 = __builtin_amdgcn_readfirstlane(max(half, ceil_sqrt(edge[0] - c2, kc1)));
+        // the modes in the bins: a0 <= a < a1, a = |kx|
+        const int a0 = __builtin_amdgcn_readfirstlane(ceil_sqrt(edge[0] - c2, kc1));
         const int a1 = __builtin_amdgcn_readfirstlane(ceil_sqrt(edge[nb] - c2, kc1));
         if (a0 >= a1) continue;
         const double w = kz == 0 ? 1.0 : 2.0;
-        const int L = a1 - a0;
+        const int nrow = ky > 0 ? 2 : 1, nh = 2 * nrow;  // rows +ky, -ky; their half-rows
+        const int rowp = kz * cd.Ky + ky, rowm = kz * cd.Ky + (ky > 0 ? cd.Ky - ky : 0);
+        const int s1 = max(1, a0), L = max(0, a1 - s1);  // the pieces cover a >= 1 in every half-row
         // bins of the first and the last mode: the number of upper edges at or below their |n|^2
         const int64_t n2f = (int64_t)a0 * a0 + c2, n2l = (int64_t)(a1 - 1) * (a1 - 1) + c2;
         int bf = 0, bl = 0;
@@ -184,32 +263,34 @@ __global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T>
             bf += __popcll(__ballot(up <= n2f));
             bl += __popcll(__ballot(up <= n2l));
         }
-        const int nbr = bl - bf + 1;  // bins the half-row meets (some may hold no mode)
-        // piece length: the pieces fit the lanes when fewer than 64 bins are met,
-        // and stay within about twice the length of an even split of the stretch
-        const int even = (L + 63) / 64;
-        const int s = nbr < 64 ? max(1, min((L + 63 - nbr) / (64 - nbr), 2 * even + 2)) : even;
-        const float rs = 1.0f / (float)s;
-        const cpx<T>* row[NF];
-#pragma unroll
-        for (int i = 0; i < NF; ++i)
-            if (TRI > 0 || i < 2 * npairs) row[i] = field(i) + (size_t)rowi * Kx;
+        const int nbr = bl - bf + 1;  // bins the unit meets (some may hold no mode)
+        const bool staged = L <= W;   // the stretch fits the LDS window
         for (int g0 = 0; g0 < nbr; g0 += 64) {
-            // lane j: bin b = bf + g0 + j, its stretch [lo, hi) and its np pieces
+            // lane j: bin b = bf + g0 + j, its stretch [lo, hi) of a >= s1
             const int j = g0 + lane, b = bf + j;
             int lo = 0, hi = 0;
             if (j < nbr) {
-                lo = max(a0, ceil_sqrt(edge[b] - c2, kc1));
+                lo = max(s1, ceil_sqrt(edge[b] - c2, kc1));
                 hi = min(a1, ceil_sqrt(edge[b + 1] - c2, kc1));
             }
             const int len = max(0, hi - lo);
-            const int x = len + s - 1;  // np = floor(x / s): the float quotient is off by at most one
-            int np = (int)((float)x * rs);
-            if (np * s > x) --np;
-            if ((np + 1) * s <= x) ++np;
+            // piece length s: the least for which the group's pieces fit 64 lanes, searched
+            // between an even split of the stretch and a length that fits (or about twice
+            // the even split, the most allowed: then the pieces take several rounds)
+            const int ng = min(64, nbr - g0);
+            const int even = max(1, (L + 63) / 64);
+            int slo = even, shi = ng < 64 ? max(even, min((L + 63 - ng) / (64 - ng), 2 * even + 2)) : even;
+            while (slo < shi) {
+                const int mid = (slo + shi) >> 1;
+                const int t = __builtin_amdgcn_readlane(wave_incl_scan(ceil_div_small(len, mid, 1.0f / (float)mid)), 63);
+                if (t <= 64) shi = mid;
+                else slo = mid + 1;
+            }
+            const int s = slo;
+            const int np = ceil_div_small(len, s, 1.0f / (float)s);
             const int incl = wave_incl_scan(np);
-            const int off = incl - np;                               // first piece of bin j
-            const int npc = __builtin_amdgcn_readlane(incl, 63);     // pieces of this group of bins
+            const int off = incl - np;                            // first piece of bin j
+            const int npc = __builtin_amdgcn_readlane(incl, 63);  // pieces of this group of bins
             for (int r0 = 0; r0 < npc; r0 += 64) {
                 // bin lanes: the table entry of each of their pieces in this round
                 const int t0 = max(off, r0), t1 = min(off + np, r0 + 64);
@@ -217,57 +298,107 @@ __global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T>
                 wave_sync();
                 // piece lanes: modes d.x + k d.y < d.z; a lane past the last piece has none
                 const bool act = r0 + lane < npc;
-                const int4 d = act ? piece[lane] : make_int4(a0, 1, a0, 0);
+                const int4 d = act ? piece[lane] : make_int4(s1, 1, s1, 0);
                 double v[NQ];
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) v[q] = 0.0;
-                for (int k = 0; __ballot(d.x + k * d.y < d.z); k += G) {
-                    int am[G];
-                    unsigned mk[G];  // all ones for a mode of the piece, else 0
-#pragma unroll
-                    for (int gg = 0; gg < G; ++gg) {
-                        const int m = d.x + (k + gg) * d.y;
-                        mk[gg] = m < d.z ? 0xffffffffu : 0u;
-                        am[gg] = m < d.z ? m : a0;  // a mode of the stretch: the load stays in the row
-                    }
-                    cpx<T> xs[G][NF];
-#pragma unroll
-                    for (int gg = 0; gg < G; ++gg) {
-                        const uint32_t o = (uint32_t)(half ? Kx - am[gg] : am[gg]);
+                // mode k of every piece lane: MASK when some piece lane has no mode k
+                auto trip = [&](auto mask_tag, int k) {
+                    constexpr bool MASK = decltype(mask_tag)::value;
+                    const int m = d.x + k * d.y;
+                    const bool ok = m < d.z;
+                    const int am = ok ? m : s1;  // a mode of the stretch: the loads stay in their rows
+                    const unsigned mk = ok ? 0xffffffffu : 0u;
+                    // the unit's half-rows h = 2 r + half (row r: +ky, -ky), H at a time
+                    auto load = [&](int h, cpx<T>(&x)[NF]) {
+                        const int row = (h >> 1) && h < nh ? rowm : rowp;  // h >= nh (ky = 0): row +ky again
+                        const uint32_t o = (uint32_t)((h & 1) ? Kx - am : am);
 #pragma unroll
                         for (int i = 0; i < NF; ++i)
-                            if (TRI > 0 || i < 2 * npairs) xs[gg][i] = ldo(row[i], o);  // uniform guard
-                    }
-                    // a mode past the piece adds zeros (its values masked to +0)
-#pragma unroll
-                    for (int gg = 0; gg < G; ++gg) {
-                        double re[NF], im[NF];
-#pragma unroll
-                        for (int i = 0; i < NF; ++i) {
-                            re[i] = (double)and_bits(xs[gg][i].x, mk[gg]);
-                            im[i] = (double)and_bits(xs[gg][i].y, mk[gg]);
+                            if (TRI > 0 || i < 2 * npairs) x[i] = ldo(field(i) + (size_t)row * Kx, o);
+                    };
+                    if constexpr (H == 1) {
+#pragma unroll 1
+                        for (int h = 0; h < nh; ++h) {
+                            cpx<T> x[NF];
+                            load(h, x);
+                            add_mode(mask_tag, x, mk, v);
                         }
-                        if constexpr (TRI > 0) {
+                    } else {
 #pragma unroll
-                            for (int i = 0; i < TRI; ++i)
+                        for (int hb = 0; hb < 4; hb += H) {
+                            if (hb >= nh) break;  // uniform
+                            cpx<T> xs[H][NF];
 #pragma unroll
-                                for (int i2 = i; i2 < TRI; ++i2) {
-                                    double& t = v[tri_index(i, i2, TRI)];
-                                    t = fma(re[i], re[i2], t);
-                                    t = fma(im[i], im[i2], t);
-                                }
-                        } else {
+                            for (int hh = 0; hh < H; ++hh) load(hb + hh, xs[hh]);
 #pragma unroll
-                            for (int q = 0; q < QP; ++q) {
-                                if (q < npairs) {
-                                    v[q] = fma(re[2 * q], re[2 * q + 1], v[q]);
-                                    v[q] = fma(im[2 * q], im[2 * q + 1], v[q]);
-                                }
+                            for (int hh = 0; hh < H; ++hh)
+                                if (hb + hh < nh) add_mode(mask_tag, xs[hh], mk, v);
+                        }
+                    }
+                    const double cnt = nh, ks = a.kF * nh;
+                    v[NP] += MASK ? and_bits(cnt, mk) : cnt;
+                    v[NP + 1] = fma(MASK ? and_bits(ks, mk) : ks, root_of_int(am * am + c2), v[NP + 1]);
+                };
+                // modes per piece: every piece lane has the first kmin, some have up to kmax
+                const int cnt = act ? ceil_div_small(d.z - d.x, d.y, 1.0f / (float)d.y) : 0;
+                const int kmax = __builtin_amdgcn_readlane(wave_incl_max(cnt), 63);
+                const int kmin = __builtin_amdgcn_readlane(wave_incl_max(act ? -cnt : -kmax), 63) * -1;
+                if (STAGED && staged) {
+                    // half-row by half-row: its stretch [s1, a1) (positions c0 .. c0 + L - 1 of the
+                    // row, ascending) is read with coalesced loads into LDS, the next half-row's
+                    // loads in flight while the pieces of this one read theirs from LDS
+                    cpx<T> xs[WL][NF];
+                    auto issue = [&](int h) {
+                        const int row = (h >> 1) ? rowm : rowp;
+                        const int c0 = (h & 1) ? Kx - (a1 - 1) : s1;
+#pragma unroll
+                        for (int t = 0; t < WL; ++t) {
+                            if (t * 64 < L) {  // uniform
+                                const uint32_t o = (uint32_t)(c0 + min(t * 64 + lane, L - 1));
+#pragma unroll
+                                for (int i = 0; i < NF; ++i) xs[t][i] = ldo(field(i) + (size_t)row * Kx, o);
                             }
                         }
-                        v[NP] += and_bits(1.0, mk[gg]);
-                        v[NP + 1] = fma(and_bits(a.kF, mk[gg]), root_of_int(am[gg] * am[gg] + c2), v[NP + 1]);
+                    };
+                    issue(0);
+                    for (int h = 0; h < nh; ++h) {
+                        wave_sync();  // the previous half-row's reads of buf are done
+#pragma unroll
+                        for (int t = 0; t < WL; ++t)
+                            if (t * 64 < L)
+#pragma unroll
+                                for (int i = 0; i < NF; ++i) buf[i * W + t * 64 + lane] = xs[t][i];
+                        wave_sync();
+                        if (h + 1 < nh) issue(h + 1);
+                        // mode a of this half-row sits at LDS index a - s1 (kx >= 0) or a1 - 1 - a
+                        const bool neg = h & 1, first = h == 0;
+                        auto trip_lds = [&](auto mask_tag, int k) {
+                            constexpr bool MASK = decltype(mask_tag)::value;
+                            const int m = d.x + k * d.y;
+                            const bool ok = m < d.z;
+                            const int am = ok ? m : s1;
+                            const unsigned mk = ok ? 0xffffffffu : 0u;
+                            const int idx = neg ? a1 - 1 - am : am - s1;
+                            cpx<T> x[NF];
+#pragma unroll
+                            for (int i = 0; i < NF; ++i) x[i] = buf[i * W + idx];
+                            add_mode(mask_tag, x, mk, v);
+                            if (first) {  // the count and sum |k| of all nh half-rows
+                                const double cnt = nh, ks = a.kF * nh;
+                                v[NP] += MASK ? and_bits(cnt, mk) : cnt;
+                                v[NP + 1] = fma(MASK ? and_bits(ks, mk) : ks, root_of_int(am * am + c2), v[NP + 1]);
+                            }
+                        };
+                        int k = 0;
+                        for (; k < kmin; ++k) trip_lds(std::false_type{}, k);
+                        for (; k < kmax; ++k) trip_lds(std::true_type{}, k);
                     }
+                    wave_sync();  // buf is read before the piece sums take its place
+                } else {
+                    int k = 0;
+                    for (; k < kmin; ++k) trip(std::false_type{}, k);
+                    for (; k < kmax; ++k) trip(std::true_type{}, k);
                 }
                 if (act) {
                     double* dst = stage + lane * Q;
@@ -297,12 +428,34 @@ __global__ __launch_bounds__(64 * kPowerWaves) void k_power_partial(PowerArgs<T>
                 wave_sync();
             }
         }
+        // the kx = 0 mode of each row (one half-row holds it), in bin bf when a0 = 0
+        if (a0 == 0 && lane == 0) {
+            double z[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) z[q] = 0.0;
+            for (int r = 0; r < nrow; ++r) {
+                cpx<T> x[NF];
+#pragma unroll
+                for (int i = 0; i < NF; ++i)
+                    if (TRI > 0 || i < 2 * npairs) x[i] = field(i)[(size_t)(r ? rowm : rowp) * Kx];
+                add_mode(std::false_type{}, x, 0u, z);
+            }
+            z[NP] = (double)nrow;
+            z[NP + 1] = a.kF * nrow * root_of_int(c2);
+            double* dst = acc + (size_t)bf * Q;
+#pragma unroll
+            for (int q = 0; q < NP; ++q)
+                if (q < npairs) dst[q] += w * z[q];
+            dst[npairs] += w * z[NP];
+            dst[npairs + 1] += w * z[NP + 1];
+        }
+        wave_sync();
     }
     __syncthreads();
     double* out = zptr(a.partial, zs) + (size_t)blockIdx.x * nb * Q;
     for (int i = threadIdx.x; i < nb * Q; i += blockDim.x) {
         double sum = 0.0;
-        for (int wv = 0; wv < kPowerWaves; ++wv) sum += smem[(size_t)wv * nb * Q + i];
+        for (int wv = 0; wv < kPowerWaves; ++wv) sum += acc_of(wv)[i];
         out[i] = sum;
     }
 }

@@ -144,22 +144,22 @@ int power_enqueue(gridspt_ctx* c, const gridspt_grid* g, const void* const* fiel
             a.kF = 2.0 * M_PI / g->box;
             a.partial = partial;
             const int nq = nacc + 2;
-            const size_t shm = power_shm_bytes(nbins, nq);
             const CubeDims cdims{(int)d.Kc, (int)d.Kz, (int)d.Ky};
             const dim3 pblock(64 * kPowerWaves);
             const double pbytes = (double)nz * nf * nread * d.cpx_bytes;
             int used = nblk;  // blocks of this launch (<= nblk, the partials' capacity)
-            auto go = [&](auto kern) {
+            auto go = [&](auto kern, size_t stage_bytes) {
+                const size_t shm = (size_t)kPowerWaves * power_wave_bytes(nbins, nq, stage_bytes);
                 used = power_launch_blocks(d, kern, shm, nz);
                 return launch(c, KD_POWER, pbytes, dim3(used, 1, nz), pblock, shm, kern, a, be, cdims, bt.zs);
             };
             switch (tri) {
-                case 1: CHECK(go(k_power_partial<T, 1>)); break;
-                case 2: CHECK(go(k_power_partial<T, 2>)); break;
-                case 3: CHECK(go(k_power_partial<T, 3>)); break;
-                case 4: CHECK(go(k_power_partial<T, 4>)); break;
-                case 5: CHECK(go(k_power_partial<T, 5>)); break;
-                default: CHECK(go(k_power_partial<T, 0>));
+                case 1: CHECK(go(k_power_partial<T, 1>, power_stage_bytes<T, 1>())); break;
+                case 2: CHECK(go(k_power_partial<T, 2>, power_stage_bytes<T, 2>())); break;
+                case 3: CHECK(go(k_power_partial<T, 3>, power_stage_bytes<T, 3>())); break;
+                case 4: CHECK(go(k_power_partial<T, 4>, power_stage_bytes<T, 4>())); break;
+                case 5: CHECK(go(k_power_partial<T, 5>, power_stage_bytes<T, 5>())); break;
+                default: CHECK(go(k_power_partial<T, 0>, power_stage_bytes<T, 0>()));
             }
             CHECK(launch(c, KD_POWER_FINAL, (double)nz * used * nbins * nq * 8.0, dim3(nbins * nq, 1, nz),
                          dim3(kReduceThreads), 0, k_power_reduce, (const double*)partial, used, sums, bt.zs));
