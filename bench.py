@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -367,6 +368,61 @@ def adjoint_bench(args) -> int:
     return 0
 
 
+def cut_sweep(args) -> int:
+    """App. A: sensitivity to the high-k cutoff on the paper's grid (512^3,
+    L = 1000 Mpc/h, z = 1).  For one sharp-k cut on every order, k_cut in
+    {0.8, 1.0, 1.2, 4/3, 1.5, 1.6} h/Mpc, and for the default pair (1 and 4/3),
+    the P-form (printed sources) and the D-form run on the same seeded linear
+    field (FP32).  Reported per setup: the relative L2 of P - D of delta_n
+    (the aliased terms), and the two-loop delta spectrum
+    P11 + P22 + 2 P13 + P33 + 2 P24 + 2 P15 of the P-form in the lowest bins,
+    relative to the default setup.  Not a timed benchmark."""
+    import torch
+
+    import paper_1807_04215_amd as g
+
+    n, box, nmax = 512, 1000.0, 5
+    dz = g.growth(0.279, 0.721, 1.0)
+    setups = [("default 1, 4/3", 1.0, 4.0 / 3.0)] + [("%.3g" % k, k, k) for k in (0.8, 1.0, 1.2, 4.0 / 3.0, 1.5, 1.6)]
+    kmax_bins = 0.5                                   # h/Mpc
+    nb = 20
+    n_kmax = int(kmax_bins * box / (2.0 * math.pi))  # bins on [0, about 0.5 h/Mpc]
+    ctx = g.Context()
+    pairs = [(0, 0), (1, 1), (0, 2), (2, 2), (1, 3), (0, 4)]
+    coef = [1.0, 1.0, 2.0, 1.0, 2.0, 2.0]
+    res = {}
+    ref = None
+    for name, k1, k2 in setups:
+        cut1, cut2 = g.cut_n2max(n, box, k1), g.cut_n2max(n, box, k2)
+        grid = g.Grid(n, box, g.cube_kc(max(cut1, cut2)), g.F32)
+        lp = g.LinearSpectrum(amp=g.sigma8_amp(0.8, 0.96, 0.21), ns=0.96, gamma=0.21, growth=dz, n2max=cut1, seed=6)
+        d1 = g.linear_field(ctx, grid, lp)
+        pf = g.orders_pform(ctx, grid, nmax, cut1, cut2, d1)
+        df = g.orders(ctx, grid, nmax, cut1, cut2, d1, spectra=False)
+        edges = g.linear_edges(nb, n_kmax, 1, cut2)
+        pk, km, nm = g.power(ctx, grid, pf.delta_k, pairs, edges)
+        torch.cuda.synchronize()
+        pd = []
+        for i in range(nmax):
+            a, b = pf.delta[i].double(), df.delta[i].double()
+            pd.append(float((torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item()))
+            del a, b
+        p2 = sum(c * pk[i] for i, c in enumerate(coef)).cpu().numpy()
+        if ref is None:
+            ref = p2
+        res[name] = {"n2max": [int(cut1), int(cut2)], "p_minus_d_rel_l2_delta": ["%.3e" % e for e in pd],
+                     "p2loop_over_default_bins_0_to_7": ["%.4f" % (p2[b] / ref[b]) for b in range(8)]}
+        print("cut %-16s P-D %s  P2loop/default %s" % (name, res[name]["p_minus_d_rel_l2_delta"],
+                                                     res[name]["p2loop_over_default_bins_0_to_7"]), file=sys.stderr,
+              flush=True)
+        del pf, df, d1
+        torch.cuda.empty_cache()
+    kmean = km.cpu().numpy()[:8]
+    print(json.dumps({"cut_sweep": res, "grid": "512^3, L = 1000 Mpc/h, z = 1, seed 6, FP32",
+                      "bins_kmean_h_per_mpc": ["%.4f" % k for k in kmean]}), flush=True)
+    return 0
+
+
 def pform_bench(args) -> int:
     """C6: the paper-literal P-form on the paper's own grid and cuts: 512^3,
     L = 1000 Mpc/h, z = 0, k_cut = 1 h/Mpc for the linear field and 4/3 h/Mpc for
@@ -538,6 +594,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-spectra", action="store_true", help="skip the spectrum stores and P(k)")
     ap.add_argument("--kernels", action="store_true", help="also print the per-kernel table to stderr")
+    ap.add_argument("--cut-sweep", action="store_true",
+                    help="App. A: P - D and the two-loop P(k) for several sharp-k cuts on 512^3 (not timed)")
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the FP64 leg (its rate and the FP32 errors against it) after the timed FP32 steps")
     ap.add_argument("--copy-probe", action="store_true",
@@ -567,6 +625,8 @@ def main() -> int:
         return batch_bench(args)
     if args.workload == "c5":
         return adjoint_bench(args)
+    if args.cut_sweep:
+        return cut_sweep(args)
     if args.workload == "c6":
         return pform_bench(args)
     if args.workload == "c7":
