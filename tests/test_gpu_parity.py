@@ -296,18 +296,21 @@ def test_bispectrum_matches_oracle(ctx, dtype, n, box):
 @pytest.mark.parametrize("dtype", [g.F64, g.F32])
 def test_sum_orders(ctx, dtype):
     """The FP64 sum of orders in both instantiations (FP32 fields are what the
-    benchmark sums): against the oracle's sum of the very fields the kernel was
-    given, and, through the whole path, against the oracle's FP64 fields."""
+    benchmark sums): the oracle's fields, rounded to the grid's precision and
+    uploaded, against the oracle's sum of the same values; and, through the
+    whole path, the sum of the GPU's orders against the oracle's FP64 fields."""
     n, box = 64, 500.0
     grid, out, (rd, _, _, _) = _orders_case(ctx, dtype, n, box, 5, 8)
     coef = [0.9 ** (i + 1) for i in range(5)]
-    s = g.sum_orders(ctx, grid, out.delta, coef)
+    host = [_rounded(np.ascontiguousarray(r), grid) for r in rd]
+    given = g.sum_orders(ctx, grid, [_to_dev(h, grid) for h in host], coef)
+    whole = g.sum_orders(ctx, grid, out.delta, coef)
     ctx.sync()
-    got = s.cpu().numpy()
-    own = oracle.sum_orders(np.stack([d.cpu().numpy().astype(np.float64) for d in out.delta]), coef)
+    got = given.cpu().numpy()
+    own = oracle.sum_orders(np.stack(host), coef)
     assert rel_l2(got, own) < 1e-15
     assert np.abs(got - own).max() <= 4e-16 * np.abs(own).max() * 5
-    assert rel_l2(got, oracle.sum_orders(rd, coef)) < TOL[dtype]
+    assert rel_l2(whole.cpu().numpy(), oracle.sum_orders(rd, coef)) < TOL[dtype]
 
 
 def test_zeldovich_planar_on_gpu(ctx):
