@@ -599,7 +599,7 @@ def main() -> int:
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the FP64 leg (its rate and the FP32 errors against it) after the timed FP32 steps")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="one 4 GiB device-to-device copy (calibrates HBM byte counters), then exit")
+                    help="a 4 GiB fill, copy and sum (calibrate the HBM byte counters), then exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -613,13 +613,17 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     if args.copy_probe:
+        # kernels of known HBM traffic, in this order: a fill (writes 4 GiB), a copy
+        # (reads and writes 4 GiB), a sum (reads 4 GiB, writes one value)
         a = torch.empty(1 << 30, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         a.fill_(1.0)
         torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_read": 4 << 30, "copy_probe_bytes_written": 4 << 30}))
+        total = float(b.sum().item())
+        print(json.dumps({"copy_probe_bytes_read": 4 << 30, "copy_probe_bytes_written": 4 << 30,
+                          "fill_bytes_written": 4 << 30, "sum_bytes_read": 4 << 30, "sum": total}))
         return 0
     if args.workload == "c4":
         return batch_bench(args)
