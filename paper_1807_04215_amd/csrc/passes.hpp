@@ -115,6 +115,19 @@ __device__ __forceinline__ int pos_to_compact(int p, int Kc, int n) {
 // pair r / 2 and the cosine (r even) or sine (r odd) branch.  The transform
 // runs in the precision T of the field (an FP32 field needs no FP64 logarithm).
 // --------------------------------------------------------------------------
+// Full 128-bit product a m, high and low halves, from the four 32 x 32 -> 64-bit
+// partial products (a = a1 2^32 + a0, m likewise); the low half is assembled from
+// the same partials rather than multiplied out again.
+__device__ __forceinline__ void mul_hilo64(uint64_t a, uint64_t m, uint64_t& lo, uint64_t& hi) {
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), m0 = (uint32_t)m, m1 = (uint32_t)(m >> 32);
+    const uint64_t p00 = (uint64_t)a0 * m0;
+    const uint64_t t = (uint64_t)a0 * m1 + (p00 >> 32);  // < 2^64: (2^32 - 1)^2 + 2^32 - 1
+    const uint64_t u = (uint64_t)a1 * m0 + (uint32_t)t;
+    const uint64_t v = (uint64_t)a1 * m1 + (t >> 32);
+    hi = v + (u >> 32);
+    lo = (u << 32) | (uint32_t)p00;
+}
+
 template <typename T>
 __device__ __forceinline__ void group_gaussians(uint64_t seed, uint64_t stream, uint64_t q, T (&g)[4]) {
     uint64_t c0 = q, c1 = stream, c2 = 0, c3 = 0;
@@ -125,8 +138,9 @@ __device__ __forceinline__ void group_gaussians(uint64_t seed, uint64_t stream, 
             k0 += 0x9E3779B97F4A7C15ull;
             k1 += 0xBB67AE8584CAA73Bull;
         }
-        const uint64_t lo0 = 0xD2E7470EE14C6C93ull * c0, hi0 = __umul64hi(0xD2E7470EE14C6C93ull, c0);
-        const uint64_t lo1 = 0xCA5A826395121157ull * c2, hi1 = __umul64hi(0xCA5A826395121157ull, c2);
+        uint64_t lo0, hi0, lo1, hi1;
+        mul_hilo64(c0, 0xD2E7470EE14C6C93ull, lo0, hi0);
+        mul_hilo64(c2, 0xCA5A826395121157ull, lo1, hi1);
         const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
         c1 = lo1;
