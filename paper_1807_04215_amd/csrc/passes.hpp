@@ -128,6 +128,14 @@ __device__ __forceinline__ void mul_hilo64(uint64_t a, uint64_t m, uint64_t& lo,
     lo = (u << 32) | (uint32_t)p00;
 }
 
+// a ^ b ^ c in one three-input bitwise operation per 32-bit half (truth table 0x96)
+__device__ __forceinline__ uint64_t xor3_64(uint64_t a, uint64_t b, uint64_t c) {
+    const uint32_t lo = __builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, (uint32_t)c, 0x96);
+    const uint32_t hi =
+        __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32), 0x96);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 template <typename T>
 __device__ __forceinline__ void group_gaussians(uint64_t seed, uint64_t stream, uint64_t q, T (&g)[4]) {
     uint64_t c0 = q, c1 = stream, c2 = 0, c3 = 0;
@@ -141,7 +149,7 @@ __device__ __forceinline__ void group_gaussians(uint64_t seed, uint64_t stream, 
         uint64_t lo0, hi0, lo1, hi1;
         mul_hilo64(c0, 0xD2E7470EE14C6C93ull, lo0, hi0);
         mul_hilo64(c2, 0xCA5A826395121157ull, lo1, hi1);
-        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        const uint64_t n0 = xor3_64(hi1, c1, k0), n2 = xor3_64(hi0, c3, k1);
         c0 = n0;
         c1 = lo1;
         c2 = n2;
