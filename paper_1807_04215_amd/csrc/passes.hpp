@@ -17,6 +17,7 @@
 //   S1 [x][kz/TZ][y][kz%TZ]           after the z pass        (Kz = Kc + 1)
 //                    N  x Kz x N, in tiles of TZ kz (the last tile narrower)
 //   S2 [kz][x][ky]   Kz x N  x Ky     after the y pass        (Ky = 2Kc + 1)
+//                    rows s2_row apart (Ky rounded up to a multiple of 16)
 //   S3 [kz][ky][x]   Kz x Ky x N      after the fused x pass
 //   S4 [x][kz][y]    N  x Kz x N      after the inverse y pass
 //   cube [kz][ky][kx] Kz x Ky x Kx    the spectra handed to the caller
@@ -593,7 +594,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_zchain(Produ
 // --------------------------------------------------------------------------
 // P2: y pass, forward.  Rows (x, kz) along y of S1; block = RPB consecutive
 // kz at one x (one S1 tile); grid.y = j takes input field j in_step to output
-// field j out_step.  Keeps |ky| <= Kc and writes S2 rows (kz, x) of Ky values.
+// field j out_step.  Keeps |ky| <= Kc and writes S2 rows (kz, x) of Ky values
+// (s2_row apart).
 // COMB (the products of an order, one launch with grid.y = 1; the steps are
 // unused): output field 1 is D = i (ky V_y + kz V_z) from inputs V_y, V_z (fields 1, 2).
 // i k.V is linear, so its y and z terms are summed here and the x pass needs one
@@ -602,7 +604,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_zchain(Produ
 template <typename T, int N, int V, bool COMB = false>
 __global__ __launch_bounds__(((COMB ? 2 : 1) * Rows<T, N, V>::THREADS)) void k_yfwd(
     const cpx<T>* __restrict__ s1, size_t s1_field, cpx<T>* __restrict__ s2, size_t s2_field,
-    const cpx<T>* __restrict__ tw, CubeDims cd, size_t zs, int in_step, int out_step) {
+    const cpx<T>* __restrict__ tw, CubeDims cd, size_t zs, int in_step, int out_step, int s2_row) {
     using RW = Rows<T, N, V>;
     using PL = typename RW::PL;
     constexpr int P = RW::P, RPB = RW::RPB, ROWE = RW::ROWE, E = RW::E;
@@ -663,13 +665,13 @@ __global__ __launch_bounds__(((COMB ? 2 : 1) * Rows<T, N, V>::THREADS)) void k_y
             v[e] = cmul_i(cpx<T>{ky * v[e].x + kz * vz.x, ky * v[e].y + kz * vz.y});
         }
     }
-    // S2 row (kz0 + r, x): the kept ky in compact order
+    // S2 row (kz0 + r, x): the kept ky in compact order, rows s2_row >= Ky apart
     if (r < nrows) {
-        cpx<T>* out = s2 + (size_t)fout * s2_field + ((size_t)kz0 * N + x) * cd.Ky;
+        cpx<T>* out = s2 + (size_t)fout * s2_field + ((size_t)kz0 * N + x) * s2_row;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int ic = pos_to_compact(l + P * e, cd.Kc, N);
-            if (ic >= 0) sto(out, (uint32_t)(r * N * cd.Ky + ic), v[e]);
+            if (ic >= 0) sto(out, (uint32_t)(r * N * s2_row + ic), v[e]);
         }
     }
 }
@@ -697,6 +699,7 @@ template <typename T>
 struct XArgs {
     const cpx<T>* s2;
     size_t s2_field;
+    int s2_row;  // S2 row stride (complex elements, >= Ky)
     cpx<T>* s3;
     size_t s3_field;
     cpx<T>* cube_d;  // may be null
@@ -786,7 +789,7 @@ __attribute__((amdgpu_waves_per_eu(
     // loaded before field f is transformed, so their latency hides behind it (not in
     // the reverse mode, whose k-space accumulation leaves no registers for them).
     auto gather_field = [&](int f, cpx<T>(&gf)[E]) {
-        gather_runs<T, N, V>(gf, a.s2 + (size_t)f * a.s2_field + (size_t)kz * N * cd.Ky + ky0, (uint32_t)cd.Ky, N,
+        gather_runs<T, N, V>(gf, a.s2 + (size_t)f * a.s2_field + (size_t)kz * N * a.s2_row + ky0, (uint32_t)a.s2_row, N,
                              nrows);
     };
     cpx<T> g[E];

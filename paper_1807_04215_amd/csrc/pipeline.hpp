@@ -196,7 +196,7 @@ struct Pipe {
             return launch(c, KD_YFWD, bytes, dim3((unsigned)(N * ((d.Kz + RW::RPB - 1) / RW::RPB)), nf, nz()),
                           dim3(RW::THREADS), 0,
                           k_yfwd<T, N, V>, (const cpx<T>*)A(), (size_t)L.a_field_s1, B(), (size_t)L.b_field_s2,
-                          (const cpx<T>*)tw(), cd, bt.zs, 1, 1);
+                          (const cpx<T>*)tw(), cd, bt.zs, 1, 1, (int)d.s2_row());
         });
     }
 
@@ -210,10 +210,10 @@ struct Pipe {
             const dim3 grid((unsigned)(N * ((d.Kz + RW::RPB - 1) / RW::RPB)), 2, nz()), block(RW::THREADS);
             GRIDSPT_CHECK(launch(c, KD_YFWD, nb() * 2.0 * (d.s1() + d.s2()) * d.cpx_bytes, grid, block, 0,
                                  k_yfwd<T, N, V>, (const cpx<T>*)A(), (size_t)L.a_field_s1, B(),
-                                 (size_t)L.b_field_s2, (const cpx<T>*)tw(), cd, bt.zs, 3, 2));
+                                 (size_t)L.b_field_s2, (const cpx<T>*)tw(), cd, bt.zs, 3, 2, (int)d.s2_row()));
             return launch(c, KD_YFWD, nb() * (2.0 * d.s1() + d.s2()) * d.cpx_bytes, dim3(grid.x, 1, nz()),
                           dim3(2 * RW::THREADS), 0, k_yfwd<T, N, V, true>, (const cpx<T>*)A(), (size_t)L.a_field_s1, B(), (size_t)L.b_field_s2,
-                          (const cpx<T>*)tw(), cd, bt.zs, 0, 0);
+                          (const cpx<T>*)tw(), cd, bt.zs, 0, 0, (int)d.s2_row());
         });
     }
 
@@ -221,6 +221,7 @@ struct Pipe {
     int xfused(int mode, XArgs<T> a) {
         a.s2 = B();
         a.s2_field = (size_t)L.b_field_s2;
+        a.s2_row = (int)d.s2_row();
         a.s3 = A();
         a.s3_field = (size_t)L.a_field_s3;
         const int kind = mode == XM_ORDER    ? KD_XFUSED_ORDER

@@ -227,6 +227,11 @@ struct Dims {
     int64_t ncell() const { return N * N * N; }
     int64_t s1() const { return Kz * N * N; }  // complex elements per field
     int64_t s2() const { return Kz * Ky * N; }
+    // S2 rows (kz, x) start every s2_row() complex elements: Ky rounded up to a multiple of
+    // 16, so every row starts on a 128-byte boundary (256 in FP64) and the x pass's short
+    // runs of consecutive ky' cross no more cache lines than they must
+    int64_t s2_row() const { return (Ky + 15) / 16 * 16; }
+    int64_t s2_alloc() const { return Kz * s2_row() * N; }
     int64_t s3() const { return Kz * N * Ky; }
     int64_t s4() const { return N * N * Kz; }
     int64_t cube() const { return Kz * Ky * Ky; }
@@ -261,13 +266,13 @@ inline Layout layout_of(const Dims& d, int nmax) {
     L.a = align_up(L.amp + (d.Kc + 1) * (d.Kc + 1) * 8);
     const int64_t asz = std::max(4 * d.s1(), 5 * d.s3()) * d.cpx_bytes;
     L.b = align_up(L.a + asz);
-    const int64_t bsz = std::max(4 * d.s2(), 5 * d.s4()) * d.cpx_bytes;
+    const int64_t bsz = std::max(4 * d.s2_alloc(), 5 * d.s4()) * d.cpx_bytes;
     L.u = align_up(L.b + bsz);
     const int nu = std::max(nmax - 2, 0) * 3;
     L.end = align_up(L.u + (int64_t)nu * d.ncell() * d.real_bytes);
     L.a_field_s1 = d.s1();
     L.a_field_s3 = d.s3();
-    L.b_field_s2 = d.s2();
+    L.b_field_s2 = d.s2_alloc();
     L.b_field_s4 = d.s4();
     return L;
 }
