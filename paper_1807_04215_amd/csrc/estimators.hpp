@@ -630,20 +630,25 @@ struct SumArgs {
     double* out;
 };
 
-template <typename T>
+template <typename T, int NMAX>
 __global__ void k_sum_orders(SumArgs<T> s) {
-    // four consecutive cells per thread and iteration (ncell is a multiple of 4)
+    // four consecutive cells per thread and iteration (ncell is a multiple of 4); the
+    // loads of every order go out before the sums, which add the orders in turn
+    static_assert(NMAX >= 1 && NMAX <= 8, "orders per sum");
     using V4 = HIP_vector_type<T, 4>;
     const size_t n4 = s.ncell / 4;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+        V4 v[NMAX];
+#pragma unroll
+        for (int n = 0; n < NMAX; ++n) v[n] = reinterpret_cast<const V4*>(s.d[n])[i];
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int n = 0; n < s.nmax; ++n) {
-            const V4 v = reinterpret_cast<const V4*>(s.d[n])[i];
-            acc[0] += s.coef[n] * (double)v.x;
-            acc[1] += s.coef[n] * (double)v.y;
-            acc[2] += s.coef[n] * (double)v.z;
-            acc[3] += s.coef[n] * (double)v.w;
+#pragma unroll
+        for (int n = 0; n < NMAX; ++n) {
+            acc[0] += s.coef[n] * (double)v[n].x;
+            acc[1] += s.coef[n] * (double)v[n].y;
+            acc[2] += s.coef[n] * (double)v[n].z;
+            acc[3] += s.coef[n] * (double)v[n].w;
         }
         double2* o = reinterpret_cast<double2*>(s.out + 4 * i);
         o[0] = make_double2(acc[0], acc[1]);

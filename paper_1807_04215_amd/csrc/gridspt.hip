@@ -1044,7 +1044,17 @@ int gridspt_sum_orders(gridspt_ctx* c, const gridspt_grid* g, int32_t nmax, cons
         s.ncell = (size_t)d.ncell();
         s.out = out;
         const double bytes = (double)d.ncell() * (nmax * d.real_bytes + 8.0);
-        return launch(c, KD_SUM_ORDERS, bytes, dim3(4096), dim3(256), 0, k_sum_orders<T>, s);
+        auto run = [&](auto kern) { return launch(c, KD_SUM_ORDERS, bytes, dim3(4096), dim3(256), 0, kern, s); };
+        switch (nmax) {
+            case 1: return run(k_sum_orders<T, 1>);
+            case 2: return run(k_sum_orders<T, 2>);
+            case 3: return run(k_sum_orders<T, 3>);
+            case 4: return run(k_sum_orders<T, 4>);
+            case 5: return run(k_sum_orders<T, 5>);
+            case 6: return run(k_sum_orders<T, 6>);
+            case 7: return run(k_sum_orders<T, 7>);
+            default: return run(k_sum_orders<T, 8>);
+        }
     };
     if (g->dtype == GRIDSPT_F64) return go(tag_t<double>{});
     return go(tag_t<float>{});
