@@ -109,13 +109,6 @@ __device__ __forceinline__ int pos_to_compact(int p, int Kc, int n) {
     return -1;
 }
 
-// --------------------------------------------------------------------------
-// Philox4x64-10 (Salmon et al., SC'11) and Box-Muller: unit Gaussians of the
-// four cells 4q .. 4q+3.  counter = (q, stream, 0, 0), key = (seed, 0); word
-// pairs (w0, w1), (w2, w3) give 53-bit uniforms in (0, 1); cell 4q + r takes
-// pair r / 2 and the cosine (r even) or sine (r odd) branch.  The transform
-// runs in the precision T of the field (an FP32 field needs no FP64 logarithm).
-// --------------------------------------------------------------------------
 // Full 128-bit product a m, high and low halves, from the four 32 x 32 -> 64-bit
 // partial products (a = a1 2^32 + a0, m likewise); the low half is assembled from
 // the same partials rather than multiplied out again.
@@ -137,6 +130,13 @@ __device__ __forceinline__ uint64_t xor3_64(uint64_t a, uint64_t b, uint64_t c) 
     return ((uint64_t)hi << 32) | lo;
 }
 
+// --------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11) and Box-Muller: unit Gaussians of the
+// four cells 4q .. 4q+3.  counter = (q, stream, 0, 0), key = (seed, 0); word
+// pairs (w0, w1), (w2, w3) give 53-bit uniforms in (0, 1); cell 4q + r takes
+// pair r / 2 and the cosine (r even) or sine (r odd) branch.  The transform
+// runs in the precision T of the field (an FP32 field needs no FP64 logarithm).
+// --------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void group_gaussians(uint64_t seed, uint64_t stream, uint64_t q, T (&g)[4]) {
     uint64_t c0 = q, c1 = stream, c2 = 0, c3 = 0;
