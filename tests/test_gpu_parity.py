@@ -313,6 +313,27 @@ def test_sum_orders(ctx, dtype):
     assert rel_l2(whole.cpu().numpy(), oracle.sum_orders(rd, coef)) < TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", [g.F64, g.F32])
+@pytest.mark.parametrize("nf", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_sum_orders_every_count(ctx, dtype, nf):
+    """The FP64 sum for every number of fields the call accepts (1 .. 8, each its
+    own kernel instantiation): white-noise fields rounded to the grid's precision
+    against the oracle's sum of the same values, cell by cell within twice the
+    recursive-summation bound (nf + 1) u sum_i |c_i v_i| of one FP64 evaluation.
+    N = 48: the cell count is a multiple of 4 but not of the launch's threads."""
+    n, box = 48, 150.0
+    grid = g.Grid(n, box, g.cube_kc(g.cut_n2max(n, box)), dtype)
+    host = [_rounded(inputs.white(n, 900 + 10 * nf + i), grid) for i in range(nf)]
+    coef = [(-0.7) ** i + 0.1 * i for i in range(nf)]
+    got = g.sum_orders(ctx, grid, [_to_dev(h, grid) for h in host], coef)
+    ctx.sync()
+    got = got.cpu().numpy()
+    want = oracle.sum_orders(np.stack(host), coef)
+    scale = sum(abs(c) * np.abs(h) for c, h in zip(coef, host))
+    u = np.finfo(np.float64).eps / 2
+    assert np.all(np.abs(got - want) <= 2 * (nf + 1) * u * scale)
+
+
 def test_zeldovich_planar_on_gpu(ctx):
     """The planar pin of the oracle, directly on the GPU path (FP64)."""
     n, box, nmax = 64, 200.0, 5
