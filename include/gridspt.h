@@ -267,7 +267,9 @@ int gridspt_tuning(const gridspt_ctx* ctx, const gridspt_grid* g, int32_t max, c
 int gridspt_sum_orders(gridspt_ctx* ctx, const gridspt_grid* g, int32_t nmax, const void* const* delta,
                        const double* coef, double* out);
 
-/* Device scratch needed by gridspt_power. */
+/* Device scratch needed by gridspt_power: per-block partial sums and their
+ * reduction for the most products one launch accumulates, which nbins sets
+ * (npairs is checked but does not change the size). */
 int64_t gridspt_power_workspace_bytes(const gridspt_grid* g, int32_t npairs, int32_t nbins);
 
 /* Shell-averaged cross spectra, the estimators of Eq. 19-21 with the volume

@@ -43,8 +43,14 @@ int power_launch_blocks(const Dims& d, Kern kern, size_t shm, unsigned nz) {
     const int64_t resident = (int64_t)std::max(cus, 1) * std::max(per_cu, 1) / std::max(nz, 1u);
     return (int)std::max<int64_t>(1, std::min<int64_t>(most, resident));
 }
-int64_t power_ws(const Dims& d, int npairs, int nbins) {
-    const int q = std::min(npairs, power_chunk(nbins)) + 2;
+// Columns of a launch's partial sums: at most power_chunk products per mode (the
+// requested pairs of the chunk, or, from up to five fields, every pair i <= j of
+// them, which that mode takes only when they fit the chunk), then the mode count
+// and the sum of |k|.  Sized for the chunk whatever npairs is: a single pair of
+// two fields still accumulates all three of their pairs.
+int power_cols(int nbins) { return power_chunk(nbins) + 2; }
+int64_t power_ws(const Dims& d, int nbins) {
+    const int q = power_cols(nbins);
     // block partials and the reduced sums
     return align_up((int64_t)power_blocks(d) * nbins * q * 8) + align_up((int64_t)nbins * q * 8);
 }
@@ -102,7 +108,7 @@ int power_enqueue(gridspt_ctx* c, const gridspt_grid* g, const void* const* fiel
     auto go = [&](auto tag) -> int {
         using T = typename decltype(tag)::type;
         double* partial = static_cast<double*>(work);
-        const int64_t part_bytes = align_up((int64_t)nblk * nbins * (std::min(npairs, chunk) + 2) * 8);
+        const int64_t part_bytes = align_up((int64_t)nblk * nbins * power_cols(nbins) * 8);
         double* sums = reinterpret_cast<double*>(static_cast<char*>(work) + part_bytes);
         BinEdges be{};
         for (int b = 0; b <= nbins; ++b) be.e[b] = edge_n2[b];
@@ -176,8 +182,8 @@ int power_enqueue(gridspt_ctx* c, const gridspt_grid* g, const void* const* fiel
 // ---------------------------------------------------------------------------
 // Scratch of gridspt_power_static, for callers that cannot allocate: one array
 // per GPU, held for the life of the process.  Its largest use: 1024 blocks x
-// 1792 partial sums (nbins (pairs per launch + 2) <= 1792 for every nbins <=
-// 256) of 8 bytes, and the reduced sums: about 14.7 MB.  In host code
+// 1792 partial sums (nbins power_cols(nbins) <= 1792 for every nbins <= 256)
+// of 8 bytes, and the reduced sums: about 14.7 MB.  In host code
 // `scratch` only names the symbol; the device address comes from
 // hipGetSymbolAddress, once per device.
 // ---------------------------------------------------------------------------
@@ -1064,7 +1070,7 @@ int64_t gridspt_power_workspace_bytes(const gridspt_grid* g, int32_t npairs, int
     const int rc = check_grid(g);
     if (rc != GRIDSPT_OK) return rc;
     if (npairs < 1 || npairs > kMaxPairs || nbins < 1 || nbins > kMaxBins) return GRIDSPT_EINVAL;
-    return power_ws(dims_of(g), npairs, nbins);
+    return power_ws(dims_of(g), nbins);
 }
 
 int gridspt_power(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields, const void* const* fields_k,
@@ -1093,7 +1099,7 @@ int gridspt_power_static(gridspt_ctx* c, const gridspt_grid* g, int32_t nfields,
     CHECK(check_ptr(pk));
     if (kmean) CHECK(check_ptr(kmean));
     if (nmodes) CHECK(check_ptr(nmodes));
-    if (power_ws(dims_of(g), npairs, nbins) > kStaticScratchBytes) return GRIDSPT_EWORKSPACE;
+    if (power_ws(dims_of(g), nbins) > kStaticScratchBytes) return GRIDSPT_EWORKSPACE;
     void* ws = nullptr;
     CHECK(static_scratch(&ws));
     // every word of the scratch the kernels read is written earlier in the same call
@@ -1302,7 +1308,7 @@ int64_t plan_group(GroupPlan& p) {
     p.o_delta = take((int64_t)nmax * d.ncell() * d.real_bytes);
     p.o_theta = take((int64_t)std::max(nmax - 1, 0) * d.ncell() * d.real_bytes);
     p.o_cube = take((int64_t)nmax * d.cube() * d.cpx_bytes);
-    p.o_pws = take(power_ws(d, p.g.npairs, p.g.nbins));
+    p.o_pws = take(power_ws(d, p.g.nbins));
     p.o_pk = take((int64_t)p.g.npairs * p.g.nbins * 8);
     p.o_kmean = take((int64_t)p.g.nbins * 8);
     p.o_nmodes = take((int64_t)p.g.nbins * 8);

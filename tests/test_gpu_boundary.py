@@ -2,6 +2,8 @@
 (GRIDSPT_ENONFINITE, nothing written), the half-layout export against the
 oracle's spectrum, per-order kernel timing, and the binding's tensor checks
 on GPU tensors (they raise before any call reaches the library)."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -147,3 +149,38 @@ def test_binding_rejects_wrong_gpu_tensors(ctx):
         g.orders_from_noise(w, ctx, grid, lp, 2, cut)
     with pytest.raises(ValueError, match="shape"):
         g.sum_orders(ctx, grid, [d1, d1], [1.0, 1.0], out=torch.empty((n, n), dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("dtype", [g.F64, g.F32])
+def test_power_stays_inside_its_workspace(ctx, dtype):
+    """gridspt_power on exactly the workspace gridspt_power_workspace_bytes asks
+    for, inside an allocation that continues with guard bytes: one requested pair
+    (P_10) of two fields, whose launch accumulates all three of their pairs, must
+    leave every guard byte as it was and give the (0, 1) row, the mode counts and
+    the mean |k| of the all-pairs call bit for bit."""
+    n, box, nbins = 64, 400.0, 24
+    cut = g.cut_n2max(n, box)
+    grid = g.Grid(n, box, g.cube_kc(cut), dtype)
+    edges = np.ascontiguousarray(g.linear_edges(nbins, n, 3, cut), dtype=np.int64)
+    gen = torch.Generator(device="cuda").manual_seed(401)
+    cubes = [torch.randn(grid.cube_shape, generator=gen, device="cuda", dtype=grid.real_dtype) for _ in range(2)]
+    gs = grid.cstruct
+    need = g.lib().gridspt_power_workspace_bytes(ctypes.byref(gs), 1, nbins)
+    assert need > 0
+    guard = 1 << 20
+    buf = torch.full((need + guard,), 0xA5, dtype=torch.uint8, device="cuda")
+    pk = torch.empty((1, nbins), dtype=torch.float64, device="cuda")
+    km = torch.empty(nbins, dtype=torch.float64, device="cuda")
+    nm = torch.empty(nbins, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    pairs = np.ascontiguousarray([1, 0], dtype=np.int32)
+    rc = g.lib().gridspt_power(ctx.handle, ctypes.byref(gs), 2, g._cube_array(ctx, grid, cubes, "fields_k"), 1,
+                               pairs.ctypes.data, nbins, edges.ctypes.data, g._f64(ctx, pk, "pk", (1, nbins)),
+                               g._f64(ctx, km, "kmean", (nbins,)), g._f64(ctx, nm, "nmodes", (nbins,)),
+                               ctypes.c_void_p(buf.data_ptr()), need)
+    assert rc == 0
+    ctx.sync()
+    assert bool(torch.all(buf[need:] == 0xA5))
+    wpk, wkm, wnm = g.power(ctx, grid, cubes, [(0, 0), (0, 1), (1, 1)], edges)
+    ctx.sync()
+    assert torch.equal(pk[0], wpk[1]) and torch.equal(nm, wnm) and torch.equal(km, wkm)

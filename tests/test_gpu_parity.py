@@ -248,6 +248,35 @@ def test_power_narrow_and_empty_bins(ctx, dtype, nf, npairs):
 
 
 @pytest.mark.parametrize("dtype", [g.F64, g.F32])
+@pytest.mark.parametrize("nf", [1, 2, 3, 4, 5])
+def test_power_every_field_count(ctx, dtype, nf):
+    """One to five fields, each count its own kernel (every pair i <= j formed from
+    one load of each field per mode), with the requested pairs a subset of those
+    in reversed order and orientation (P_ba for P_ab): random spectra against the
+    oracle's direct sum, N_k exactly and P within 1e-12 of sqrt(P_aa P_bb) per bin."""
+    n, box = 64, 400.0
+    cut = g.cut_n2max(n, box)
+    kc = g.cube_kc(cut)
+    grid = g.Grid(n, box, kc, dtype)
+    edges = g.linear_edges(24, n, 3, cut)
+    cubes = _random_cubes(grid, nf, 300 + nf)
+    every = [(a, b) for a in range(nf) for b in range(a, nf)]
+    pairs = [(b, a) for (a, b) in every[::-1]][: max(1, len(every) - 1)]
+    pk, km, nm = g.power(ctx, grid, cubes, pairs, edges)
+    ctx.sync()
+    halves = [_cube_to_half(cube_from_tensor(c), n, kc) for c in cubes]
+    rpk, rkm, rnm = oracle.power(halves, box, pairs, edges)
+    assert np.array_equal(nm.cpu().numpy(), rnm)
+    assert np.allclose(km.cpu().numpy(), rkm, rtol=1e-13, atol=0)
+    got = pk.cpu().numpy()
+    auto = {f: oracle.power([halves[f]], box, [(0, 0)], edges)[0][0] for f in range(nf)}
+    ok = rnm > 0
+    for p, (a, b) in enumerate(pairs):
+        err = np.abs(got[p] - rpk[p])[ok] / np.sqrt(auto[a] * auto[b])[ok]
+        assert err.max() < 1e-12, (pairs[p], err.max())
+
+
+@pytest.mark.parametrize("dtype", [g.F64, g.F32])
 def test_power_bins_past_the_cube_corners(ctx, dtype):
     """A last edge past the cube's corners (3 (Kc + 1)^2): every stored mode but
     k = 0 is binned, so sum_b N_b = (2 Kc + 1)^3 - 1 and sum_b N_b P_aa / L^3
