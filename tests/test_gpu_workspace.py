@@ -1,6 +1,10 @@
 """Every call that takes a caller workspace, run on exactly the size its query
-returns, inside an allocation that continues with guard bytes: no call may
-write past its workspace (the guard bytes must come back as they were)."""
+returns, inside an allocation that continues with guard bytes.  The whole
+allocation starts as 0xFF bytes, a NaN in FP32 and FP64: no call may write past
+its workspace (the guard bytes must come back as they were), and no call may
+read a workspace word it has not written first (its outputs must equal, bit for
+bit, those of the same call on a plain context, whose workspace holds whatever
+earlier calls left in it)."""
 import numpy as np
 import pytest
 import torch
@@ -12,14 +16,14 @@ from tests import inputs
 pytestmark = pytest.mark.gpu
 
 GUARD = 1 << 20
-PATTERN = 0xA5
+PATTERN = 0xFF
 NS, GAMMA = 0.96, 0.21
 
 
 class GuardedContext(g.Context):
     """A context whose byte buffers (the workspace of each call, the batch's work
     buffer) are fresh views of exactly the requested size, each followed by
-    GUARD bytes of PATTERN in the same allocation."""
+    GUARD bytes in the same allocation, all of it filled with PATTERN."""
 
     def __init__(self):
         super().__init__()
@@ -52,6 +56,11 @@ def gctx():
     return GuardedContext()
 
 
+@pytest.fixture(scope="module")
+def pctx():
+    return g.Context()
+
+
 def _grid(n, box, dtype):
     cut = g.cut_n2max(n, box)
     return g.Grid(n, box, g.cube_kc(cut), dtype), cut
@@ -66,61 +75,78 @@ def _dev(a, grid):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=grid.real_dtype)
 
 
+def _flat(x):
+    if isinstance(x, torch.Tensor):
+        return [x]
+    if isinstance(x, g.Orders):
+        return _flat([x.delta, x.theta, x.delta_k, x.theta_k])
+    if isinstance(x, dict):
+        return _flat([x[k] for k in sorted(x)])
+    if isinstance(x, (list, tuple)):
+        return [t for y in x for t in _flat(y)]
+    return []  # None
+
+
+def _same(gctx, pctx, a, b):
+    """The guards hold, and the guarded call's outputs a equal the plain call's b."""
+    assert gctx.guards_intact() == []
+    pctx.sync()
+    ta, tb = _flat(a), _flat(b)
+    assert len(ta) == len(tb) and len(ta) > 0
+    for i, (x, y) in enumerate(zip(ta, tb)):
+        assert torch.equal(x, y), i
+
+
 @pytest.mark.parametrize("dtype", [g.F64, g.F32])
-def test_transform_pipeline_calls(gctx, dtype):
+def test_transform_pipeline_calls(gctx, pctx, dtype):
     """Linear field, noise field, forward transform, orders (two nmax), seeded
-    orders, P-form, autotuning and the reverse mode: each on an exact workspace."""
+    orders, P-form, the reverse mode and autotuning: each on an exact workspace."""
     grid, cut = _grid(32, 200.0, dtype)
+    for c in (gctx, pctx):
+        g.set_tuning(c, grid, 0)
     lp = _lin(cut, 5)
-    g.linear_field(gctx, grid, lp, spectrum=True)
-    assert gctx.guards_intact() == []
+    _same(gctx, pctx, *[g.linear_field(c, grid, lp, spectrum=True) for c in (gctx, pctx)])
     noise = _dev(inputs.white(32, 41), grid)
-    d1 = g.noise_field(gctx, grid, lp, noise)
-    assert gctx.guards_intact() == []
-    g.forward(gctx, grid, cut, d1)
-    assert gctx.guards_intact() == []
+    d1 = [g.noise_field(c, grid, lp, noise) for c in (gctx, pctx)]
+    _same(gctx, pctx, *d1)
+    d1 = d1[1]
+    _same(gctx, pctx, *[g.forward(c, grid, cut, d1) for c in (gctx, pctx)])
     for nmax in (2, 5):
-        g.orders(gctx, grid, nmax, cut, cut, d1)
-        assert gctx.guards_intact() == [], nmax
-    g.orders_linear(gctx, grid, lp, 5, cut)
-    assert gctx.guards_intact() == []
-    g.orders_pform(gctx, grid, 3, cut, cut, d1)
-    assert gctx.guards_intact() == []
-    g.tune_orders(gctx, grid, lp, 3, cut)
+        _same(gctx, pctx, *[g.orders(c, grid, nmax, cut, cut, d1) for c in (gctx, pctx)])
+    _same(gctx, pctx, *[g.orders_linear(c, grid, lp, 5, cut) for c in (gctx, pctx)])
+    _same(gctx, pctx, *[g.orders_pform(c, grid, 3, cut, cut, d1) for c in (gctx, pctx)])
+    out = g.orders(pctx, grid, 3, cut, cut, d1)
+    pctx.sync()
+    gd = [_dev(inputs.white(32, 50 + i), grid) for i in range(3)]
+    _same(gctx, pctx, *[g.adjoint(c, grid, lp, 3, cut, out.delta_k, out.theta_k, gd) for c in (gctx, pctx)])
+    g.tune_orders(gctx, grid, lp, 3, cut)  # timings decide the variants: guards only
     assert gctx.guards_intact() == []
     g.set_tuning(gctx, grid, 0)
-    out = g.orders(gctx, grid, 3, cut, cut, d1)
-    assert gctx.guards_intact() == []
-    gd = [_dev(inputs.white(32, 50 + i), grid) for i in range(3)]
-    g.adjoint(gctx, grid, lp, 3, cut, out.delta_k, out.theta_k, gd)
-    assert gctx.guards_intact() == []
 
 
 @pytest.mark.parametrize("dtype", [g.F64, g.F32])
-def test_estimator_calls(gctx, dtype):
+def test_estimator_calls(gctx, pctx, dtype):
     """Smoothing, one-point and joint statistics, cross spectra (one chunk, a
     subset of the pairs of two fields, and several chunks) and bispectra."""
     grid, cut = _grid(48, 300.0, dtype)
-    out = g.orders_linear(gctx, grid, _lin(cut, 7), 3, cut)
-    assert gctx.guards_intact() == []
-    g.smooth(gctx, grid, out.delta_k, [1.0, 0.8, 0.6], 10.0)
-    assert gctx.guards_intact() == []
-    g.field_stats(gctx, grid, out.delta, 40, -1.0, 1.0, 16)
-    assert gctx.guards_intact() == []
+    for c in (gctx, pctx):
+        g.set_tuning(c, grid, 0)
+    out = g.orders_linear(pctx, grid, _lin(cut, 7), 3, cut)
+    pctx.sync()
+    _same(gctx, pctx, *[g.smooth(c, grid, out.delta_k, [1.0, 0.8, 0.6], 10.0) for c in (gctx, pctx)])
+    _same(gctx, pctx, *[g.field_stats(c, grid, out.delta, 40, -1.0, 1.0, 16) for c in (gctx, pctx)])
     edges = g.linear_edges(20, 48, 3, cut)
     for pairs in ([(0, 0), (0, 1), (1, 1)], [(1, 0)], [(a, b) for a in range(3) for b in range(3)] * 3):
-        g.power(gctx, grid, out.delta_k, pairs, edges)
-        assert gctx.guards_intact() == [], pairs
+        _same(gctx, pctx, *[g.power(c, grid, out.delta_k, pairs, edges) for c in (gctx, pctx)])
     bedges = g.linear_edges(8, 32, 3, cut)
     tris = [(b, b, b) for b in range(2, 8)] + [(b, b, 1) for b in range(2, 8)]
     terms = [c + (t,) for t in range(len(tris)) for c in ((0, 0, 1), (0, 1, 0), (1, 0, 0), (0, 1, 2))]
-    g.bispectrum(gctx, grid, out.delta_k, tris, terms, bedges)
-    assert gctx.guards_intact() == []
+    _same(gctx, pctx, *[g.bispectrum(c, grid, out.delta_k, tris, terms, bedges) for c in (gctx, pctx)])
 
 
-def test_batch(gctx):
+def test_batch(gctx, pctx):
     """A two-group batch (spectra and bispectra) on an exact work buffer,
-    captured and replayed."""
+    captured and replayed twice."""
     groups = []
     for n, box, nreal, seed in ((32, 200.0, 3, 11), (48, 300.0, 2, 12)):
         grid, cut = _grid(n, box, g.F32)
@@ -129,7 +155,8 @@ def test_batch(gctx):
         terms = [c + (t,) for t in range(len(tris)) for c in ((0, 0, 1), (0, 1, 0), (1, 0, 0))]
         groups.append(g.BatchGroup(grid, nreal, 3, cut, lp, [(0, 0), (0, 1), (1, 2)], g.linear_edges(10, n, 3, cut),
                                    tris, terms))
-    b = g.Batch(gctx, groups)
+    bg, bp = g.Batch(gctx, groups), g.Batch(pctx, groups)
     for _ in range(2):
-        b.run()
-    assert gctx.guards_intact() == []
+        bg.run()
+        bp.run()
+    _same(gctx, pctx, bg.out, bp.out)
