@@ -160,3 +160,20 @@ def test_batch(gctx, pctx):
         bg.run()
         bp.run()
     _same(gctx, pctx, bg.out, bp.out)
+
+
+def test_batch_bispectrum_in_chunks(gctx, pctx):
+    """A batch group whose bispectrum needs more shell slots than one chunk holds
+    (three fields over 20 bins: 60 field slots against 32 per chunk, 20 indicator
+    slots against 16), on an exact work buffer: guards and bitwise outputs."""
+    n, box = 64, 400.0
+    cut = g.cut_n2max(n, box)
+    grid = g.Grid(n, box, g.cube_kc(cut), g.F32)
+    edges = g.linear_edges(20, n, 4, cut)  # shells up to N/4: every triangle closes without wrapping
+    tris = [(b, b, b) for b in range(20)] + [(b, b, 0) for b in range(1, 20)]
+    terms = [c + (t,) for t in range(len(tris)) for c in ((0, 0, 1), (0, 1, 2), (1, 1, 1))]
+    groups = [g.BatchGroup(grid, 2, 3, cut, _lin(cut, 13), [(0, 0), (1, 2)], edges, tris, terms)]
+    bg, bp = g.Batch(gctx, groups), g.Batch(pctx, groups)
+    bg.run()
+    bp.run()
+    _same(gctx, pctx, bg.out, bp.out)
