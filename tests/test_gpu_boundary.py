@@ -184,3 +184,29 @@ def test_power_stays_inside_its_workspace(ctx, dtype):
     wpk, wkm, wnm = g.power(ctx, grid, cubes, [(0, 0), (0, 1), (1, 1)], edges)
     ctx.sync()
     assert torch.equal(pk[0], wpk[1]) and torch.equal(nm, wnm) and torch.equal(km, wkm)
+
+
+@pytest.mark.parametrize("dtype", [g.F64, g.F32])
+def test_orders_with_some_spectra(ctx, dtype):
+    """Spectra requested for some orders only (null entries elsewhere, theta_1
+    null too): every real field and every requested spectrum equals, bit for bit,
+    the run that stores all of them."""
+    n, box, nmax = 48, 300.0, 5
+    cut = g.cut_n2max(n, box)
+    grid = g.Grid(n, box, g.cube_kc(cut), dtype)
+    d1 = torch.from_numpy(inputs.white(n, 90)).to(device="cuda", dtype=grid.real_dtype)
+    full = g.orders(ctx, grid, nmax, cut, cut, d1)
+    part = g.alloc_orders(grid, nmax, True, ctx)
+    part.theta[0] = None
+    part.delta_k = [part.delta_k[0], None, part.delta_k[2], None, part.delta_k[4]]
+    part.theta_k = [None, None, part.theta_k[2], part.theta_k[3], None]
+    g.orders(ctx, grid, nmax, cut, cut, d1, out=part)
+    ctx.sync()
+    for i in range(nmax):
+        assert torch.equal(part.delta[i], full.delta[i]), i
+        if part.theta[i] is not None:
+            assert torch.equal(part.theta[i], full.theta[i]), i
+        if part.delta_k[i] is not None:
+            assert torch.equal(part.delta_k[i], full.delta_k[i]), i
+        if part.theta_k[i] is not None:
+            assert torch.equal(part.theta_k[i], full.theta_k[i]), i
