@@ -210,3 +210,36 @@ def test_orders_with_some_spectra(ctx, dtype):
             assert torch.equal(part.delta_k[i], full.delta_k[i]), i
         if part.theta_k[i] is not None:
             assert torch.equal(part.theta_k[i], full.theta_k[i]), i
+
+
+def test_context_on_a_side_stream(ctx):
+    """A context bound to a stream other than the current one (default priority):
+    orders and cross spectra equal, bit for bit, those of the current-stream
+    context.  The input is freed on the current stream right after the call and
+    tensors of its size are filled with NaN at once: the binding marks inputs as
+    used on the context's stream, so their memory is not reused before the
+    context's work has read it."""
+    n, box, nmax = 48, 300.0, 4
+    cut = g.cut_n2max(n, box)
+    grid = g.Grid(n, box, g.cube_kc(cut), g.F32)
+    host = inputs.white(n, 123)
+    ref = g.orders(ctx, grid, nmax, cut, cut, torch.from_numpy(host).to(device="cuda", dtype=grid.real_dtype))
+    edges = g.linear_edges(12, n, 3, cut)
+    pairs = [(a, b) for a in range(nmax) for b in range(a, nmax)]
+    rpk = g.power(ctx, grid, ref.delta_k, pairs, edges)
+    ctx.sync()
+    side = torch.cuda.Stream()
+    sctx = g.Context(stream=side)
+    d1 = torch.from_numpy(host).to(device="cuda", dtype=grid.real_dtype)
+    torch.cuda.current_stream().synchronize()  # the upload is done before the side stream reads it
+    out = g.orders(sctx, grid, nmax, cut, cut, d1)
+    del d1
+    junk = [torch.full(grid.real_shape, float("nan"), device="cuda", dtype=grid.real_dtype) for _ in range(4)]
+    pk = g.power(sctx, grid, out.delta_k, pairs, edges)
+    sctx.sync()
+    del junk
+    for i in range(nmax):
+        assert torch.equal(out.delta[i], ref.delta[i]) and torch.equal(out.theta[i], ref.theta[i]), i
+        assert torch.equal(out.delta_k[i], ref.delta_k[i]), i
+    for a, b in zip(pk, rpk):
+        assert torch.equal(a, b)
