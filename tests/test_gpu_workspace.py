@@ -177,3 +177,12 @@ def test_batch_bispectrum_in_chunks(gctx, pctx):
     bg.run()
     bp.run()
     _same(gctx, pctx, bg.out, bp.out)
+
+
+@pytest.mark.parametrize("dtype", [g.F64, g.F32])
+def test_field_stats_at_the_limits(gctx, pctx, dtype):
+    """One-point and joint statistics at the largest sizes the call accepts (8
+    fields, 1024 bins, 64 x 64 joint bins), on an exact workspace."""
+    grid, _ = _grid(32, 200.0, dtype)
+    fields = [_dev(0.4 * inputs.white(32, 200 + i), grid) for i in range(8)]
+    _same(gctx, pctx, *[g.field_stats(c, grid, fields, 1024, -1.5, 1.5, 64) for c in (gctx, pctx)])
