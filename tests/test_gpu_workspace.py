@@ -186,3 +186,17 @@ def test_field_stats_at_the_limits(gctx, pctx, dtype):
     grid, _ = _grid(32, 200.0, dtype)
     fields = [_dev(0.4 * inputs.white(32, 200 + i), grid) for i in range(8)]
     _same(gctx, pctx, *[g.field_stats(c, grid, fields, 1024, -1.5, 1.5, 64) for c in (gctx, pctx)])
+
+
+@pytest.mark.parametrize("dtype", [g.F64, g.F32])
+def test_power_at_the_limits(gctx, pctx, dtype):
+    """Cross spectra at the largest sizes the call accepts (16 fields, 64 pairs,
+    256 bins: 13 launches of 5 pairs), on an exact workspace."""
+    grid, cut = _grid(32, 200.0, dtype)
+    gen = torch.Generator(device="cuda").manual_seed(17)
+    cubes = [torch.randn(grid.cube_shape, generator=gen, device="cuda", dtype=grid.real_dtype) for _ in range(16)]
+    pairs = [(i % 16, (5 * i + 3) % 16) for i in range(64)]
+    r = np.sqrt(cut) * np.arange(1, 257) / 256.0
+    edges = np.maximum.accumulate(np.concatenate([[1], np.ceil(r * r).astype(np.int64)]))
+    edges[-1] = cut + 1
+    _same(gctx, pctx, *[g.power(c, grid, cubes, pairs, edges) for c in (gctx, pctx)])
