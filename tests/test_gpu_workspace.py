@@ -200,3 +200,18 @@ def test_power_at_the_limits(gctx, pctx, dtype):
     edges = np.maximum.accumulate(np.concatenate([[1], np.ceil(r * r).astype(np.int64)]))
     edges[-1] = cut + 1
     _same(gctx, pctx, *[g.power(c, grid, cubes, pairs, edges) for c in (gctx, pctx)])
+
+
+@pytest.mark.parametrize("dtype", [g.F64, g.F32])
+def test_bispectrum_many_triangles(gctx, pctx, dtype):
+    """Every closable shell triple b1 <= b2 <= b3 of 12 shells up to N/4 (the
+    shells of a triangle overlap when b3 <= b1 + b2 + 1), three terms each, on an
+    exact workspace."""
+    grid, cut = _grid(48, 300.0, dtype)
+    out = g.orders_linear(pctx, grid, _lin(cut, 19), 3, cut)
+    pctx.sync()
+    edges = g.linear_edges(12, 48, 4, cut)
+    tris = [(a, b, c) for a in range(12) for b in range(a, 12) for c in range(b, 12) if c <= a + b + 1]
+    terms = [f + (t,) for t in range(len(tris)) for f in ((0, 0, 1), (0, 1, 2), (1, 1, 1))]
+    assert len(tris) > 150
+    _same(gctx, pctx, *[g.bispectrum(c, grid, out.delta_k, tris, terms, edges) for c in (gctx, pctx)])
